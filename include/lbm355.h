@@ -1,0 +1,227 @@
+/*
+ * lbm355.h -- C ABI of the MI355X (gfx950) D3Q19 lattice Boltzmann node-update library.
+ *
+ * The library implements the fused collide-and-propagate update of the
+ * propagation schemes compared by Wittmann, Zeiser, Hager and Wellein,
+ * "Comparison of different Propagation Steps for the Lattice Boltzmann
+ * Method":
+ *   - two-step two-grid (Sec. 2, Table 1),
+ *   - one-step two-grid, push and pull (Sec. 3, Fig. 1, Table 2),
+ *   - AA pattern, separate even and odd kernels (Sec. 6, Fig. 5, Table 5),
+ *   - esoteric twist (Sec. 7, Fig. 6, Table 6),
+ * each on a directly addressed full grid and on an indirectly addressed
+ * sparse grid of fluid nodes with an 18-entry neighbour index array (Sec. 1),
+ * in SoA and AoS layouts (Sec. 1).  The collision is BGK with the Guo body
+ * force; PDFs are stored in FP64, FP32, or FP16 as shifted deviations
+ * (f_i - w_i) * sigma with FP32 arithmetic.
+ *
+ * Conventions shared by every call:
+ *   - All functions return an int status (LBM_OK or a negative LBM_E_*);
+ *     lbm_last_error() gives the text of the last failure on the calling
+ *     thread.  No C++ exception crosses this boundary.
+ *   - Pointers named d_* are device pointers (HIP device memory of the
+ *     current device).  All device memory is owned by the caller; the library
+ *     never allocates device memory.  Host pointers are plain host memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     device work of a call is enqueued on it, asynchronously, unless the call
+ *     says it synchronises.  Launch errors are reported by the launching call;
+ *     asynchronous faults surface at the caller's next synchronisation.
+ *   - Canonical PDF arrays are FP64 [19][n_nodes] (row i = direction i of the
+ *     ordering below, node n in lexicographic order with x fastest).  For a
+ *     direct grid the nodes are the fluid cells (all cells, or the cells with
+ *     1 <= z <= nz-2 when wall_z is set); for an indirect grid they are the
+ *     fluid ids assigned by lbm_build_idx.
+ *
+ * D3Q19 ordering (fixed convention of this library, each moving direction
+ * followed by its opposite):
+ *   i :  0  1  2  3  4  5  6  7  8  9 10 11 12 13 14 15 16 17 18
+ *   cx:  0  1 -1  0  0  0  0  1 -1  1 -1  1 -1  1 -1  0  0  0  0
+ *   cy:  0  0  0  1 -1  0  0  1 -1 -1  1  0  0  0  0  1 -1  1 -1
+ *   cz:  0  0  0  0  0  1 -1  0  0  0  0  1 -1 -1  1  1 -1 -1  1
+ *   w : 1/3 for i = 0, 1/18 for i = 1..6, 1/36 for i = 7..18.
+ */
+#ifndef LBM355_H
+#define LBM355_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+enum {
+    LBM_OK = 0,
+    LBM_E_ARG = -1,         /* invalid argument or buffer too small            */
+    LBM_E_STATE = -2,       /* wrong call order, unbound buffer, scheme mismatch */
+    LBM_E_HIP = -3,         /* HIP runtime error (text in lbm_last_error)      */
+    LBM_E_UNSUPPORTED = -4, /* combination not provided by this build          */
+    LBM_E_DIVERGED = -5     /* a reduction saw a NaN                           */
+};
+
+/* ---------------------------------------------------------------- enums */
+enum lbm_addressing { LBM_DIRECT = 0, LBM_INDIRECT = 1 };
+enum lbm_layout { LBM_SOA = 0, LBM_AOS = 1 };
+enum lbm_precision { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2 };
+enum lbm_scheme {
+    LBM_TS = 0,      /* two-step two-grid, Sec. 2                        */
+    LBM_OS_PUSH = 1, /* one-step two-grid, push, Sec. 3                   */
+    LBM_OS_PULL = 2, /* one-step two-grid, pull, Sec. 3                   */
+    LBM_AA = 3,      /* AA pattern, Sec. 6                                */
+    LBM_ET = 4,      /* esoteric twist, Sec. 7                            */
+    /* transfer model only (lbm_model_bytes); no kernels:                 */
+    LBM_OS_NT = 5,   /* one-step with non-temporal stores, Sec. 3          */
+    LBM_CG = 6,      /* compressed grid, Sec. 4                            */
+    LBM_SWAP = 7     /* swap algorithm, Sec. 5                             */
+};
+enum lbm_collider { LBM_IDENTITY = 0, LBM_BGK = 1 };
+
+/* ---------------------------------------------------------------- grid */
+typedef struct lbm_grid lbm_grid;
+
+typedef struct {
+    int32_t nx, ny, nz;  /* box in cells; x is the fastest index                */
+    int32_t addressing;  /* enum lbm_addressing                                  */
+    int32_t layout;      /* enum lbm_layout                                      */
+    int32_t precision;   /* enum lbm_precision                                   */
+    int32_t wall_z;      /* DIRECT only: 1 = cell planes z = 0 and z = nz-1 are
+                            solid walls (half-way bounce-back); 0 = periodic z.
+                            x and y are always periodic.  INDIRECT grids are
+                            periodic on all axes; solids come from the mask.   */
+    int32_t et_ghosts;   /* INDIRECT only: 1 = lbm_build_idx also numbers the
+                            solid cells the esoteric twist stores PDFs in.      */
+    double omega;        /* BGK relaxation rate, 0 < omega < 2                   */
+    double g[3];         /* body-force acceleration (force density rho * g)      */
+    double f16_scale;    /* sigma of the FP16 shifted form (> 0); else ignored    */
+} lbm_grid_desc;
+
+typedef struct {
+    int64_t n_cells;       /* nx * ny * nz                                         */
+    int64_t n_nodes;       /* nodes updated per step (fluid nodes); 0 before
+                              lbm_build_idx on an indirect grid                     */
+    int64_t n_ghost;       /* extra storage entries of the esoteric twist           */
+    int64_t pitch;         /* SoA: elements between direction arrays                */
+    int64_t idx_pitch;     /* entries between IDX rows                              */
+    int64_t pdf_bytes;     /* one lattice for the queried scheme                    */
+    int64_t pdf1_bytes;    /* second lattice (TS, OS push, OS pull) or 0           */
+    int64_t idx_bytes;     /* int32 IDX[18][idx_pitch] (indirect) or 0              */
+    int64_t aux_bytes;     /* int32 ET table [7][idx_pitch] (indirect ET) or 0      */
+    int64_t scratch_bytes; /* moment-reduction partials                             */
+    int64_t cellmap_bytes; /* int32 cellmap[n_cells] (indirect)                     */
+    int64_t build_scratch_bytes; /* scratch of lbm_build_idx                        */
+} lbm_sizes;
+
+/* Text of the last error on this thread ("" if none).  Never NULL. */
+const char *lbm_last_error(void);
+
+/* Library version as an integer (major * 10000 + minor * 100 + patch). */
+int lbm_version(void);
+
+/* The library's canonical lattice: c[19*3] (cx, cy, cz per direction),
+ * w[19], opp[19].  Host pointers; any may be NULL.  Touches no GPU. */
+int lbm_lattice(int32_t *c, double *w, int32_t *opp);
+
+/* Creates a grid from `desc` (host struct, copied).  Sec. 1: direct
+ * addressing uses index arithmetic on the full box; indirect addressing keeps
+ * only fluid nodes and an index array of their 18 neighbours.
+ * Errors: LBM_E_ARG for non-positive sizes, n_cells >= 2^31, omega outside
+ * (0, 2), an unknown enum, or f16_scale <= 0 with LBM_F16S. */
+int lbm_create_grid(const lbm_grid_desc *desc, lbm_grid **out);
+
+/* Releases the host-side descriptor.  Device buffers stay the caller's. */
+int lbm_destroy_grid(lbm_grid *g);
+
+/* Replaces omega and g (host values) for subsequent steps. */
+int lbm_set_params(lbm_grid *g, double omega, const double g_acc[3]);
+
+/* Buffer sizes of `scheme` on this grid (host struct out).  For an indirect
+ * grid, n_nodes, pdf/idx/aux sizes are known only after the first
+ * lbm_build_idx call; before it they are 0 and cellmap_bytes /
+ * build_scratch_bytes are already valid. */
+int lbm_query_sizes(const lbm_grid *g, int32_t scheme, lbm_sizes *out);
+
+/* Index array of indirect addressing (Sec. 1; fluid nodes and their q-1
+ * neighbours).  Two calls:
+ *   1. d_idx == NULL: reads d_mask (uint8[n_cells], 1 = solid, x fastest),
+ *      writes d_cellmap (int32[n_cells]): the fluid id of each fluid cell in
+ *      lexicographic order, -1 for a solid cell, or -2 - k for the solid cell
+ *      holding esoteric-twist storage entry k (et_ghosts only, ghosts numbered
+ *      in lexicographic order).  Stores N_f in *n_fluid_out (host) and keeps
+ *      N_f and the ghost count in the grid.  Synchronises `stream` once.
+ *   2. d_idx != NULL: reads d_cellmap, writes d_idx (int32[18][idx_pitch]):
+ *      IDX[k][n] = fluid id of the cell at x_n + c_{k+1} (periodic wrap) or -1
+ *      when that cell is solid.  With et_ghosts, d_et (int32[7][idx_pitch])
+ *      receives the six storage addresses the esoteric twist reads at
+ *      x + (1,0,0), (0,1,0), (0,0,1), (1,1,0), (1,0,1), (0,1,1) (fluid id, or
+ *      N_f + ghost number for a solid cell) and, in row 6, a bit mask whose
+ *      bit i-1 is set when x + c_i is solid.  Asynchronous.
+ * d_scratch: build_scratch_bytes of device memory.  Errors: LBM_E_STATE on a
+ * direct grid or when call 2 precedes call 1. */
+int lbm_build_idx(lbm_grid *g, const uint8_t *d_mask, int32_t *d_cellmap, int32_t *d_idx,
+                  int32_t *d_et, void *d_scratch, int64_t *n_fluid_out, void *stream);
+
+/* Binds the caller's device buffers for `scheme` (sizes from
+ * lbm_query_sizes) and resets the step counter t to 0.  pdf1 is required for
+ * TS and OS, ignored otherwise; idx is required for indirect grids; aux is
+ * the ET table (indirect ET only); scratch holds reduction partials.
+ * The PDF contents are undefined until lbm_set_pdfs or lbm_init_equilibrium.
+ * Errors: LBM_E_ARG for a missing buffer, LBM_E_STATE before the indirect
+ * index is built, LBM_E_UNSUPPORTED for ET on an indirect grid created
+ * without et_ghosts. */
+int lbm_bind(lbm_grid *g, int32_t scheme, void *d_pdf0, void *d_pdf1, const int32_t *d_idx,
+             const int32_t *d_aux, void *d_scratch);
+
+/* Uploads a canonical FP64 state d_canon[19][n_nodes] into the bound scheme's
+ * layout (the inverse of the scheme's next read, so that the next step sees
+ * exactly these f_i), rounding to the storage precision (FP16S stores
+ * (f_i - w_i) * sigma rounded to nearest).  Asynchronous. */
+int lbm_set_pdfs(lbm_grid *g, const double *d_canon, void *stream);
+
+/* Reads the canonical FP64 state f(t) into d_canon[19][n_nodes]: the values
+ * the next step of the bound scheme will read (for the one-step pull scheme
+ * this applies the pending propagation, for the AA pattern after an odd
+ * number of steps the odd-step gather, for the esoteric twist the parity's
+ * direction table).  Asynchronous. */
+int lbm_get_pdfs(const lbm_grid *g, double *d_canon, void *stream);
+
+/* f = f^eq(rho, u) per node from d_rho_u[4][n_nodes] (rho, ux, uy, uz), or the
+ * rest state rho = 1, u = 0 when d_rho_u is NULL; resets t to 0.
+ * Asynchronous. */
+int lbm_init_equilibrium(lbm_grid *g, const double *d_rho_u, void *stream);
+
+/* Advances the bound state by n_steps time steps of `scheme` (must be the
+ * bound scheme: LBM_E_STATE otherwise).  Per step: TS launches its collision
+ * and propagation kernels (Sec. 2); OS push/pull one fused kernel followed by
+ * the lattice swap (Sec. 3); AA the even kernel at even t and the odd kernel
+ * at odd t (Sec. 6); ET one kernel with the parity's direction table, the
+ * swap of opposing directions being the parity flip (Sec. 7).  LBM_IDENTITY
+ * replaces the collision by the identity (pure propagation).  Asynchronous. */
+int lbm_step(lbm_grid *g, int32_t scheme, int32_t collider, int64_t n_steps, void *stream);
+
+/* Number of completed time steps since bind/set/init. */
+int64_t lbm_time(const lbm_grid *g);
+
+/* FP64 moments of the canonical state: d_out4 = {M, Jx, Jy, Jz} with
+ * M = sum_n sum_i f_i and J = sum_n sum_i c_i f_i (raw; the mean velocity
+ * adds M g / 2).  Deterministic: per-node FP64 sums, a fixed-shape tree per
+ * block of 256 nodes, then one fixed-order final pass.  A NaN anywhere makes
+ * M NaN.  Uses the bound scratch.  Asynchronous. */
+int lbm_reduce_moments(lbm_grid *g, double *d_out4, void *stream);
+
+/* Plain device copy of `bytes` (multiple of 16, 16-byte aligned pointers):
+ * the STREAM-copy bandwidth calibration of Table 7.  Asynchronous. */
+int lbm_stream_copy(const void *d_src, void *d_dst, int64_t bytes, void *stream);
+
+/* Memory traffic per fluid-node update (bytes/LUP) of the transfer-count
+ * model of Tables 1-6 and 8.  model = 0: the paper's counts (write-allocate
+ * included, 8-byte PDFs, 4-byte IDX entries, precision ignored).  model = 1:
+ * GPU algorithmic bytes of this library (no write-allocate, PDF size of
+ * `precision`, this library's IDX use).  Returns < 0 for combinations the
+ * model does not cover. */
+double lbm_model_bytes(int32_t scheme, int32_t addressing, int32_t precision, int32_t model);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM355_H */

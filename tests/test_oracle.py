@@ -1,0 +1,330 @@
+"""Pins of the FP64 oracle against facts fixed outside it.
+
+Each test checks the oracle against mathematics or hand-worked values, never
+against a retyped copy of its own formulas:
+  * lattice tables  -- golden ordering file and the isotropy identities of D3Q19;
+  * equilibrium     -- its velocity moments up to second order;
+  * Guo forcing     -- its moments (zero mass, (1-w/2)F momentum, stress term);
+  * collision       -- exact mass conservation and momentum gain F per node;
+  * propagation     -- an exact permutation, built here with numpy rolls;
+  * whole runs      -- mass conservation, momentum growth M g per step,
+                       the rest state, Poiseuille flow (closed form, exact at
+                       the TRT 'magic' relaxation), shear-wave viscosity and the
+                       slit permeability;
+  * IDX             -- a hand-worked 4^3 example and the link symmetry;
+  * binary16 rounding -- numpy's float16 conversion.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import lbm_inputs
+import oracle
+from golden_io import d3q19_ordering, idx_4cube
+
+C, W, OPP = d3q19_ordering()
+Wf = np.array([float(w) for w in W])
+G = (1e-6, 0.0, 0.0)
+
+
+# ---------------------------------------------------------------- tables
+def test_tables_match_golden_ordering():
+    c, w, opp = oracle.tables()
+    np.testing.assert_array_equal(c, C)
+    np.testing.assert_array_equal(opp, OPP)
+    np.testing.assert_allclose(w, Wf, rtol=0, atol=1e-17)
+
+
+def test_lattice_isotropy():
+    """sum w = 1, sum w c_a c_b = d_ab/3, 4th moment = (d d + d d + d d)/9 (exact, in fractions)."""
+    c, _, opp = oracle.tables()
+    assert len({tuple(v) for v in c}) == 19
+    assert sum(W) == 1
+    for a in range(3):
+        for b in range(3):
+            assert sum(W[i] * int(C[i, a] * C[i, b]) for i in range(19)) == (Fraction(1, 3) if a == b else 0)
+            for g in range(3):
+                assert sum(W[i] * int(C[i, a] * C[i, b] * C[i, g]) for i in range(19)) == 0
+                for d in range(3):
+                    m4 = sum(W[i] * int(C[i, a] * C[i, b] * C[i, g] * C[i, d]) for i in range(19))
+                    want = ((a == b) * (g == d) + (a == g) * (b == d) + (a == d) * (b == g))
+                    assert m4 * 9 == want
+    for i in range(19):
+        np.testing.assert_array_equal(c[opp[i]], -c[i])
+
+
+# ---------------------------------------------------------------- equilibrium / forcing / collision
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_equilibrium_moments(seed):
+    rng = np.random.default_rng(seed)
+    rho = 1.0 + 0.1 * rng.standard_normal()
+    u = 0.05 * rng.standard_normal(3)
+    feq = oracle.equilibrium(rho, u)
+    assert abs(feq.sum() - rho) < 1e-15
+    np.testing.assert_allclose(C.T @ feq, rho * u, rtol=0, atol=1e-16)
+    P = np.einsum("ia,ib,i->ab", C, C, feq)
+    np.testing.assert_allclose(P, rho * np.outer(u, u) + rho / 3.0 * np.eye(3), rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("omega", [0.7, 1.0, 1.6])
+def test_guo_source_moments(omega):
+    rng = np.random.default_rng(7)
+    rho = 1.02
+    u = 0.03 * rng.standard_normal(3)
+    g = 1e-3 * rng.standard_normal(3)
+    F = rho * g
+    S = oracle.guo_source(rho, u, omega, g)
+    k = 1.0 - 0.5 * omega
+    assert abs(S.sum()) < 1e-18
+    np.testing.assert_allclose(C.T @ S, k * F, rtol=1e-13, atol=1e-19)
+    P = np.einsum("ia,ib,i->ab", C, C, S)
+    np.testing.assert_allclose(P, k * (np.outer(u, F) + np.outer(F, u)), rtol=1e-12, atol=1e-19)
+
+
+@pytest.mark.parametrize("omega", [0.6, 1.0, 1.9])
+def test_collision_conserves_mass_and_adds_force(omega):
+    rng = np.random.default_rng(3)
+    f = Wf * (1.0 + 0.01 * rng.standard_normal(19))
+    g = np.array([1e-4, -2e-4, 3e-5])
+    fs = oracle.collide_node(f, omega, g)
+    rho = f.sum()
+    assert abs(fs.sum() - rho) <= 4 * np.finfo(float).eps * rho
+    # with u = (j + rho g/2)/rho the post-collision momentum is j + rho g exactly
+    np.testing.assert_allclose(C.T @ fs, C.T @ f + rho * g, rtol=0, atol=4e-16)
+
+
+def test_collision_at_omega_one_is_equilibrium_plus_source():
+    rng = np.random.default_rng(4)
+    f = Wf * (1.0 + 0.01 * rng.standard_normal(19))
+    fs = oracle.collide_node(f, 1.0, (0, 0, 0))
+    rho = f.sum()
+    u = (C.T @ f) / rho
+    np.testing.assert_allclose(fs, oracle.equilibrium(rho, u), rtol=0, atol=1e-17)
+
+
+def test_identity_collider_is_identity():
+    f = np.random.default_rng(5).standard_normal(19)
+    np.testing.assert_array_equal(oracle.collide_node(f, 1.3, G, "identity"), f)
+
+
+# ---------------------------------------------------------------- propagation = permutation
+def _numpy_pull_permutation(B, solid):
+    """A[i][x] = B[i][x - c_i], or B[opp i][x] when x - c_i is solid (periodic box)."""
+    A = np.zeros_like(B)
+    for i in range(19):
+        shift = (int(C[i, 2]), int(C[i, 1]), int(C[i, 0]))  # array axes are z, y, x
+        src = np.roll(B[i], shift, axis=(0, 1, 2))
+        src_solid = np.roll(solid, shift, axis=(0, 1, 2)).astype(bool)
+        A[i] = np.where(src_solid, B[OPP[i]], src)
+    A[:, solid.astype(bool)] = 0.0
+    return A
+
+
+@pytest.mark.parametrize("shape", [(5, 6, 7), (8, 4, 3), (1, 1, 9)])
+def test_stream_only_step_is_exact_permutation(shape):
+    rng = np.random.default_rng(11)
+    solid = (rng.random(shape) < 0.25).astype(np.uint8)
+    # random 64-bit patterns, NaN payloads included: only a permutation keeps them
+    bits = rng.integers(0, 2**63, size=(19,) + shape, dtype=np.int64)
+    f = bits.view(np.float64).copy()
+    f[:, solid.astype(bool)] = 0.0
+    got = oracle.run_ts(f, solid, 1, 1.3, G, collider="identity")
+    want = _numpy_pull_permutation(f, solid)
+    np.testing.assert_array_equal(got.view(np.int64), want.view(np.int64))
+
+
+def test_stream_only_two_steps_compose():
+    rng = np.random.default_rng(12)
+    shape = (6, 5, 4)
+    solid = (rng.random(shape) < 0.3).astype(np.uint8)
+    f = rng.standard_normal((19,) + shape)
+    f[:, solid.astype(bool)] = 0.0
+    got = oracle.run_ts(f, solid, 2, 1.0, G, collider="identity")
+    want = _numpy_pull_permutation(_numpy_pull_permutation(f, solid), solid)
+    np.testing.assert_array_equal(got, want)
+
+
+def test_non_periodic_axis_bounces_back():
+    """Outside a non-periodic axis behaves like a solid cell: same as an explicit wall layer."""
+    rng = np.random.default_rng(13)
+    inner = (4, 3, 5)
+    f_in = rng.standard_normal((19,) + inner)
+    got = oracle.run_ts(f_in, np.zeros(inner, np.uint8), 1, 1.0, G, periodic=(1, 1, 0), collider="identity")
+    padded = np.zeros((19, inner[0] + 2) + inner[1:])
+    padded[:, 1:-1] = f_in
+    solid = np.zeros((inner[0] + 2,) + inner[1:], np.uint8)
+    solid[0] = solid[-1] = 1
+    want = oracle.run_ts(padded, solid, 1, 1.0, G, periodic=(1, 1, 1), collider="identity")[:, 1:-1]
+    np.testing.assert_array_equal(got, want)
+
+
+# ---------------------------------------------------------------- whole runs
+def _config1_state():
+    solid = lbm_inputs.channel_mask(32, 32, 32)
+    ru = lbm_inputs.rho_u_field(solid.shape, lbm_inputs.velocity_noise(solid.shape, 1e-3, seed=1))
+    return solid, oracle.init_equilibrium(ru, solid)
+
+
+def test_mass_conservation_config1():
+    solid, f0 = _config1_state()
+    f = oracle.run_ts(f0, solid, 100, 1.0, G)
+    M0 = oracle.moments(f0, solid)[0]
+    M1 = oracle.moments(f, solid)[0]
+    assert abs(M1 - M0) / M0 <= 1e-13
+
+
+def test_mass_conservation_porous():
+    solid, _ = lbm_inputs.sphere_pack(24, 3, 0.5, seed=9)
+    ru = lbm_inputs.rho_u_field(solid.shape, lbm_inputs.velocity_noise(solid.shape, 1e-3, seed=2))
+    f0 = oracle.init_equilibrium(ru, solid)
+    f = oracle.run_ts(f0, solid, 100, 1.6, G)
+    M0, M1 = oracle.moments(f0, solid)[0], oracle.moments(f, solid)[0]
+    assert abs(M1 - M0) / M0 <= 1e-13
+
+
+def test_momentum_grows_by_Mg_per_step_in_periodic_box():
+    shape = (8, 8, 8)
+    solid = np.zeros(shape, np.uint8)
+    ru = lbm_inputs.rho_u_field(shape, lbm_inputs.velocity_noise(shape, 1e-3, seed=3))
+    f0 = oracle.init_equilibrium(ru, solid)
+    g = (1e-5, -2e-5, 3e-6)
+    f = oracle.run_ts(f0, solid, 50, 1.3, g)
+    m0, m1 = oracle.moments(f0, solid), oracle.moments(f, solid)
+    want = m0[1:] + 50 * m0[0] * np.array(g)
+    np.testing.assert_allclose(m1[1:], want, rtol=1e-11, atol=0)
+
+
+def test_rest_state_is_fixed_point():
+    shape = (4, 5, 6)
+    solid = np.zeros(shape, np.uint8)
+    solid[1, 2, 3] = 1
+    f0 = oracle.init_equilibrium(lbm_inputs.rho_u_field(shape), solid)
+    f = oracle.run_ts(f0, solid, 10, 1.4, (0, 0, 0))
+    np.testing.assert_allclose(f, f0, rtol=0, atol=2e-16)
+
+
+def _poiseuille(omega, nz=32, steps=None):
+    solid = lbm_inputs.channel_mask(2, 2, nz)
+    nu = (1.0 / omega - 0.5) / 3.0
+    H = nz - 2
+    steps = steps or int(5 * H * H / nu)
+    f = oracle.init_equilibrium(lbm_inputs.rho_u_field(solid.shape), solid)
+    f = oracle.run_ts(f, solid, steps, omega, G)
+    _, u = oracle.macroscopic(f, solid, G)
+    ux = u[0, 1:-1, 0, 0]
+    z = np.arange(1, nz - 1, dtype=np.float64)
+    exact = G[0] / (2 * nu) * (z - 0.5) * (H + 0.5 - z)  # walls half-way, at z = 1/2 and H + 1/2
+    return f, solid, ux, exact, nu
+
+
+def test_poiseuille_curvature_and_profile():
+    _, _, ux, exact, nu = _poiseuille(1.0)
+    curv = ux[2:] - 2 * ux[1:-1] + ux[:-2]
+    np.testing.assert_allclose(curv, -G[0] / nu, rtol=1e-9)
+    assert np.abs(ux - exact).max() / exact.max() < 1e-3
+
+
+def test_poiseuille_slip_follows_magic_parameter():
+    """BGK is TRT with Lambda = (1/omega - 1/2)^2: the bounce-back slip is (g/nu)(16 Lambda - 3)/24."""
+    for omega in (1.0, 0.8):
+        _, _, ux, exact, nu = _poiseuille(omega)
+        lam = (1.0 / omega - 0.5) ** 2
+        slip = (ux - exact).mean()
+        assert abs(slip / (G[0] / nu * (16 * lam - 3) / 24) - 1) < 5e-3
+
+
+def test_poiseuille_exact_at_magic_relaxation():
+    omega = 1.0 / (0.5 + math.sqrt(3.0) / 4.0)  # Lambda = 3/16
+    _, _, ux, exact, _ = _poiseuille(omega)
+    assert np.abs(ux - exact).max() / exact.max() < 1e-9
+
+
+def test_slit_permeability_closed_form():
+    """Darcy k of a slit of width H in a box of height nz: H^3/(12 nz) (1 + 1/(2 H^2))."""
+    omega = 1.0 / (0.5 + math.sqrt(3.0) / 4.0)
+    f, solid, _, _, _ = _poiseuille(omega)
+    nz = solid.shape[0]
+    H = nz - 2
+    phi = float((solid == 0).mean())
+    k = oracle.permeability(oracle.moments(f, solid), G, omega, phi)
+    want = H ** 3 / (12.0 * nz) * (1 + 1.0 / (2 * H * H))
+    assert abs(k / want - 1) < 1e-9
+
+
+@pytest.mark.parametrize("omega,tol", [(1.0, 1e-5), (1.6, 3e-3)])
+def test_shear_wave_viscosity(omega, tol):
+    L = 64
+    solid = np.zeros((L, 1, 1), np.uint8)
+    z = np.arange(L)
+    ru = lbm_inputs.rho_u_field(solid.shape)
+    ru[1, :, 0, 0] = 1e-4 * np.sin(2 * np.pi * z / L)
+    f = oracle.init_equilibrium(ru, solid)
+    k = 2 * np.pi / L
+
+    def amp(f):
+        _, u = oracle.macroscopic(f, solid, (0, 0, 0))
+        return (u[0, :, 0, 0] * np.sin(k * z)).sum() * 2 / L
+
+    f = oracle.run_ts(f, solid, 200, omega, (0, 0, 0))
+    a1 = amp(f)
+    f = oracle.run_ts(f, solid, 2000, omega, (0, 0, 0))
+    a2 = amp(f)
+    nu = (1.0 / omega - 0.5) / 3.0
+    assert abs(-math.log(a2 / a1) / (k * k * 2000) / nu - 1) < tol
+
+
+# ---------------------------------------------------------------- IDX
+def test_idx_hand_worked_4cube():
+    solid_cells, nodes = idx_4cube()
+    solid = np.zeros((4, 4, 4), np.uint8)
+    for c in solid_cells:
+        solid.reshape(-1)[c] = 1
+    cellmap, idx, nf = oracle.build_idx(solid)
+    assert nf == 62
+    for n, want in nodes.items():
+        assert list(idx[:, n]) == want
+
+
+def test_idx_link_symmetry_and_counts():
+    solid, _ = lbm_inputs.sphere_pack((10, 9, 8), 2, 0.55, seed=21)
+    cellmap, idx, nf = oracle.build_idx(solid)
+    assert nf == int((solid == 0).sum())
+    flat = cellmap.reshape(-1)
+    assert (flat[solid.reshape(-1) == 1] == -1).all()
+    np.testing.assert_array_equal(flat[solid.reshape(-1) == 0], np.arange(nf))
+    for k in range(18):
+        kk = OPP[k + 1] - 1
+        m = idx[k]
+        ok = m >= 0
+        np.testing.assert_array_equal(idx[kk, m[ok]], np.arange(nf)[ok])
+    # number of fluid->solid links equals the count of solid neighbours, direction by direction
+    for k in range(18):
+        shift = tuple(-int(v) for v in C[k + 1][::-1])
+        nb_solid = np.roll(solid, shift, axis=(0, 1, 2)).reshape(-1)[solid.reshape(-1) == 0]
+        assert int((idx[k] == -1).sum()) == int(nb_solid.sum())
+
+
+# ---------------------------------------------------------------- storage rounding
+def test_round_half_matches_ieee_binary16():
+    rng = np.random.default_rng(17)
+    v = np.concatenate([
+        rng.standard_normal(20000) * 10.0 ** rng.integers(-9, 5, 20000),
+        np.array([65504.0, 65519.99, 65520.0, 7e4, 2.0 ** -24, 2.0 ** -25, 1.5 * 2.0 ** -25, 2.0 ** -14,
+                  1.0 + 2.0 ** -11, 1.0 + 3 * 2.0 ** -11, -3.0e-6, 0.0]),
+    ])
+    got = oracle.round_half(v)
+    want = v.astype(np.float16).astype(np.float64)
+    np.testing.assert_array_equal(got, want)
+
+
+def test_quantize_forms():
+    rng = np.random.default_rng(18)
+    solid = np.zeros((3, 3, 3), np.uint8)
+    f = Wf[:, None, None, None] * (1 + 1e-3 * rng.standard_normal((19, 3, 3, 3)))
+    np.testing.assert_array_equal(oracle.quantize(f, solid, "f32"), f.astype(np.float32).astype(np.float64))
+    sigma = 1024.0
+    q = oracle.quantize(f, solid, "f16s", sigma)
+    h = ((f - Wf[:, None, None, None]) * sigma).astype(np.float16).astype(np.float64)
+    np.testing.assert_array_equal(q, Wf[:, None, None, None] + h / sigma)
