@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Benchmark: D3Q19 BGK node updates per second on one MI355X.
+
+Headline (`value`): MFLUP/s of the AA pattern (SoA, direct addressing, FP64)
+on the 256^3 channel (walls z = 0 and 255, periodic x and y, omega = 1.6,
+body force 1e-6 in x, equilibrium start with +-1e-3 velocity noise).  A step
+is one lattice time step (AA kernels alternate even/odd); the timed region
+holds exactly --steps steps with the inputs resident in HBM.
+
+Besides the headline the JSON line carries:
+  roofline      achieved HBM bandwidth of the dominant kernel from its
+                algorithmic bytes per launch and its event-timed average
+                launch duration, against the 8 TB/s HBM3E peak;
+  schemes       MFLUP/s and GB/s of every scheme x layout on the same lattice;
+  porous512     AA and two-step on the 512^3 sphere pack (indirect addressing);
+  copy          the STREAM-style copy bandwidth of the device;
+  cpu_baseline  the FP64 oracle timed on the host cores on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--only-main] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "MFLUP/s D3Q19 AA (fp64/fp32, %HBM roofline); served solves/s + p99 latency"
+KERNEL_SOURCES = ["kernels.hpp", "collide.hpp", "storage.hpp", "d3q19.hpp"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1111_0922_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if still current."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_hash") != kernel_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def channel_grid(P, torch, n, scheme, layout, precision="f64"):
+    import lbm_inputs
+    grid = P.Grid(n, n, n, layout=layout, precision=precision, wall_z=True, omega=1.6, g=(1e-6, 0.0, 0.0))
+    grid.bind(scheme)
+    nf = grid.n_nodes
+    u = torch.from_numpy(lbm_inputs.velocity_noise((n - 2, n, n), 1e-3, seed=1).reshape(3, -1))
+    rho_u = torch.cat([torch.ones(1, nf, dtype=torch.float64), u], 0).cuda()
+    grid.init_equilibrium(rho_u)
+    del rho_u
+    return grid
+
+
+def time_steps(torch, grid, steps, warmup):
+    grid.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    grid.step(steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def per_launch_ms(torch, grid, launches):
+    """Average duration of single-step launches measured with events on the launch stream."""
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * launches)]
+    per_kind = {0: [], 1: []}
+    for k in range(launches):
+        parity = grid.t & 1
+        ev[2 * k].record(stream)
+        grid.step(1)
+        ev[2 * k + 1].record(stream)
+        per_kind[parity].append(k)
+    torch.cuda.synchronize()
+    out = {}
+    for parity, ks in per_kind.items():
+        if ks:
+            out[parity] = float(np.mean([ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in ks]))
+    return out
+
+
+def bench_copy(P, torch, nbytes=4 << 30, reps=10):
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    P.stream_copy(src, dst)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        P.stream_copy(src, dst)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    del src, dst
+    return 2 * nbytes / dt / 1e9
+
+
+def cpu_baseline(budget_s=12.0):
+    """Oracle (two-step, FP64) on the host cores: 256^3 channel steps until the budget is used."""
+    import lbm_inputs
+    import oracle
+    oracle.build(force=False)
+    n = 256
+    solid = lbm_inputs.channel_mask(n, n, n)
+    f = oracle.init_equilibrium(lbm_inputs.rho_u_field(solid.shape), solid)
+    threads = oracle.num_threads(0)
+    nf = int((solid == 0).sum())
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        f = oracle.run_ts(f, solid, 1, 1.6, (1e-6, 0.0, 0.0), threads=threads)
+        steps += 1
+        if time.perf_counter() - t0 > budget_s or steps >= 40:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": round(nf * steps / dt / 1e6, 2), "unit": "MFLUP/s", "cores": threads, "kind": "oracle",
+            "sample": f"256^3 channel, FP64 two-step (pull), {steps} steps, {threads} threads, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--only-main", action="store_true", help="headline AA run only (for profiling)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this library has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    if args.steps % 2:
+        args.steps += 1  # whole even/odd pairs
+
+    import torch
+    import paper_1111_0922_amd as P
+
+    n = 256
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+    log(f"[bench] AA SoA FP64 256^3 channel: warmup {args.warmup}, steps {args.steps}")
+    grid = channel_grid(P, torch, n, "aa", "soa")
+    nf = grid.n_nodes
+    m0 = grid.moments().cpu().numpy()
+    dt = time_steps(torch, grid, args.steps, args.warmup)
+    ms_per_step = dt / args.steps * 1e3
+    mflups = nf * args.steps / dt / 1e6
+    m1 = grid.moments().cpu().numpy()
+    b_lup = P.model_bytes("aa", "direct", "f64")
+    launch = per_launch_ms(torch, grid, 200)
+    dom = max(launch, key=lambda k: launch[k])
+    kname = "aa_even" if dom == 0 else "aa_odd"
+    bytes_per_launch = b_lup * nf
+    achieved = bytes_per_launch / (launch[dom] * 1e-3) / 1e9
+    traffic = measured_traffic(kname, "256cube_f64_soa")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
+                "avg_launch_ms": {("aa_even" if k == 0 else "aa_odd"): round(v, 4) for k, v in launch.items()},
+                "algorithmic_bytes_per_launch": int(bytes_per_launch),
+                "algorithmic_bytes_per_lup": b_lup}
+    del grid
+    torch.cuda.empty_cache()
+
+    result = {"metric": METRIC, "value": round(mflups, 1), "unit": "MFLUP/s", "n_gpus": 1,
+              "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+              "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+              "data": "synthetic",
+              "config": {"workload": "D3Q19 BGK 256^3 channel (walls z=0,255; periodic x,y), direct addressing, "
+                                     "SoA, AA pattern, omega 1.6, g 1e-6 x",
+                         "nodes": nf, "lattice": "256x256x256", "layout": "soa", "addressing": "direct",
+                         "scheme": "aa"},
+              "roofline": roofline,
+              "mass_drift": float(abs(m1[0] - m0[0]) / m0[0])}
+
+    if not args.only_main:
+        log("[bench] copy calibration")
+        result["copy"] = {"GB/s": round(bench_copy(P, torch), 1)}
+        log("[bench] scheme x layout table, 256^3 channel FP64")
+        table = {}
+        for layout in ("soa", "aos"):
+            for scheme in ("ts", "os_push", "os_pull", "aa", "et"):
+                g = channel_grid(P, torch, n, scheme, layout)
+                steps = 100
+                dts = time_steps(torch, g, steps, 10)
+                mf = g.n_nodes * steps / dts / 1e6
+                bl = P.model_bytes(scheme, "direct", "f64")
+                table[f"{scheme}/{layout}"] = {"MFLUP/s": round(mf, 1), "GB/s": round(mf * bl / 1e3, 1),
+                                               "bytes_per_lup": bl, "frac_hbm": round(mf * bl / 1e3 / HBM_PEAK_GBS, 4)}
+                del g
+                torch.cuda.empty_cache()
+                log(f"[bench]   {scheme}/{layout}: {mf:.0f} MFLUP/s")
+        result["schemes"] = table
+
+        log("[bench] 512^3 sphere pack (r 8, porosity 0.40), indirect, FP64")
+        import lbm_inputs
+        mask, spheres = lbm_inputs.sphere_pack(512, 8, 0.40, seed=3)
+        porous = {"spheres": spheres, "porosity": float(1 - mask.mean())}
+        mask_t = torch.from_numpy(mask).cuda()
+        del mask
+        for scheme in ("aa", "ts"):
+            g = P.Grid(512, 512, 512, addressing="indirect", omega=1.6, g=(1e-6, 0, 0))
+            nfp = g.build_idx(mask_t)
+            g.bind(scheme)
+            g.init_equilibrium()
+            steps = 100
+            dts = time_steps(torch, g, steps, 10)
+            mf = nfp * steps / dts / 1e6
+            bl = P.model_bytes(scheme, "indirect", "f64")
+            porous[scheme] = {"MFLUP/s": round(mf, 1), "GB/s": round(mf * bl / 1e3, 1), "bytes_per_lup": bl,
+                              "frac_hbm": round(mf * bl / 1e3 / HBM_PEAK_GBS, 4)}
+            porous["nodes"] = nfp
+            del g
+            torch.cuda.empty_cache()
+            log(f"[bench]   {scheme}: {mf:.0f} MFLUP/s")
+        result["porous512"] = porous
+
+    if not args.no_cpu and not args.only_main:
+        log("[bench] CPU oracle baseline")
+        result["cpu_baseline"] = cpu_baseline()
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -134,6 +134,13 @@ int lbm_destroy_grid(lbm_grid *g);
 /* Replaces omega and g (host values) for subsequent steps. */
 int lbm_set_params(lbm_grid *g, double omega, const double g_acc[3]);
 
+/* Launch options.  LBM_OPT_XCD_REMAP (value 0/1, default 0): order the
+ * update kernels' workgroups so that consecutive node blocks run on the same
+ * XCD (MI355X dispatches workgroups round-robin over its 8 XCDs, each with
+ * its own L2); results are bit-identical either way. */
+enum { LBM_OPT_XCD_REMAP = 1 };
+int lbm_set_option(lbm_grid *g, int32_t option, int64_t value);
+
 /* Buffer sizes of `scheme` on this grid (host struct out).  For an indirect
  * grid, n_nodes, pdf/idx/aux sizes are known only after the first
  * lbm_build_idx call; before it they are 0 and cellmap_bytes /

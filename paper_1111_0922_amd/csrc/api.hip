@@ -1,0 +1,451 @@
+// api.hip -- the C ABI of lbm355.h: validation, buffer bookkeeping and
+// dispatch of the kernel instantiations.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/lbm355.h"
+#include "common.hpp"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_check(hipError_t e, const char *where)
+{
+    if (e == hipSuccess) return LBM_OK;
+    return fail(LBM_E_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+constexpr int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+int pdf_size(int precision) { return precision == LBM_F64 ? 8 : (precision == LBM_F32 ? 4 : 2); }
+
+const PrecTable &table(int precision)
+{
+    return precision == LBM_F64 ? table_f64() : (precision == LBM_F32 ? table_f32() : table_f16s());
+}
+
+bool two_lattices(int scheme) { return scheme == LBM_TS || scheme == LBM_OS_PUSH || scheme == LBM_OS_PULL; }
+bool kernel_scheme(int scheme) { return scheme >= LBM_TS && scheme <= LBM_ET; }
+
+} // namespace
+
+struct lbm_grid {
+    lbm_grid_desc d;
+    int64_t n_cells = 0;
+    int64_t n_nodes = 0; // fluid nodes (direct: cells between the walls)
+    int64_t n_ghost = 0;
+    int idx_phase = 0;   // indirect: 1 after the cellmap pass, 2 after the fill pass
+    // bound state
+    int scheme = -1;
+    void *pdf[2] = {nullptr, nullptr};
+    int cur = 0;         // pdf[cur] holds the state of TS / OS
+    const int32_t *idx = nullptr;
+    const int32_t *aux = nullptr;
+    double *scratch = nullptr;
+    int64_t pitch = 0;
+    int64_t t = 0;
+    int remap = 0;
+};
+
+namespace {
+
+int64_t storage_nodes(const lbm_grid *g, int scheme)
+{
+    if (g->d.addressing == LBM_DIRECT) return g->n_cells;
+    return g->n_nodes + (scheme == LBM_ET ? g->n_ghost : 0);
+}
+
+int64_t idx_pitch_of(const lbm_grid *g) { return round_up(g->n_nodes > 0 ? g->n_nodes : 1, 64); }
+
+uint32_t node_blocks(const lbm_grid *g) { return (uint32_t)((g->n_nodes + BLOCK - 1) / BLOCK); }
+
+KArgs base_args(const lbm_grid *g)
+{
+    KArgs a;
+    std::memset(&a, 0, sizeof a);
+    const lbm_grid_desc &d = g->d;
+    a.idx = g->idx;
+    a.et = g->aux;
+    a.pitch = g->pitch;
+    a.idx_pitch = idx_pitch_of(g);
+    a.plane = (int64_t)d.nx * d.ny;
+    const int z0 = (d.addressing == LBM_DIRECT && d.wall_z) ? 1 : 0;
+    a.z0 = z0;
+    a.z0_offset = (int64_t)z0 * a.plane;
+    a.n_nodes = (uint32_t)g->n_nodes;
+    a.nx = d.nx;
+    a.ny = d.ny;
+    a.nz = d.nz;
+    a.wall = (d.addressing == LBM_DIRECT) ? d.wall_z : 0;
+    a.dvx = make_fastdiv((uint32_t)d.nx);
+    a.dvy = make_fastdiv((uint32_t)d.ny);
+    a.remap = g->remap;
+    a.omega = d.omega;
+    a.gx = d.g[0];
+    a.gy = d.g[1];
+    a.gz = d.g[2];
+    a.sigma = d.precision == LBM_F16S ? d.f16_scale : 1.0;
+    return a;
+}
+
+// read map of the state the next step consumes
+int state_rmap(const lbm_grid *g)
+{
+    switch (g->scheme) {
+    case LBM_OS_PULL: return R_PULL;
+    case LBM_AA: return (g->t & 1) ? R_AAODD : R_LOCAL;
+    case LBM_ET: return (g->t & 1) ? R_ET1 : R_ET0;
+    default: return R_LOCAL;
+    }
+}
+
+int check_bound(const lbm_grid *g)
+{
+    if (!g) return fail(LBM_E_ARG, "null grid");
+    if (g->scheme < 0) return fail(LBM_E_STATE, "no buffers bound (call lbm_bind)");
+    if (g->n_nodes <= 0) return fail(LBM_E_STATE, "grid has no fluid nodes");
+    return LBM_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+const char *lbm_last_error(void) { return g_err.c_str(); }
+
+int lbm_version(void) { return 100; }
+
+int lbm_lattice(int32_t *c, double *w, int32_t *opp_out)
+{
+    for (int i = 0; i < Q; ++i) {
+        if (c) {
+            c[3 * i] = cx(i);
+            c[3 * i + 1] = cy(i);
+            c[3 * i + 2] = cz(i);
+        }
+        if (w) w[i] = wd(i);
+        if (opp_out) opp_out[i] = opp(i);
+    }
+    return LBM_OK;
+}
+
+int lbm_create_grid(const lbm_grid_desc *desc, lbm_grid **out)
+{
+    if (!desc || !out) return fail(LBM_E_ARG, "null argument");
+    const lbm_grid_desc &d = *desc;
+    if (d.nx <= 0 || d.ny <= 0 || d.nz <= 0) return fail(LBM_E_ARG, "box sizes must be positive");
+    const int64_t nc = (int64_t)d.nx * d.ny * d.nz;
+    if (nc >= (int64_t)1 << 31) return fail(LBM_E_ARG, "box of %lld cells exceeds 2^31 - 1", (long long)nc);
+    if (d.addressing != LBM_DIRECT && d.addressing != LBM_INDIRECT) return fail(LBM_E_ARG, "unknown addressing");
+    if (d.layout != LBM_SOA && d.layout != LBM_AOS) return fail(LBM_E_ARG, "unknown layout");
+    if (d.precision < LBM_F64 || d.precision > LBM_F16S) return fail(LBM_E_ARG, "unknown precision");
+    if (!(d.omega > 0.0 && d.omega < 2.0)) return fail(LBM_E_ARG, "omega must lie in (0, 2)");
+    if (d.precision == LBM_F16S && !(d.f16_scale > 0.0)) return fail(LBM_E_ARG, "f16_scale must be > 0");
+    if (d.addressing == LBM_DIRECT && d.wall_z && d.nz < 3) return fail(LBM_E_ARG, "walls need nz >= 3");
+    if (nc * Q >= ((int64_t)1 << 40)) return fail(LBM_E_ARG, "box too large");
+    lbm_grid *g = new lbm_grid();
+    g->d = d;
+    g->n_cells = nc;
+    if (d.addressing == LBM_DIRECT) g->n_nodes = (int64_t)d.nx * d.ny * (d.nz - (d.wall_z ? 2 : 0));
+    *out = g;
+    return LBM_OK;
+}
+
+int lbm_destroy_grid(lbm_grid *g)
+{
+    delete g;
+    return LBM_OK;
+}
+
+int lbm_set_params(lbm_grid *g, double omega, const double g_acc[3])
+{
+    if (!g || !g_acc) return fail(LBM_E_ARG, "null argument");
+    if (!(omega > 0.0 && omega < 2.0)) return fail(LBM_E_ARG, "omega must lie in (0, 2)");
+    g->d.omega = omega;
+    for (int k = 0; k < 3; ++k) g->d.g[k] = g_acc[k];
+    return LBM_OK;
+}
+
+int lbm_set_option(lbm_grid *g, int32_t option, int64_t value)
+{
+    if (!g) return fail(LBM_E_ARG, "null grid");
+    if (option == LBM_OPT_XCD_REMAP) {
+        g->remap = value ? 1 : 0;
+        return LBM_OK;
+    }
+    return fail(LBM_E_ARG, "unknown option %d", option);
+}
+
+int lbm_query_sizes(const lbm_grid *g, int32_t scheme, lbm_sizes *out)
+{
+    if (!g || !out) return fail(LBM_E_ARG, "null argument");
+    if (!kernel_scheme(scheme)) return fail(LBM_E_ARG, "scheme %d has no kernels", scheme);
+    std::memset(out, 0, sizeof *out);
+    const lbm_grid_desc &d = g->d;
+    out->n_cells = g->n_cells;
+    out->n_nodes = g->n_nodes;
+    out->n_ghost = (scheme == LBM_ET) ? g->n_ghost : 0;
+    if (d.addressing == LBM_INDIRECT) {
+        out->cellmap_bytes = round_up(g->n_cells * 4, 256);
+        const int64_t nb = (g->n_cells + IDX_CELLS - 1) / IDX_CELLS;
+        out->build_scratch_bytes = round_up(nb * 2 * 4, 256) + (2 * nb + 2) * 8;
+        if (g->idx_phase == 0) return LBM_OK;
+        out->idx_pitch = idx_pitch_of(g);
+        out->idx_bytes = 18 * out->idx_pitch * 4;
+        if (scheme == LBM_ET) out->aux_bytes = 7 * out->idx_pitch * 4;
+    }
+    const int64_t ns = storage_nodes(g, scheme);
+    const int s = pdf_size(d.precision);
+    out->pitch = round_up(ns, 128);
+    out->pdf_bytes = d.layout == LBM_SOA ? Q * out->pitch * s : round_up(ns * Q * s, 256);
+    out->pdf1_bytes = two_lattices(scheme) ? out->pdf_bytes : 0;
+    out->scratch_bytes = round_up((int64_t)node_blocks(g) * 4 * 8, 256);
+    return LBM_OK;
+}
+
+int lbm_build_idx(lbm_grid *g, const uint8_t *d_mask, int32_t *d_cellmap, int32_t *d_idx, int32_t *d_et,
+                  void *d_scratch, int64_t *n_fluid_out, void *stream)
+{
+    if (!g) return fail(LBM_E_ARG, "null grid");
+    if (g->d.addressing != LBM_INDIRECT) return fail(LBM_E_STATE, "lbm_build_idx needs an indirect grid");
+    if (!d_cellmap) return fail(LBM_E_ARG, "d_cellmap is required");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    BuildArgs b;
+    std::memset(&b, 0, sizeof b);
+    b.mask = d_mask;
+    b.cellmap = d_cellmap;
+    b.nx = g->d.nx;
+    b.ny = g->d.ny;
+    b.nz = g->d.nz;
+    b.dvx = make_fastdiv((uint32_t)b.nx);
+    b.dvy = make_fastdiv((uint32_t)b.ny);
+    b.n_cells = (uint32_t)g->n_cells;
+    b.n_blocks = (uint32_t)((g->n_cells + IDX_CELLS - 1) / IDX_CELLS);
+    b.et_on = g->d.et_ghosts ? 1 : 0;
+    if (!d_idx) {
+        if (!d_mask || !d_scratch) return fail(LBM_E_ARG, "d_mask and d_scratch are required");
+        b.counts = static_cast<int32_t *>(d_scratch);
+        b.offsets = reinterpret_cast<int64_t *>(static_cast<char *>(d_scratch) + round_up((int64_t)b.n_blocks * 2 * 4, 256));
+        launch_idx_phase1(b, s);
+        int rc = hip_check(hipGetLastError(), "index build (cellmap pass)");
+        if (rc) return rc;
+        int64_t totals[2] = {0, 0};
+        rc = hip_check(hipMemcpyAsync(totals, b.offsets + 2 * (int64_t)b.n_blocks, sizeof totals, hipMemcpyDeviceToHost, s),
+                       "index build (totals)");
+        if (rc) return rc;
+        rc = hip_check(hipStreamSynchronize(s), "index build (sync)");
+        if (rc) return rc;
+        g->n_nodes = totals[0];
+        g->n_ghost = g->d.et_ghosts ? totals[1] : 0;
+        g->idx_phase = 1;
+        g->scheme = -1;
+        if (n_fluid_out) *n_fluid_out = g->n_nodes;
+        return LBM_OK;
+    }
+    if (g->idx_phase < 1) return fail(LBM_E_STATE, "call lbm_build_idx with d_idx = NULL first");
+    b.idx = d_idx;
+    b.et = g->d.et_ghosts ? d_et : nullptr;
+    b.et_on = b.et ? 1 : 0;
+    b.idx_pitch = idx_pitch_of(g);
+    b.n_fluid = g->n_nodes;
+    launch_idx_phase2(b, s);
+    int rc = hip_check(hipGetLastError(), "index build (fill pass)");
+    if (rc) return rc;
+    g->idx_phase = 2;
+    if (n_fluid_out) *n_fluid_out = g->n_nodes;
+    return LBM_OK;
+}
+
+int lbm_bind(lbm_grid *g, int32_t scheme, void *d_pdf0, void *d_pdf1, const int32_t *d_idx, const int32_t *d_aux,
+             void *d_scratch)
+{
+    if (!g) return fail(LBM_E_ARG, "null grid");
+    if (!kernel_scheme(scheme)) return fail(LBM_E_ARG, "scheme %d has no kernels", scheme);
+    const bool ind = g->d.addressing == LBM_INDIRECT;
+    if (ind && g->idx_phase < 2) return fail(LBM_E_STATE, "indirect grid: build the index first");
+    if (ind && scheme == LBM_ET && !g->d.et_ghosts)
+        return fail(LBM_E_UNSUPPORTED, "esoteric twist on an indirect grid needs et_ghosts = 1 at creation");
+    if (!d_pdf0 || !d_scratch) return fail(LBM_E_ARG, "pdf0 and scratch are required");
+    if (two_lattices(scheme) && !d_pdf1) return fail(LBM_E_ARG, "this scheme needs a second lattice");
+    if (ind && !d_idx) return fail(LBM_E_ARG, "indirect grid needs the IDX buffer");
+    if (ind && scheme == LBM_ET && !d_aux) return fail(LBM_E_ARG, "indirect esoteric twist needs the ET table");
+    lbm_sizes sz;
+    int rc = lbm_query_sizes(g, scheme, &sz);
+    if (rc) return rc;
+    g->scheme = scheme;
+    g->pdf[0] = d_pdf0;
+    g->pdf[1] = two_lattices(scheme) ? d_pdf1 : nullptr;
+    g->cur = 0;
+    g->idx = ind ? d_idx : nullptr;
+    g->aux = (ind && scheme == LBM_ET) ? d_aux : nullptr;
+    g->scratch = static_cast<double *>(d_scratch);
+    g->pitch = sz.pitch;
+    g->t = 0;
+    return LBM_OK;
+}
+
+int lbm_set_pdfs(lbm_grid *g, const double *d_canon, void *stream)
+{
+    int rc = check_bound(g);
+    if (rc) return rc;
+    if (!d_canon) return fail(LBM_E_ARG, "null canonical array");
+    KArgs a = base_args(g);
+    a.dst = g->pdf[g->cur];
+    a.canon_in = d_canon;
+    table(g->d.precision).set[g->d.addressing][g->d.layout][state_rmap(g)](a, node_blocks(g), static_cast<hipStream_t>(stream));
+    return hip_check(hipGetLastError(), "lbm_set_pdfs");
+}
+
+int lbm_get_pdfs(const lbm_grid *g, double *d_canon, void *stream)
+{
+    int rc = check_bound(g);
+    if (rc) return rc;
+    if (!d_canon) return fail(LBM_E_ARG, "null canonical array");
+    KArgs a = base_args(g);
+    a.src = g->pdf[g->cur];
+    a.canon = d_canon;
+    table(g->d.precision).get[g->d.addressing][g->d.layout][state_rmap(g)](a, node_blocks(g), static_cast<hipStream_t>(stream));
+    return hip_check(hipGetLastError(), "lbm_get_pdfs");
+}
+
+int lbm_init_equilibrium(lbm_grid *g, const double *d_rho_u, void *stream)
+{
+    int rc = check_bound(g);
+    if (rc) return rc;
+    g->t = 0;
+    g->cur = 0;
+    KArgs a = base_args(g);
+    a.dst = g->pdf[0];
+    a.rho_u = d_rho_u;
+    table(g->d.precision).init[g->d.addressing][g->d.layout][state_rmap(g)](a, node_blocks(g), static_cast<hipStream_t>(stream));
+    return hip_check(hipGetLastError(), "lbm_init_equilibrium");
+}
+
+int lbm_step(lbm_grid *g, int32_t scheme, int32_t collider, int64_t n_steps, void *stream)
+{
+    int rc = check_bound(g);
+    if (rc) return rc;
+    if (scheme != g->scheme) return fail(LBM_E_STATE, "scheme %d requested, %d bound", scheme, g->scheme);
+    if (collider != LBM_BGK && collider != LBM_IDENTITY) return fail(LBM_E_ARG, "unknown collider");
+    if (n_steps < 0) return fail(LBM_E_ARG, "negative step count");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const PrecTable &tb = table(g->d.precision);
+    const int A = g->d.addressing, L = g->d.layout, C = collider;
+    const uint32_t nb = node_blocks(g);
+    KArgs a = base_args(g);
+    for (int64_t k = 0; k < n_steps; ++k) {
+        switch (g->scheme) {
+        case LBM_TS:
+            a.src = g->pdf[g->cur];
+            a.dst = g->pdf[1 - g->cur];
+            tb.update[A][L][C][K_TS_COLLIDE](a, nb, s);
+            a.src = g->pdf[1 - g->cur];
+            a.dst = g->pdf[g->cur];
+            tb.update[A][L][C][K_TS_STREAM](a, nb, s);
+            break;
+        case LBM_OS_PUSH:
+        case LBM_OS_PULL:
+            a.src = g->pdf[g->cur];
+            a.dst = g->pdf[1 - g->cur];
+            tb.update[A][L][C][g->scheme == LBM_OS_PUSH ? K_OS_PUSH : K_OS_PULL](a, nb, s);
+            g->cur = 1 - g->cur;
+            break;
+        case LBM_AA:
+            a.src = a.dst = g->pdf[0];
+            tb.update[A][L][C][(g->t & 1) ? K_AA_ODD : K_AA_EVEN](a, nb, s);
+            break;
+        case LBM_ET:
+            a.src = a.dst = g->pdf[0];
+            tb.update[A][L][C][(g->t & 1) ? K_ET1 : K_ET0](a, nb, s);
+            break;
+        }
+        ++g->t;
+    }
+    return hip_check(hipGetLastError(), "lbm_step");
+}
+
+int64_t lbm_time(const lbm_grid *g) { return g ? g->t : -1; }
+
+int lbm_reduce_moments(lbm_grid *g, double *d_out4, void *stream)
+{
+    int rc = check_bound(g);
+    if (rc) return rc;
+    if (!d_out4) return fail(LBM_E_ARG, "null output");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    KArgs a = base_args(g);
+    a.src = g->pdf[g->cur];
+    a.partials = g->scratch;
+    const uint32_t nb = node_blocks(g);
+    table(g->d.precision).reduce[g->d.addressing][g->d.layout][state_rmap(g)](a, nb, s);
+    launch_reduce_final(g->scratch, nb, d_out4, s);
+    return hip_check(hipGetLastError(), "lbm_reduce_moments");
+}
+
+int lbm_stream_copy(const void *d_src, void *d_dst, int64_t bytes, void *stream)
+{
+    if (!d_src || !d_dst || bytes < 0 || (bytes & 15) || ((uintptr_t)d_src & 15) || ((uintptr_t)d_dst & 15))
+        return fail(LBM_E_ARG, "copy needs 16-byte aligned pointers and a multiple of 16 bytes");
+    launch_stream_copy(d_src, d_dst, bytes, static_cast<hipStream_t>(stream));
+    return hip_check(hipGetLastError(), "lbm_stream_copy");
+}
+
+double lbm_model_bytes(int32_t scheme, int32_t addressing, int32_t precision, int32_t model)
+{
+    const int q = Q;
+    const bool ind = addressing == LBM_INDIRECT;
+    if (addressing != LBM_DIRECT && addressing != LBM_INDIRECT) return -1.0;
+    if (model == 0) {
+        // Tables 1-6: PDF transfers (loads, stores, write-allocates) and IDX loads per LUP
+        double pdfs, idxs;
+        switch (scheme) {
+        case LBM_TS: pdfs = 6 * q; idxs = 2 * (q - 1); break;
+        case LBM_OS_PUSH:
+        case LBM_OS_PULL: pdfs = 3 * q; idxs = q - 1; break;
+        case LBM_OS_NT: pdfs = 2 * q; idxs = q - 1; break;
+        case LBM_CG: pdfs = 3 * q - 1; idxs = q - 1; break;
+        case LBM_SWAP: pdfs = 3 * q - 1; idxs = (q - 1) / 2.0; break;
+        case LBM_AA: pdfs = 2 * q; idxs = (q - 1) / 2.0; break;
+        case LBM_ET: pdfs = 2 * q; idxs = (q + 1) / 2.0; break;
+        default: return -1.0;
+        }
+        return pdfs * 8.0 + (ind ? idxs * 4.0 : 0.0);
+    }
+    if (model == 1) {
+        if (precision < LBM_F64 || precision > LBM_F16S) return -1.0;
+        const double s = pdf_size(precision);
+        // no write-allocate on the GPU: each PDF is loaded once and stored once per kernel
+        double pdfs, idxs;
+        switch (scheme) {
+        case LBM_TS: pdfs = 4 * q; idxs = q - 1; break;           // IDX in the propagation kernel only
+        case LBM_OS_PUSH:
+        case LBM_OS_PULL: pdfs = 2 * q; idxs = q - 1; break;
+        case LBM_AA: pdfs = 2 * q; idxs = (q - 1) / 2.0; break;   // q-1 on odd steps, none on even
+        case LBM_ET: pdfs = 2 * q; idxs = 7; break;               // six storage addresses + solid mask
+        default: return -1.0;
+        }
+        return pdfs * s + (ind ? idxs * 4.0 : 0.0);
+    }
+    return -1.0;
+}
+
+} // extern "C"

@@ -1,0 +1,95 @@
+// collide.hpp -- BGK collision with the Guo body force, in registers.
+//
+// The paper's solver uses a TRT collision (Sec. 10) and does not print an
+// operator; this library implements single-relaxation BGK:
+//   rho = sum f_i,  j = sum c_i f_i,  u = (j + rho g / 2) / rho
+//   f_i^eq = w_i rho (1 + 3 c_i.u + 9/2 (c_i.u)^2 - 3/2 u.u)
+//   S_i = (1 - omega/2) w_i [3 (c_i - u) + 9 (c_i.u) c_i] . (rho g)      (Guo, Zheng & Shi 2002)
+//   f_i* = f_i - omega (f_i - f_i^eq) + S_i
+// evaluated per pair of opposite directions, whose equilibria and sources
+// split into a part even in c_i (shared) and a part odd in c_i (sign flip).
+//
+// SHIFTED = true works on v_i = sigma (f_i - w_i) (the FP16 storage form):
+//   rho = 1 + sum v / sigma, j = sum c v / sigma,
+//   v_i^eq = sigma w_i (rho - 1 + rho (3 c.u + 9/2 (c.u)^2 - 3/2 u.u)),
+//   v_i* = v_i - omega (v_i - v_i^eq) + sigma S_i,
+// which equals sigma (f_i* - w_i) in exact arithmetic.
+#pragma once
+
+#include "d3q19.hpp"
+
+namespace lbm {
+
+template <typename T>
+struct CollideParams {
+    T omega, gx, gy, gz;
+    T sigma, inv_sigma;
+};
+
+template <typename T, bool SHIFTED>
+__device__ __forceinline__ void collide_bgk(T (&v)[Q], const CollideParams<T> &p)
+{
+    // moments, fixed summation order
+    T s = T(0), jx = T(0), jy = T(0), jz = T(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        s += v[i];
+        if (cx(i) > 0) jx += v[i];
+        if (cx(i) < 0) jx -= v[i];
+        if (cy(i) > 0) jy += v[i];
+        if (cy(i) < 0) jy -= v[i];
+        if (cz(i) > 0) jz += v[i];
+        if (cz(i) < 0) jz -= v[i];
+    }
+    T rho, drho;
+    if constexpr (SHIFTED) {
+        drho = s * p.inv_sigma;
+        rho = T(1) + drho;
+        jx *= p.inv_sigma;
+        jy *= p.inv_sigma;
+        jz *= p.inv_sigma;
+    } else {
+        rho = s;
+        drho = T(0);
+    }
+    const T inv_rho = T(1) / rho;
+    const T ux = (jx + T(0.5) * rho * p.gx) * inv_rho;
+    const T uy = (jy + T(0.5) * rho * p.gy) * inv_rho;
+    const T uz = (jz + T(0.5) * rho * p.gz) * inv_rho;
+    const T Fx = rho * p.gx, Fy = rho * p.gy, Fz = rho * p.gz;
+    const T uu = ux * ux + uy * uy + uz * uz;
+    const T uF = ux * Fx + uy * Fy + uz * Fz;
+    const T om = p.omega;
+    const T kf = T(1) - T(0.5) * om;            // Guo prefactor (1 - omega/2)
+    const T sc = SHIFTED ? p.sigma : T(1);      // scale of the stored form
+    const T base = SHIFTED ? drho : rho;        // rho (plain) or rho - 1 (shifted)
+
+    // rest direction
+    {
+        constexpr T w0 = T(1.0 / 3.0);
+        const T eq = sc * w0 * (base - rho * T(1.5) * uu);
+        const T src = sc * kf * w0 * (T(-3) * uF);
+        v[0] = v[0] - om * (v[0] - eq) + src;
+    }
+#pragma unroll
+    for (int i = 1; i < Q; i += 2) {
+        const int k = i + 1; // opposite of i
+        const T w = (i <= 6) ? T(1.0 / 18.0) : T(1.0 / 36.0);
+        T cu = T(0), cF = T(0);
+        if (cx(i) > 0) { cu += ux; cF += Fx; }
+        if (cx(i) < 0) { cu -= ux; cF -= Fx; }
+        if (cy(i) > 0) { cu += uy; cF += Fy; }
+        if (cy(i) < 0) { cu -= uy; cF -= Fy; }
+        if (cz(i) > 0) { cu += uz; cF += Fz; }
+        if (cz(i) < 0) { cu -= uz; cF -= Fz; }
+        const T eq_even = sc * w * (base + rho * (T(4.5) * cu * cu - T(1.5) * uu));
+        const T eq_odd = sc * w * rho * T(3) * cu;
+        const T src_even = sc * kf * w * (T(9) * cu * cF - T(3) * uF);
+        const T src_odd = sc * kf * w * T(3) * cF;
+        const T vi = v[i], vk = v[k];
+        v[i] = vi - om * (vi - (eq_even + eq_odd)) + (src_even + src_odd);
+        v[k] = vk - om * (vk - (eq_even - eq_odd)) + (src_even - src_odd);
+    }
+}
+
+} // namespace lbm

@@ -1,0 +1,256 @@
+// common.hip -- precision-independent kernels: final moment reduction, the
+// STREAM-style copy used for bandwidth calibration, and the index-array
+// build of indirect addressing.
+#include "common.hpp"
+
+namespace lbm {
+
+// ------------------------------------------------------------------ final reduction
+__global__ void __launch_bounds__(BLOCK) k_reduce_final(const double *partials, uint32_t n_blocks, double *out)
+{
+    double m[4] = {0.0, 0.0, 0.0, 0.0};
+    for (uint32_t b = threadIdx.x; b < n_blocks; b += BLOCK) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) m[k] += partials[4 * (int64_t)b + k];
+    }
+    block_sum4(m, out);
+}
+
+void launch_reduce_final(const double *partials, uint32_t n_blocks, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLOCK), 0, s, partials, n_blocks, out);
+}
+
+// ------------------------------------------------------------------ copy
+// Each thread moves COPY_UNROLL 16-byte words spaced one block apart, so a
+// wavefront's accesses stay contiguous.
+constexpr int COPY_UNROLL = 4;
+
+__global__ void __launch_bounds__(BLOCK) k_stream_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst, int64_t n16)
+{
+    const int64_t base = (int64_t)blockIdx.x * BLOCK * COPY_UNROLL + threadIdx.x;
+    uint4 v[COPY_UNROLL];
+#pragma unroll
+    for (int u = 0; u < COPY_UNROLL; ++u) {
+        const int64_t k = base + (int64_t)u * BLOCK;
+        if (k < n16) v[u] = src[k];
+    }
+#pragma unroll
+    for (int u = 0; u < COPY_UNROLL; ++u) {
+        const int64_t k = base + (int64_t)u * BLOCK;
+        if (k < n16) dst[k] = v[u];
+    }
+}
+
+void launch_stream_copy(const void *src, void *dst, int64_t bytes, hipStream_t s)
+{
+    const int64_t n16 = bytes / 16;
+    const int64_t blocks = (n16 + BLOCK * COPY_UNROLL - 1) / (BLOCK * COPY_UNROLL);
+    if (blocks > 0)
+        hipLaunchKernelGGL(k_stream_copy, dim3((uint32_t)blocks), dim3(BLOCK), 0, s, static_cast<const uint4 *>(src),
+                           static_cast<uint4 *>(dst), n16);
+}
+
+// ------------------------------------------------------------------ index build
+// Cells are processed in chunks of IDX_CELLS (IDX_PER_THREAD consecutive
+// cells per thread), so a block's fluid cells are numbered in lexicographic
+// order by (block offset) + (exclusive prefix over its threads) + (position
+// inside the thread's run).
+
+__device__ __forceinline__ void cell_xyz(const BuildArgs &b, uint32_t c, int &x, int &y, int &z)
+{
+    const uint32_t q = fdiv(c, b.dvx);
+    x = (int)(c - q * (uint32_t)b.nx);
+    const uint32_t r = fdiv(q, b.dvy);
+    y = (int)(q - r * (uint32_t)b.ny);
+    z = (int)r;
+}
+
+__device__ __forceinline__ uint32_t wrap_cell(const BuildArgs &b, int x, int y, int z)
+{
+    x = x < 0 ? x + b.nx : (x >= b.nx ? x - b.nx : x);
+    y = y < 0 ? y + b.ny : (y >= b.ny ? y - b.ny : y);
+    z = z < 0 ? z + b.nz : (z >= b.nz ? z - b.nz : z);
+    return (uint32_t)x + (uint32_t)b.nx * ((uint32_t)y + (uint32_t)b.ny * (uint32_t)z);
+}
+
+// A solid cell holds esoteric-twist storage when some fluid cell reads it:
+// s = x + o for fluid x and o one of the six non-zero offsets o_i.
+__device__ __forceinline__ bool needs_ghost(const BuildArgs &b, uint32_t c)
+{
+    int x, y, z;
+    cell_xyz(b, c, x, y, z);
+    constexpr int off[6][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}};
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        if (!b.mask[wrap_cell(b, x - off[k][0], y - off[k][1], z - off[k][2])]) return true;
+    return false;
+}
+
+__device__ __forceinline__ void cell_flags(const BuildArgs &b, uint32_t c, int &fluid, int &ghost)
+{
+    fluid = 0;
+    ghost = 0;
+    if (c >= b.n_cells) return;
+    if (!b.mask[c])
+        fluid = 1;
+    else if (b.et_on)
+        ghost = needs_ghost(b, c) ? 1 : 0;
+}
+
+// exclusive prefix over the block of two counters; returns block totals
+__device__ __forceinline__ void block_excl_scan2(int &a, int &g, int &tot_a, int &tot_g)
+{
+    __shared__ int sa[BLOCK], sg[BLOCK];
+    const int t = threadIdx.x;
+    sa[t] = a;
+    sg[t] = g;
+    __syncthreads();
+    for (int off = 1; off < BLOCK; off <<= 1) {
+        int va = 0, vg = 0;
+        if (t >= off) {
+            va = sa[t - off];
+            vg = sg[t - off];
+        }
+        __syncthreads();
+        sa[t] += va;
+        sg[t] += vg;
+        __syncthreads();
+    }
+    tot_a = sa[BLOCK - 1];
+    tot_g = sg[BLOCK - 1];
+    a = sa[t] - a;
+    g = sg[t] - g;
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(BLOCK) k_idx_count(BuildArgs b)
+{
+    int nf = 0, ng = 0;
+    const uint32_t c0 = blockIdx.x * IDX_CELLS + threadIdx.x * IDX_PER_THREAD;
+#pragma unroll
+    for (int u = 0; u < IDX_PER_THREAD; ++u) {
+        int f, g;
+        cell_flags(b, c0 + u, f, g);
+        nf += f;
+        ng += g;
+    }
+    int tf, tg;
+    block_excl_scan2(nf, ng, tf, tg);
+    if (threadIdx.x == 0) {
+        b.counts[blockIdx.x] = tf;
+        b.counts[b.n_blocks + blockIdx.x] = tg;
+    }
+}
+
+// One block of SCAN_THREADS: exclusive scan of the per-block counts into
+// 64-bit offsets, totals in offsets[2 * n_blocks], offsets[2 * n_blocks + 1].
+constexpr int SCAN_THREADS = 1024;
+
+__global__ void __launch_bounds__(SCAN_THREADS) k_idx_scan(BuildArgs b)
+{
+    __shared__ int64_t sf[SCAN_THREADS], sg[SCAN_THREADS];
+    const uint32_t t = threadIdx.x;
+    const uint32_t chunk = (b.n_blocks + SCAN_THREADS - 1) / SCAN_THREADS;
+    const uint32_t lo = t * chunk, hi = min(lo + chunk, b.n_blocks);
+    int64_t f = 0, g = 0;
+    for (uint32_t k = lo; k < hi; ++k) {
+        f += b.counts[k];
+        g += b.counts[b.n_blocks + k];
+    }
+    sf[t] = f;
+    sg[t] = g;
+    __syncthreads();
+    for (uint32_t off = 1; off < SCAN_THREADS; off <<= 1) {
+        int64_t vf = 0, vg = 0;
+        if (t >= off) {
+            vf = sf[t - off];
+            vg = sg[t - off];
+        }
+        __syncthreads();
+        sf[t] += vf;
+        sg[t] += vg;
+        __syncthreads();
+    }
+    int64_t of = sf[t] - f, og = sg[t] - g;
+    for (uint32_t k = lo; k < hi; ++k) {
+        b.offsets[k] = of;
+        b.offsets[b.n_blocks + k] = og;
+        of += b.counts[k];
+        og += b.counts[b.n_blocks + k];
+    }
+    if (t == SCAN_THREADS - 1) {
+        b.offsets[2 * (int64_t)b.n_blocks] = sf[t];
+        b.offsets[2 * (int64_t)b.n_blocks + 1] = sg[t];
+    }
+}
+
+__global__ void __launch_bounds__(BLOCK) k_idx_cellmap(BuildArgs b)
+{
+    int fl[IDX_PER_THREAD], gh[IDX_PER_THREAD];
+    int nf = 0, ng = 0;
+    const uint32_t c0 = blockIdx.x * IDX_CELLS + threadIdx.x * IDX_PER_THREAD;
+#pragma unroll
+    for (int u = 0; u < IDX_PER_THREAD; ++u) {
+        cell_flags(b, c0 + u, fl[u], gh[u]);
+        nf += fl[u];
+        ng += gh[u];
+    }
+    int tf, tg;
+    block_excl_scan2(nf, ng, tf, tg);
+    int64_t idf = b.offsets[blockIdx.x] + nf;
+    int64_t idg = b.offsets[b.n_blocks + blockIdx.x] + ng;
+#pragma unroll
+    for (int u = 0; u < IDX_PER_THREAD; ++u) {
+        const uint32_t c = c0 + u;
+        if (c >= b.n_cells) break;
+        int32_t v = -1;
+        if (fl[u])
+            v = (int32_t)idf++;
+        else if (gh[u])
+            v = (int32_t)(-2 - idg++);
+        b.cellmap[c] = v;
+    }
+}
+
+// One thread per cell: fluid cells write their IDX column (and ET rows).
+__global__ void __launch_bounds__(BLOCK) k_idx_fill(BuildArgs b)
+{
+    const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
+    if (c >= b.n_cells) return;
+    const int32_t n = b.cellmap[c];
+    if (n < 0) return;
+    int x, y, z;
+    cell_xyz(b, c, x, y, z);
+    uint32_t mask = 0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const int32_t v = b.cellmap[wrap_cell(b, x + cx(i), y + cy(i), z + cz(i))];
+        b.idx[(int64_t)(i - 1) * b.idx_pitch + n] = v >= 0 ? v : -1;
+        if (v < 0) mask |= 1u << (i - 1);
+    }
+    if (b.et_on) {
+        constexpr int off[6][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}};
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const int32_t v = b.cellmap[wrap_cell(b, x + off[k][0], y + off[k][1], z + off[k][2])];
+            b.et[(int64_t)k * b.idx_pitch + n] = v >= 0 ? v : (int32_t)(b.n_fluid + (-2 - v));
+        }
+        b.et[6 * b.idx_pitch + n] = (int32_t)mask;
+    }
+}
+
+void launch_idx_phase1(const BuildArgs &b, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_idx_count, dim3(b.n_blocks), dim3(BLOCK), 0, s, b);
+    hipLaunchKernelGGL(k_idx_scan, dim3(1), dim3(SCAN_THREADS), 0, s, b);
+    hipLaunchKernelGGL(k_idx_cellmap, dim3(b.n_blocks), dim3(BLOCK), 0, s, b);
+}
+
+void launch_idx_phase2(const BuildArgs &b, hipStream_t s)
+{
+    const uint32_t blocks = (b.n_cells + BLOCK - 1) / BLOCK;
+    hipLaunchKernelGGL(k_idx_fill, dim3(blocks), dim3(BLOCK), 0, s, b);
+}
+
+} // namespace lbm

@@ -1,0 +1,31 @@
+// common.hpp -- declarations shared by the host API and common.hip.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace lbm {
+
+constexpr int IDX_PER_THREAD = 4;
+constexpr int IDX_CELLS = BLOCK * IDX_PER_THREAD;
+
+struct BuildArgs {
+    const uint8_t *mask;  // 1 = solid
+    int32_t *cellmap;
+    int32_t *idx;         // [18][idx_pitch]
+    int32_t *et;          // [7][idx_pitch] or null
+    int32_t *counts;      // [2][n_blocks] per-chunk fluid and ghost counts
+    int64_t *offsets;     // [2][n_blocks] exclusive offsets, then the two totals
+    int32_t nx, ny, nz;
+    FastDiv dvx, dvy;
+    uint32_t n_cells;
+    uint32_t n_blocks;    // ceil(n_cells / IDX_CELLS)
+    int64_t idx_pitch;
+    int64_t n_fluid;
+    int32_t et_on;
+};
+
+void launch_idx_phase1(const BuildArgs &b, hipStream_t s);
+void launch_idx_phase2(const BuildArgs &b, hipStream_t s);
+void launch_stream_copy(const void *src, void *dst, int64_t bytes, hipStream_t s);
+
+} // namespace lbm

@@ -1,0 +1,79 @@
+// instantiate.hpp -- builds the launch table of one storage precision.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace lbm {
+
+template <int A, int L, int P, int K, int C>
+void launch_update(const KArgs &a, uint32_t blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_update<A, L, P, K, C>), dim3(blocks), dim3(BLOCK), 0, s, a);
+}
+template <int A, int L, int P, int R>
+void launch_get(const KArgs &a, uint32_t blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_get<A, L, P, R>), dim3(blocks), dim3(BLOCK), 0, s, a);
+}
+template <int A, int L, int P, int R>
+void launch_set(const KArgs &a, uint32_t blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_set<A, L, P, R>), dim3(blocks), dim3(BLOCK), 0, s, a);
+}
+template <int A, int L, int P, int R>
+void launch_init(const KArgs &a, uint32_t blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_init<A, L, P, R>), dim3(blocks), dim3(BLOCK), 0, s, a);
+}
+template <int A, int L, int P, int R>
+void launch_reduce(const KArgs &a, uint32_t blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_reduce<A, L, P, R>), dim3(blocks), dim3(BLOCK), 0, s, a);
+}
+
+template <int A, int L, int P, int C>
+void fill_updates(PrecTable &t)
+{
+    t.update[A][L][C][K_TS_COLLIDE] = &launch_update<A, L, P, K_TS_COLLIDE, C>;
+    t.update[A][L][C][K_TS_STREAM] = &launch_update<A, L, P, K_TS_STREAM, 0>; // no collision
+    t.update[A][L][C][K_OS_PUSH] = &launch_update<A, L, P, K_OS_PUSH, C>;
+    t.update[A][L][C][K_OS_PULL] = &launch_update<A, L, P, K_OS_PULL, C>;
+    t.update[A][L][C][K_AA_EVEN] = &launch_update<A, L, P, K_AA_EVEN, C>;
+    t.update[A][L][C][K_AA_ODD] = &launch_update<A, L, P, K_AA_ODD, C>;
+    t.update[A][L][C][K_ET0] = &launch_update<A, L, P, K_ET0, C>;
+    t.update[A][L][C][K_ET1] = &launch_update<A, L, P, K_ET1, C>;
+}
+
+template <int A, int L, int P, int R>
+void fill_map(PrecTable &t)
+{
+    t.get[A][L][R] = &launch_get<A, L, P, R>;
+    t.set[A][L][R] = &launch_set<A, L, P, R>;
+    t.init[A][L][R] = &launch_init<A, L, P, R>;
+    t.reduce[A][L][R] = &launch_reduce<A, L, P, R>;
+}
+
+template <int A, int L, int P>
+void fill_al(PrecTable &t)
+{
+    fill_updates<A, L, P, 0>(t);
+    fill_updates<A, L, P, 1>(t);
+    fill_map<A, L, P, R_LOCAL>(t);
+    fill_map<A, L, P, R_PULL>(t);
+    fill_map<A, L, P, R_AAODD>(t);
+    fill_map<A, L, P, R_ET0>(t);
+    fill_map<A, L, P, R_ET1>(t);
+}
+
+template <int P>
+PrecTable make_table()
+{
+    PrecTable t{};
+    fill_al<A_DIRECT, L_SOA, P>(t);
+    fill_al<A_DIRECT, L_AOS, P>(t);
+    fill_al<A_INDIRECT, L_SOA, P>(t);
+    fill_al<A_INDIRECT, L_AOS, P>(t);
+    return t;
+}
+
+} // namespace lbm

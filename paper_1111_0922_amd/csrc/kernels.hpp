@@ -1,0 +1,473 @@
+// kernels.hpp -- the fused D3Q19 node-update kernels of every propagation
+// scheme, written once over (addressing, layout, precision, scheme kernel,
+// collider) and instantiated per precision in k_<prec>.hip.
+//
+// One lane updates one node.  A kernel reads the node's 19 PDFs through the
+// scheme's read map, collides them in registers and stores them through the
+// scheme's write map.  The maps (Secs. 2, 3, 6, 7):
+//
+//   read maps (slot = (direction array j, cell)):
+//     LOCAL   (i, x)
+//     PULL    (i, x - c_i), or (opp i, x) when x - c_i is solid  [bounce-back]
+//     AAODD   (opp i, x - c_i), or (i, x) when x - c_i is solid
+//     ET(p)   (ph(i), x + o_i), ph(i) = i at even parity, opp i at odd parity
+//   write maps:
+//     LOCAL   (i, x)
+//     PUSH    (i, x + c_i), or (opp i, x) when x + c_i is solid
+//     AAEVEN  (opp i, x)
+//     ET(p)   (ph(opp i), x + o_{opp i}), or (ph(i), x + o_{opp i}) when x + c_i is solid
+//
+//   two-step    collision LOCAL(A) -> LOCAL(B); propagation PULL(B) -> LOCAL(A)   (Sec. 2)
+//   one-step    push LOCAL(A) -> PUSH(B); pull PULL(A) -> LOCAL(B); swap A, B     (Sec. 3)
+//   AA pattern  even LOCAL(P) -> AAEVEN(P); odd AAODD(P) -> PUSH(P)               (Sec. 6)
+//   esoteric twist  ET(t mod 2)(P) -> ET(t mod 2)(P)                              (Sec. 7)
+//
+// For AA and ET the write set of a node equals its read set, so nodes are
+// independent and update in place.  The offsets o_i = max(-c_i, 0) satisfy
+// o_{opp i} - o_i = c_i, which makes the esoteric twist's write of f_i* land
+// where the neighbour x + c_i reads it after the parity flip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "collide.hpp"
+#include "d3q19.hpp"
+#include "storage.hpp"
+
+namespace lbm {
+
+constexpr int BLOCK = 256;
+
+// ------------------------------------------------------------------ fast division
+// n / d for 0 <= n < 2^31 by multiply-high (round-up method of Granlund and
+// Montgomery, PLDI 1994): s = ceil(log2 d), m = floor(2^32 (2^s - d) / d) + 1.
+struct FastDiv {
+    uint32_t d, m, s;
+};
+
+__host__ __device__ inline FastDiv make_fastdiv(uint32_t d)
+{
+    FastDiv f;
+    f.d = d;
+    uint32_t s = 0;
+    while ((1ull << s) < d) ++s;
+    f.s = s;
+    f.m = (uint32_t)((((1ull << s) - d) << 32) / d + 1);
+    return f;
+}
+
+__host__ __device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv &f)
+{
+#ifdef __HIP_DEVICE_COMPILE__
+    const uint32_t hi = __umulhi(f.m, n);
+#else
+    const uint32_t hi = (uint32_t)(((uint64_t)f.m * n) >> 32);
+#endif
+    return (hi + n) >> f.s;
+}
+
+// ------------------------------------------------------------------ enums
+enum Addr : int { A_DIRECT = 0, A_INDIRECT = 1 };
+enum Kind : int { K_TS_COLLIDE = 0, K_TS_STREAM, K_OS_PUSH, K_OS_PULL, K_AA_EVEN, K_AA_ODD, K_ET0, K_ET1, K_NUM };
+enum RMap : int { R_LOCAL = 0, R_PULL, R_AAODD, R_ET0, R_ET1, R_NUM };
+enum WMap : int { W_LOCAL = 0, W_PUSH, W_AAEVEN, W_ET0, W_ET1 };
+
+__host__ __device__ constexpr int rmap_of(int k)
+{
+    return k == K_TS_COLLIDE ? R_LOCAL
+         : k == K_TS_STREAM  ? R_PULL
+         : k == K_OS_PUSH    ? R_LOCAL
+         : k == K_OS_PULL    ? R_PULL
+         : k == K_AA_EVEN    ? R_LOCAL
+         : k == K_AA_ODD     ? R_AAODD
+         : k == K_ET0        ? R_ET0
+                             : R_ET1;
+}
+__host__ __device__ constexpr int wmap_of(int k)
+{
+    return k == K_TS_COLLIDE ? W_LOCAL
+         : k == K_TS_STREAM  ? W_LOCAL
+         : k == K_OS_PUSH    ? W_PUSH
+         : k == K_OS_PULL    ? W_LOCAL
+         : k == K_AA_EVEN    ? W_AAEVEN
+         : k == K_AA_ODD     ? W_PUSH
+         : k == K_ET0        ? W_ET0
+                             : W_ET1;
+}
+
+// what a node needs besides its own address
+enum Need : int { NEED_NONE = 0, NEED_NB = 1, NEED_ET = 2 };
+__host__ __device__ constexpr int need_r(int r) { return (r == R_PULL || r == R_AAODD) ? NEED_NB : (r >= R_ET0 ? NEED_ET : 0); }
+__host__ __device__ constexpr int need_w(int w) { return w == W_PUSH ? NEED_NB : (w >= W_ET0 ? NEED_ET : 0); }
+
+// ------------------------------------------------------------------ kernel arguments
+struct KArgs {
+    const void *src;       // lattice read
+    void *dst;             // lattice written (== src for AA and ET)
+    const int32_t *idx;    // IDX[18][idx_pitch] (indirect)
+    const int32_t *et;     // ET table [7][idx_pitch] (indirect ET)
+    int64_t pitch;         // SoA elements between direction arrays
+    int64_t idx_pitch;
+    int64_t plane;         // nx * ny
+    int64_t z0_offset;     // z0 * plane: cell address of node 0 (direct)
+    uint32_t n_nodes;
+    int32_t nx, ny, nz, z0, wall;
+    FastDiv dvx, dvy;
+    int32_t remap;         // XCD-aware block order
+    double omega, gx, gy, gz, sigma;
+    // canonical transfer / reductions
+    double *canon;
+    const double *canon_in;
+    const double *rho_u;
+    double *partials;
+};
+
+// ------------------------------------------------------------------ block order
+// Workgroups are dispatched round-robin over the 8 XCDs (block b on XCD
+// b mod 8).  With remap set, consecutive logical blocks (neighbouring nodes,
+// which share cache lines of the shifted accesses) run on the same XCD and
+// share its L2.  The map is a bijection on [0, gridDim.x).
+__device__ __forceinline__ uint32_t logical_block(int remap)
+{
+    uint32_t b = blockIdx.x;
+    if (remap) {
+        const uint32_t G = gridDim.x, x = b & 7u, s = b >> 3, q = G >> 3, r = G & 7u;
+        b = (x < r) ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
+    }
+    return b;
+}
+
+// ------------------------------------------------------------------ nodes
+template <int ADDR, int NEED>
+struct Node;
+
+// Direct addressing (Sec. 1): index arithmetic on the full box, x and y
+// periodic, z periodic or bounded by solid wall planes z = 0 and z = nz-1.
+template <int NEED>
+struct Node<A_DIRECT, NEED> {
+    int64_t a;
+    int64_t dxp, dxm, dyp, dym, dzp, dzm;
+    bool szp, szm;
+
+    __device__ __forceinline__ void init(const KArgs &k, uint32_t n)
+    {
+        const uint32_t q = fdiv(n, k.dvx);
+        const int x = (int)(n - q * (uint32_t)k.nx);
+        const uint32_t r = fdiv(q, k.dvy);
+        const int y = (int)(q - r * (uint32_t)k.ny);
+        const int z = (int)r + k.z0;
+        a = (int64_t)n + k.z0_offset;
+        dxp = (x == k.nx - 1) ? (int64_t)(1 - k.nx) : 1;
+        dxm = (x == 0) ? (int64_t)(k.nx - 1) : -1;
+        dyp = (y == k.ny - 1) ? -(int64_t)(k.ny - 1) * k.nx : (int64_t)k.nx;
+        dym = (y == 0) ? (int64_t)(k.ny - 1) * k.nx : -(int64_t)k.nx;
+        dzp = (z == k.nz - 1) ? -(int64_t)(k.nz - 1) * k.plane : k.plane;
+        dzm = (z == 0) ? (int64_t)(k.nz - 1) * k.plane : -k.plane;
+        szp = k.wall && (z + 1 == k.nz - 1);
+        szm = k.wall && (z - 1 == 0);
+    }
+    __device__ __forceinline__ int64_t shift(int sx, int sy, int sz) const
+    {
+        return a + (sx > 0 ? dxp : (sx < 0 ? dxm : 0)) + (sy > 0 ? dyp : (sy < 0 ? dym : 0)) +
+               (sz > 0 ? dzp : (sz < 0 ? dzm : 0));
+    }
+    // cell x + c_i and whether it is solid
+    __device__ __forceinline__ int64_t nb(int i) const { return shift(cx(i), cy(i), cz(i)); }
+    __device__ __forceinline__ bool solid(int i) const { return (cz(i) > 0 && szp) || (cz(i) < 0 && szm); }
+    // storage cell x + (ox, oy, oz), ox, oy, oz in {0, 1}
+    __device__ __forceinline__ int64_t at(int sx, int sy, int sz) const { return shift(sx, sy, sz); }
+    __device__ __forceinline__ bool et_solid(int i) const { return solid(i); }
+};
+
+// Indirect addressing (Sec. 1): node ids of fluid nodes; neighbours from
+// IDX (-1 = solid); the esoteric twist reads its storage addresses and the
+// solid-neighbour mask from the ET table.
+template <int NEED>
+struct Node<A_INDIRECT, NEED> {
+    int64_t a;
+    int32_t m[(NEED & NEED_NB) ? 18 : 1];
+    int32_t e[(NEED & NEED_ET) ? 6 : 1];
+    uint32_t mask;
+
+    __device__ __forceinline__ void init(const KArgs &k, uint32_t n)
+    {
+        a = n;
+        if constexpr ((NEED & NEED_NB) != 0) {
+#pragma unroll
+            for (int q = 0; q < 18; ++q) m[q] = k.idx[(int64_t)q * k.idx_pitch + n];
+        }
+        if constexpr ((NEED & NEED_ET) != 0) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) e[q] = k.et[(int64_t)q * k.idx_pitch + n];
+            mask = (uint32_t)k.et[6 * k.idx_pitch + n];
+        }
+    }
+    __device__ __forceinline__ int64_t nb(int i) const { return m[i - 1]; }
+    __device__ __forceinline__ bool solid(int i) const { return m[i - 1] < 0; }
+    __device__ __forceinline__ int64_t at(int sx, int sy, int sz) const
+    {
+        const int c = et_cell(sx, sy, sz);
+        return c == 0 ? a : (int64_t)e[c - 1];
+    }
+    __device__ __forceinline__ bool et_solid(int i) const { return (mask >> (i - 1)) & 1u; }
+};
+
+// ------------------------------------------------------------------ maps
+template <int R, class N>
+__device__ __forceinline__ void read_slot(const N &nd, int i, int &j, int64_t &c)
+{
+    if constexpr (R == R_LOCAL) {
+        j = i;
+        c = nd.a;
+    } else if constexpr (R == R_PULL) {
+        const int o = opp(i);
+        if (i == 0) {
+            j = 0;
+            c = nd.a;
+        } else if (nd.solid(o)) {
+            j = o;
+            c = nd.a;
+        } else {
+            j = i;
+            c = nd.nb(o);
+        }
+    } else if constexpr (R == R_AAODD) {
+        const int o = opp(i);
+        if (i == 0) {
+            j = 0;
+            c = nd.a;
+        } else if (nd.solid(o)) {
+            j = i;
+            c = nd.a;
+        } else {
+            j = o;
+            c = nd.nb(o);
+        }
+    } else {
+        constexpr bool odd = (R == R_ET1);
+        j = odd ? opp(i) : i;
+        c = nd.at(ox(i), oy(i), oz(i));
+    }
+}
+
+template <int W, class N>
+__device__ __forceinline__ void write_slot(const N &nd, int i, int &j, int64_t &c)
+{
+    if constexpr (W == W_LOCAL) {
+        j = i;
+        c = nd.a;
+    } else if constexpr (W == W_PUSH) {
+        if (i == 0) {
+            j = 0;
+            c = nd.a;
+        } else if (nd.solid(i)) {
+            j = opp(i);
+            c = nd.a;
+        } else {
+            j = i;
+            c = nd.nb(i);
+        }
+    } else if constexpr (W == W_AAEVEN) {
+        j = opp(i);
+        c = nd.a;
+    } else {
+        constexpr bool odd = (W == W_ET1);
+        const int o = opp(i);
+        c = nd.at(ox(o), oy(o), oz(o));
+        const bool s = (i != 0) && nd.et_solid(i);
+        j = s ? (odd ? o : i) : (odd ? i : o);
+    }
+}
+
+// ------------------------------------------------------------------ update kernel
+template <int ADDR, int LAY, int PREC, int KIND, int COLL>
+__global__ void __launch_bounds__(BLOCK) k_update(KArgs a)
+{
+    using S = Store<PREC>;
+    using st = typename S::st;
+    using ct = typename S::ct;
+    constexpr int R = rmap_of(KIND);
+    constexpr int W = wmap_of(KIND);
+    const uint32_t n = logical_block(a.remap) * BLOCK + threadIdx.x;
+    if (n >= a.n_nodes) return;
+    Node<ADDR, need_r(R) | need_w(W)> nd;
+    nd.init(a, n);
+    const st *src = static_cast<const st *>(a.src);
+    st *dst = static_cast<st *>(a.dst);
+    ct v[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        int j;
+        int64_t c;
+        read_slot<R>(nd, i, j, c);
+        v[i] = S::load(src[elem<LAY>(j, c, a.pitch)]);
+    }
+    if constexpr (COLL == 1 && KIND != K_TS_STREAM) {
+        CollideParams<ct> p;
+        p.omega = (ct)a.omega;
+        p.gx = (ct)a.gx;
+        p.gy = (ct)a.gy;
+        p.gz = (ct)a.gz;
+        p.sigma = (ct)a.sigma;
+        p.inv_sigma = (ct)(1.0 / a.sigma);
+        collide_bgk<ct, S::shifted>(v, p);
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        int j;
+        int64_t c;
+        write_slot<W>(nd, i, j, c);
+        dst[elem<LAY>(j, c, a.pitch)] = S::save(v[i]);
+    }
+}
+
+// ------------------------------------------------------------------ canonical transfer
+// The canonical state f(t) is what the next step reads: gather (get) and
+// scatter (set, init) go through the read map of the bound scheme's state.
+template <int ADDR, int LAY, int PREC, int R>
+__global__ void __launch_bounds__(BLOCK) k_get(KArgs a)
+{
+    using S = Store<PREC>;
+    using st = typename S::st;
+    const uint32_t n = blockIdx.x * BLOCK + threadIdx.x;
+    if (n >= a.n_nodes) return;
+    Node<ADDR, need_r(R)> nd;
+    nd.init(a, n);
+    const st *src = static_cast<const st *>(a.src);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        int j;
+        int64_t c;
+        read_slot<R>(nd, i, j, c);
+        a.canon[(int64_t)i * a.n_nodes + n] = S::to_canon(src[elem<LAY>(j, c, a.pitch)], i, a.sigma);
+    }
+}
+
+template <int ADDR, int LAY, int PREC, int R>
+__global__ void __launch_bounds__(BLOCK) k_set(KArgs a)
+{
+    using S = Store<PREC>;
+    using st = typename S::st;
+    const uint32_t n = blockIdx.x * BLOCK + threadIdx.x;
+    if (n >= a.n_nodes) return;
+    Node<ADDR, need_r(R)> nd;
+    nd.init(a, n);
+    st *dst = static_cast<st *>(a.dst);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        int j;
+        int64_t c;
+        read_slot<R>(nd, i, j, c);
+        dst[elem<LAY>(j, c, a.pitch)] = S::from_canon(a.canon_in[(int64_t)i * a.n_nodes + n], i, a.sigma);
+    }
+}
+
+// f_i = w_i rho (1 + 3 c_i.u + 9/2 (c_i.u)^2 - 3/2 u.u), FP64
+template <int ADDR, int LAY, int PREC, int R>
+__global__ void __launch_bounds__(BLOCK) k_init(KArgs a)
+{
+    using S = Store<PREC>;
+    using st = typename S::st;
+    const uint32_t n = blockIdx.x * BLOCK + threadIdx.x;
+    if (n >= a.n_nodes) return;
+    Node<ADDR, need_r(R)> nd;
+    nd.init(a, n);
+    double rho = 1.0, ux = 0.0, uy = 0.0, uz = 0.0;
+    if (a.rho_u) {
+        rho = a.rho_u[n];
+        ux = a.rho_u[(int64_t)a.n_nodes + n];
+        uy = a.rho_u[2 * (int64_t)a.n_nodes + n];
+        uz = a.rho_u[3 * (int64_t)a.n_nodes + n];
+    }
+    const double uu = ux * ux + uy * uy + uz * uz;
+    st *dst = static_cast<st *>(a.dst);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double cu = cx(i) * ux + cy(i) * uy + cz(i) * uz;
+        const double feq = wd(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+        int j;
+        int64_t c;
+        read_slot<R>(nd, i, j, c);
+        dst[elem<LAY>(j, c, a.pitch)] = S::from_canon(feq, i, a.sigma);
+    }
+}
+
+// ------------------------------------------------------------------ moments
+// Per node FP64 sums M_n = sum_i f_i, J_n = sum_i c_i f_i; per block a fixed
+// butterfly over the wavefront (64 lanes) then the 4 wavefronts in order.
+__device__ __forceinline__ void block_sum4(double (&m)[4], double *out)
+{
+    __shared__ double part[BLOCK / 64][4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) m[k] += __shfl_xor(m[k], off, 64);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) part[wave][k] = m[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            double s = part[0][k];
+#pragma unroll
+            for (int w = 1; w < BLOCK / 64; ++w) s += part[w][k];
+            out[k] = s;
+        }
+    }
+}
+
+template <int ADDR, int LAY, int PREC, int R>
+__global__ void __launch_bounds__(BLOCK) k_reduce(KArgs a)
+{
+    using S = Store<PREC>;
+    using st = typename S::st;
+    const uint32_t n = blockIdx.x * BLOCK + threadIdx.x;
+    double m[4] = {0.0, 0.0, 0.0, 0.0};
+    if (n < a.n_nodes) {
+        Node<ADDR, need_r(R)> nd;
+        nd.init(a, n);
+        const st *src = static_cast<const st *>(a.src);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            int j;
+            int64_t c;
+            read_slot<R>(nd, i, j, c);
+            const double f = S::to_canon(src[elem<LAY>(j, c, a.pitch)], i, a.sigma);
+            m[0] += f;
+            if (cx(i) > 0) m[1] += f;
+            if (cx(i) < 0) m[1] -= f;
+            if (cy(i) > 0) m[2] += f;
+            if (cy(i) < 0) m[2] -= f;
+            if (cz(i) > 0) m[3] += f;
+            if (cz(i) < 0) m[3] -= f;
+        }
+    }
+    block_sum4(m, a.partials + 4 * (int64_t)blockIdx.x);
+}
+
+// One block: thread t sums partial blocks t, t + 256, ... in order, then the
+// fixed block tree; writes out[0..3].  Defined in common.hip.
+void launch_reduce_final(const double *partials, uint32_t n_blocks, double *out, hipStream_t s);
+
+// ------------------------------------------------------------------ launch table
+using Launch = void (*)(const KArgs &, uint32_t, hipStream_t);
+
+struct PrecTable {
+    Launch update[2][2][2][K_NUM]; // [addr][layout][collider][kind]
+    Launch get[2][2][R_NUM];
+    Launch set[2][2][R_NUM];
+    Launch init[2][2][R_NUM];
+    Launch reduce[2][2][R_NUM];
+};
+
+const PrecTable &table_f64();
+const PrecTable &table_f32();
+const PrecTable &table_f16s();
+
+} // namespace lbm

@@ -21,3 +21,13 @@ def _built_host_parts():
     oracle.build(force=False)
     lbm_inputs.build(force=False)
     yield
+
+
+@pytest.fixture(autouse=True)
+def _announce_gpu_case(request):
+    """Name each GPU case on stderr before it runs, so a run that ends abruptly still says where."""
+    if request.node.get_closest_marker("gpu") is not None:
+        import sys as _sys
+        _sys.stderr.write(f"\n[gpu case] {request.node.nodeid}\n")
+        _sys.stderr.flush()
+    yield

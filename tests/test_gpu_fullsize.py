@@ -1,0 +1,102 @@
+"""Parity at the benchmark sizes, in the launch configuration the benchmark times.
+
+The oracle cannot run 256^3 or 512^3 lattices for many steps in a test, so
+these checks use what it can compute one node at a time: from the GPU's
+canonical state f(t), the oracle's own two-step update of each sampled node's
+3x3x3 neighbourhood (non-periodic, so only the centre is complete) gives
+f(t+1) at the centre, which must match the GPU's f(t+1) to 1e-12.  Mass
+conservation and cross-scheme identity are checked on the whole lattice.
+"""
+import numpy as np
+import pytest
+import torch
+
+import lbm_inputs
+import oracle
+from lbm_cases import from_device, make_grid, rel_err, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+def _sample_update(canon_t, solid, cells, omega, g):
+    """Oracle f(t+1) at `cells` (flat indices) from the canonical state f(t) (fluid nodes only)."""
+    nz, ny, nx = solid.shape
+    ids = _fluid_ids(solid)
+    out = []
+    for c in cells:
+        z, y, x = np.unravel_index(c, solid.shape)
+        zi = [(z + d) % nz for d in (-1, 0, 1)]
+        yi = [(y + d) % ny for d in (-1, 0, 1)]
+        xi = [(x + d) % nx for d in (-1, 0, 1)]
+        sub_cells = (np.array(zi)[:, None, None] * ny + np.array(yi)[None, :, None]) * nx + np.array(xi)[None, None, :]
+        sub_s = solid.reshape(-1)[sub_cells]
+        sub_ids = ids[sub_cells]
+        sub_f = np.where(sub_ids >= 0, canon_t[:, np.maximum(sub_ids, 0)], 0.0)
+        nxt = oracle.run_ts(sub_f, sub_s, 1, omega, g, periodic=(0, 0, 0))
+        out.append(nxt[:, 1, 1, 1])
+    return np.array(out).T
+
+
+def _fluid_ids(solid):
+    ids = np.full(solid.size, -1, np.int64)
+    fl = solid.reshape(-1) == 0
+    ids[fl] = np.arange(int(fl.sum()))
+    return ids
+
+
+@pytest.mark.parametrize("scheme,layout", [("aa", "soa"), ("aa", "aos"), ("et", "soa"), ("ts", "soa"),
+                                           ("os_pull", "soa"), ("os_push", "aos")])
+def test_256_channel_sampled(scheme, layout):
+    n = 256
+    solid = lbm_inputs.channel_mask(n, n, n)
+    omega, g = 1.6, (1e-6, 0.0, 0.0)
+    rng = np.random.default_rng(1)
+    grid = make_grid(solid, scheme, layout=layout, omega=omega, g=g)
+    nf = grid.n_nodes
+    u = torch.from_numpy(lbm_inputs.velocity_noise((n - 2, n, n), 1e-3, seed=1).reshape(3, -1))
+    rho_u = torch.cat([torch.ones(1, nf, dtype=torch.float64), u], 0)
+    grid.init_equilibrium(rho_u.cuda())
+    m0 = from_device(grid.moments())
+    grid.step(9)  # odd count: the next step runs the other kernel of the pair
+    for extra in (1, 2):
+        ft = from_device(grid.get_pdfs())
+        grid.step(1)
+        ft1 = from_device(grid.get_pdfs())
+        cells = rng.choice(np.flatnonzero(solid.reshape(-1) == 0), 300, replace=False)
+        cells = np.concatenate([cells, [n * n + 0, n * n * (n - 1) - 1, n * n + n - 1]])  # wrap corners
+        ids = _fluid_ids(solid)[cells]
+        want = _sample_update(ft, solid, cells, omega, g)
+        assert rel_err(ft1[:, ids], want) <= 1e-12, extra
+        del ft, ft1
+    m1 = from_device(grid.moments())
+    assert abs(m1[0] - m0[0]) / m0[0] <= 1e-13
+
+
+@pytest.fixture(scope="module")
+def pack512():
+    solid, count = lbm_inputs.sphere_pack(512, 8, 0.40, seed=3)
+    return solid
+
+
+@pytest.mark.parametrize("scheme", ["aa", "ts"])
+def test_512_porous_sampled(scheme, pack512):
+    solid = pack512
+    omega, g = 1.6, (1e-6, 0.0, 0.0)
+    grid = make_grid(solid, scheme, addressing="indirect", omega=omega, g=g)
+    cellmap_o, _, nf = oracle.build_idx(solid, with_idx=False)
+    assert grid.n_nodes == nf
+    cm = grid.cellmap[: solid.size]
+    assert torch.equal(torch.where(cm >= 0, cm, torch.full_like(cm, -1)).cpu(),
+                       torch.from_numpy(cellmap_o.reshape(-1)))
+    grid.init_equilibrium()
+    m0 = from_device(grid.moments())
+    grid.step(3)
+    ft = from_device(grid.get_pdfs())
+    grid.step(1)
+    ft1 = from_device(grid.get_pdfs())
+    rng = np.random.default_rng(2)
+    cells = rng.choice(np.flatnonzero(solid.reshape(-1) == 0), 200, replace=False)
+    ids = _fluid_ids(solid)[cells]
+    assert rel_err(ft1[:, ids], _sample_update(ft, solid, cells, omega, g)) <= 1e-12
+    m1 = from_device(grid.moments())
+    assert abs(m1[0] - m0[0]) / m0[0] <= 1e-13

@@ -1,0 +1,80 @@
+"""Index-array build on the GPU: bit-exact against the oracle's builder."""
+import numpy as np
+import pytest
+import torch
+
+import lbm_inputs
+import oracle
+from lbm_cases import make_grid
+
+pytestmark = pytest.mark.gpu
+
+OFFS = [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (1, 0, 1), (0, 1, 1)]
+
+
+def _masks():
+    rng = np.random.default_rng(5)
+    yield "random_37x23x11", (rng.random((11, 23, 37)) < 0.3).astype(np.uint8)
+    yield "spheres_40", lbm_inputs.sphere_pack(40, 4, 0.5, seed=3)[0]
+    yield "channel_16x8x12", lbm_inputs.channel_mask(16, 8, 12)
+    yield "all_fluid_9x7x5", np.zeros((5, 7, 9), np.uint8)
+    yield "thin_1x1x9", (np.arange(9) % 3 == 0).astype(np.uint8).reshape(9, 1, 1)
+    m = np.ones((6, 6, 6), np.uint8)
+    m[2, 3, 4] = 0
+    yield "one_fluid_cell", m
+
+
+def _expected_et(solid, cellmap, nf):
+    """ET storage addresses and solid masks from the definitions (test-side, integer)."""
+    nz, ny, nx = solid.shape
+    flat = cellmap.reshape(-1)
+    fluid = solid == 0
+    ghost = np.zeros_like(fluid)
+    for o in OFFS:
+        # s = x + o is a ghost when s is solid and x = s - o is fluid
+        ghost |= (solid == 1) & np.roll(fluid, (o[2], o[1], o[0]), axis=(0, 1, 2))
+    gid = np.full(solid.size, -1, np.int64)
+    gid[ghost.reshape(-1)] = np.arange(int(ghost.sum()))
+    rows = []
+    for o in OFFS:
+        nb_cell = np.roll(np.arange(solid.size).reshape(solid.shape), (-o[2], -o[1], -o[0]), axis=(0, 1, 2))
+        nbc = nb_cell.reshape(-1)[fluid.reshape(-1)]
+        v = flat[nbc].astype(np.int64)
+        rows.append(np.where(v >= 0, v, nf + gid[nbc]))
+    return np.array(rows), int(ghost.sum())
+
+
+@pytest.mark.parametrize("name,solid", list(_masks()), ids=[n for n, _ in _masks()])
+def test_idx_bit_exact(name, solid):
+    cellmap_o, idx_o, nf = oracle.build_idx(solid)
+    grid = make_grid(solid, "et", addressing="indirect")
+    torch.cuda.synchronize()
+    assert grid.n_nodes == nf
+    s = grid.sizes("et")
+    cm = grid.cellmap[: solid.size].cpu().numpy()
+    np.testing.assert_array_equal(np.where(cm >= 0, cm, -1), cellmap_o.reshape(-1))
+    idx = grid.idx.view(-1)[: 18 * s.idx_pitch].view(18, s.idx_pitch)[:, :nf].cpu().numpy()
+    np.testing.assert_array_equal(idx, idx_o)
+    et = grid.et.view(-1)[: 7 * s.idx_pitch].view(7, s.idx_pitch)[:, :nf].cpu().numpy()
+    want, n_ghost = _expected_et(solid, cellmap_o, nf)
+    assert s.n_ghost == n_ghost
+    np.testing.assert_array_equal(et[:6].astype(np.int64), want)
+    mask_bits = sum(((idx_o[k] < 0).astype(np.int64) << k) for k in range(18))
+    np.testing.assert_array_equal(et[6].astype(np.int64), mask_bits)
+
+
+def test_build_idx_without_et_keeps_plain_cellmap():
+    solid = lbm_inputs.sphere_pack(24, 3, 0.5, seed=1)[0]
+    cellmap_o, idx_o, nf = oracle.build_idx(solid)
+    grid = make_grid(solid, "aa", addressing="indirect")
+    np.testing.assert_array_equal(grid.cellmap[: solid.size].cpu().numpy(), cellmap_o.reshape(-1))
+
+
+def test_no_fluid_grid_refuses_to_bind():
+    import paper_1111_0922_amd as P
+    solid = np.ones((4, 4, 4), np.uint8)
+    grid = P.Grid(4, 4, 4, addressing="indirect")
+    assert grid.build_idx(torch.from_numpy(solid).cuda()) == 0
+    grid.bind("aa")
+    with pytest.raises(P.LbmError):
+        grid.step(1)

@@ -1,0 +1,163 @@
+"""FP64 parity of every GPU scheme against the FP64 oracle (two-step, pull).
+
+Bars (from the build's stated targets): FP64 node values within 1e-12
+relative of the oracle after 100 steps of the 32^3 channel; mass conserved
+to 1e-13; all schemes, layouts and addressings bit-identical to each other
+at even step counts (they share one collision and only move bits otherwise).
+"""
+import numpy as np
+import pytest
+import torch
+
+import lbm_inputs
+import oracle
+from lbm_cases import (ADDRESSING, LAYOUTS, SCHEMES, config1, dense_from_canon, from_device, make_grid, rel_err,
+                       to_device)
+
+pytestmark = pytest.mark.gpu
+
+STEPS = 100
+
+
+@pytest.fixture(scope="module")
+def oracle_config1():
+    solid, f0, omega, g = config1()
+    f100 = oracle.run_ts(f0, solid, STEPS, omega, g)
+    return solid, f0, f100, omega, g
+
+
+@pytest.fixture(scope="module")
+def gpu_results():
+    return {}
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("addressing", ADDRESSING)
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_fp64_config1_matches_oracle(scheme, addressing, layout, oracle_config1, gpu_results):
+    solid, f0, f100, omega, g = oracle_config1
+    grid = make_grid(solid, scheme, addressing=addressing, layout=layout, omega=omega, g=g)
+    grid.set_pdfs(to_device(oracle.fluid_view(f0, solid)))
+    m0 = from_device(grid.moments())
+    grid.step(STEPS)
+    got = from_device(grid.get_pdfs())
+    want = oracle.fluid_view(f100, solid)
+    assert rel_err(got, want) <= 1e-12
+    m1 = from_device(grid.moments())
+    assert abs(m1[0] - m0[0]) / m0[0] <= 1e-13
+    mo = oracle.moments(f100, solid)
+    assert abs(m1[0] - mo[0]) / mo[0] <= 1e-13
+    np.testing.assert_allclose(m1[1:], mo[1:], rtol=1e-9, atol=1e-13 * mo[0])
+    gpu_results[(scheme, addressing, layout)] = got
+
+
+def test_all_variants_bit_identical(gpu_results):
+    """Propagation only moves bits and all kernels share one collision: identical states."""
+    keys = sorted(gpu_results)
+    if len(keys) < 2:
+        pytest.skip("needs the parity runs of this module")
+    ref = gpu_results[keys[0]]
+    for k in keys[1:]:
+        assert np.array_equal(gpu_results[k].view(np.int64), ref.view(np.int64)), k
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_odd_step_counts_match_oracle(scheme):
+    """Odd t exercises the AA odd-step readout and the esoteric twist's odd parity."""
+    solid, f0, omega, g = config1()
+    f7 = oracle.run_ts(f0, solid, 7, 1.6, g)
+    for addressing in ADDRESSING:
+        grid = make_grid(solid, scheme, addressing=addressing, omega=1.6, g=g)
+        grid.set_pdfs(to_device(oracle.fluid_view(f0, solid)))
+        grid.step(7)
+        assert rel_err(from_device(grid.get_pdfs()), oracle.fluid_view(f7, solid)) <= 1e-13
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("shape", [(11, 5, 37), (3, 1, 1), (4, 3, 2)])
+def test_ragged_periodic_boxes(scheme, shape):
+    """Box sizes that are not powers of two, node counts off the 256-lane blocks, axes of length 1."""
+    solid = np.zeros(shape, np.uint8)
+    ru = lbm_inputs.rho_u_field(shape, lbm_inputs.velocity_noise(shape, 1e-2, seed=4))
+    f0 = oracle.init_equilibrium(ru, solid)
+    g = (1e-5, -3e-5, 2e-5)
+    want = oracle.fluid_view(oracle.run_ts(f0, solid, 10, 1.3, g), solid)
+    for addressing in ADDRESSING:
+        for layout in LAYOUTS:
+            grid = make_grid(solid, scheme, addressing=addressing, layout=layout, omega=1.3, g=g)
+            grid.set_pdfs(to_device(oracle.fluid_view(f0, solid)))
+            grid.step(10)
+            assert rel_err(from_device(grid.get_pdfs()), want) <= 1e-13, (addressing, layout)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_porous_indirect_matches_oracle(scheme, layout):
+    solid = lbm_inputs.sphere_pack((29, 21, 18), 3, 0.5, seed=6)[0]
+    ru = lbm_inputs.rho_u_field(solid.shape, lbm_inputs.velocity_noise(solid.shape, 1e-3, seed=5))
+    f0 = oracle.init_equilibrium(ru, solid)
+    g = (1e-5, 0, 0)
+    want = oracle.fluid_view(oracle.run_ts(f0, solid, 40, 1.6, g), solid)
+    grid = make_grid(solid, scheme, addressing="indirect", layout=layout, omega=1.6, g=g)
+    grid.set_pdfs(to_device(oracle.fluid_view(f0, solid)))
+    grid.step(40)
+    assert rel_err(from_device(grid.get_pdfs()), want) <= 1e-12
+
+
+@pytest.mark.parametrize("addressing", ADDRESSING)
+def test_init_equilibrium_matches_oracle(addressing):
+    solid, _, _, _ = config1()
+    ru = lbm_inputs.rho_u_field(solid.shape, lbm_inputs.velocity_noise(solid.shape, 1e-2, seed=8))
+    ru[0] += 0.01 * lbm_inputs.uniform01(9, solid.size).reshape(solid.shape)
+    want = oracle.fluid_view(oracle.init_equilibrium(ru, solid), solid)
+    rho_u = ru.reshape(4, -1)[:, solid.reshape(-1) == 0]
+    for scheme in SCHEMES:
+        grid = make_grid(solid, scheme, addressing=addressing)
+        grid.init_equilibrium(to_device(rho_u))
+        got = from_device(grid.get_pdfs())
+        assert float(np.max(np.abs(got - want))) <= 1e-15
+
+
+def test_rest_init_and_rest_fixed_point():
+    solid = lbm_inputs.channel_mask(8, 8, 8)
+    want = oracle.fluid_view(oracle.init_equilibrium(lbm_inputs.rho_u_field(solid.shape), solid), solid)
+    for scheme in SCHEMES:
+        grid = make_grid(solid, scheme, omega=1.4)
+        grid.init_equilibrium()
+        np.testing.assert_array_equal(from_device(grid.get_pdfs()), want)
+        grid.step(10)
+        assert float(np.max(np.abs(from_device(grid.get_pdfs()) - want))) <= 2e-16
+
+
+def test_reduction_deterministic_and_matches_canonical_sums():
+    solid, f0, omega, g = config1()
+    grid = make_grid(solid, "aa", omega=omega, g=g)
+    grid.set_pdfs(to_device(oracle.fluid_view(f0, solid)))
+    grid.step(3)
+    a = from_device(grid.moments())
+    b = from_device(grid.moments())
+    assert np.array_equal(a, b)
+    canon = from_device(grid.get_pdfs())
+    c = np.array([[0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0],
+                  [0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1],
+                  [0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1]])
+    want = np.concatenate([[np.sum(canon, dtype=np.float64)], (c @ canon).sum(axis=1)])
+    np.testing.assert_allclose(a, want, rtol=1e-12, atol=1e-15)
+
+
+def test_nan_shows_in_mass():
+    solid = lbm_inputs.channel_mask(8, 8, 8)
+    grid = make_grid(solid, "aa")
+    grid.init_equilibrium()
+    canon = grid.get_pdfs()
+    canon[3, 17] = float("nan")
+    grid.set_pdfs(canon)
+    assert np.isnan(from_device(grid.moments())[0])
+
+
+def test_scheme_mismatch_is_an_error():
+    import paper_1111_0922_amd as P
+    solid = lbm_inputs.channel_mask(8, 8, 8)
+    grid = make_grid(solid, "aa")
+    # refused before any launch
+    assert grid.lib.lbm_step(grid._h, P._lib.ET, P._lib.BGK, 1, None) == P._lib.LBM_E_STATE

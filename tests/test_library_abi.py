@@ -1,0 +1,86 @@
+"""Host-side checks of the C-ABI library (no GPU): exports, lattice, transfer model, validation."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from golden_io import d3q19_ordering, table8
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "lbm355.h")) as fh:
+        src = fh.read()
+    return sorted(set(re.findall(r"^[\w \*]*?\b(lbm_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_library_exports_every_declared_function():
+    import paper_1111_0922_amd as P
+    lib = ctypes.CDLL(P._lib.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(P._lib.EXPORTS) | {"lbm_lattice"} or set(P._lib.EXPORTS) <= set(names)
+
+
+def test_lattice_matches_golden_ordering():
+    import paper_1111_0922_amd as P
+    c, w, opp = P.lattice()
+    C, W, OPP = d3q19_ordering()
+    np.testing.assert_array_equal(c, C)
+    np.testing.assert_array_equal(opp, OPP)
+    np.testing.assert_array_equal(w, np.array([float(v) for v in W]))
+
+
+@pytest.mark.parametrize("scheme,key", [("ts", "TS"), ("os_push", "OS"), ("os_pull", "OS"), ("os_nt", "OS-NT"),
+                                        ("cg", "CG"), ("swap", "SWAP"), ("aa", "AAP"), ("et", "ET")])
+def test_paper_transfer_model_reproduces_table8(scheme, key):
+    import paper_1111_0922_amd as P
+    full_pdfs, full_bytes, ind_pdfs, ind_idx, ind_bytes = table8()[key]
+    assert P.model_bytes(scheme, "direct", model="paper") == full_bytes
+    assert P.model_bytes(scheme, "indirect", model="paper") == ind_bytes
+    assert full_bytes == 8 * full_pdfs and ind_bytes == 8 * ind_pdfs + 4 * ind_idx
+
+
+def test_gpu_transfer_model():
+    """No write-allocate: TS moves 4q PDFs, OS/AA/ET 2q; IDX 18 (TS, OS), 9 avg (AA), 7 (ET table)."""
+    import paper_1111_0922_amd as P
+    q = 19
+    for prec, s in (("f64", 8), ("f32", 4), ("f16s", 2)):
+        assert P.model_bytes("ts", "direct", prec) == 4 * q * s
+        for sch in ("os_push", "os_pull", "aa", "et"):
+            assert P.model_bytes(sch, "direct", prec) == 2 * q * s
+        assert P.model_bytes("ts", "indirect", prec) == 4 * q * s + 72
+        assert P.model_bytes("aa", "indirect", prec) == 2 * q * s + 36
+        assert P.model_bytes("et", "indirect", prec) == 2 * q * s + 28
+    assert P.model_bytes("aa", "indirect", "f32") == 188
+    assert P.model_bytes("aa", "indirect", "f16s") == 112
+    assert P.model_bytes("cg", "direct", "f64") < 0
+
+
+def test_validation_errors_without_gpu():
+    import paper_1111_0922_amd as P
+    with pytest.raises(P.LbmError):
+        P.Grid(8, 8, 8, omega=2.0)
+    with pytest.raises(P.LbmError):
+        P.Grid(0, 8, 8)
+    with pytest.raises(P.LbmError):
+        P.Grid(2048, 2048, 1024)
+    with pytest.raises(P.LbmError):
+        P.Grid(8, 8, 2, wall_z=True)
+    with pytest.raises(P.LbmError):
+        P.Grid(8, 8, 8, precision="f16s", f16_scale=0.0)
+    g = P.Grid(32, 32, 32, wall_z=True)
+    assert g.n_nodes == 32 * 32 * 30
+    s = g.sizes("ts")
+    assert s.pdf_bytes == s.pdf1_bytes == 19 * s.pitch * 8 and s.pitch % 128 == 0 and s.pitch >= 32 ** 3
+    assert g.sizes("aa").pdf1_bytes == 0
+    # stepping an unbound grid is refused before any launch
+    assert g.lib.lbm_step(g._h, P._lib.AA, P._lib.BGK, 1, None) == P._lib.LBM_E_STATE
+    gi = P.Grid(16, 16, 16, addressing="indirect")
+    assert gi.sizes("aa").pdf_bytes == 0  # unknown until the index is built
+    assert gi.lib.lbm_bind(gi._h, P._lib.AA, None, None, None, None, None) == P._lib.LBM_E_STATE
