@@ -134,11 +134,17 @@ int lbm_destroy_grid(lbm_grid *g);
 /* Replaces omega and g (host values) for subsequent steps. */
 int lbm_set_params(lbm_grid *g, double omega, const double g_acc[3]);
 
-/* Launch options.  LBM_OPT_XCD_REMAP (value 0/1, default 0): order the
- * update kernels' workgroups so that consecutive node blocks run on the same
- * XCD (MI355X dispatches workgroups round-robin over its 8 XCDs, each with
- * its own L2); results are bit-identical either way. */
-enum { LBM_OPT_XCD_REMAP = 1 };
+/* Launch and layout options (host values; results are bit-identical for any
+ * setting):
+ *   LBM_OPT_XCD_REMAP (0/1, default 0): order the update kernels' workgroups
+ *     so that consecutive node blocks run on the same XCD (MI355X dispatches
+ *     workgroups round-robin over its 8 XCDs, each with its own L2).
+ *   LBM_OPT_PITCH_PAD (elements, default 0, rounded up to a multiple of 128):
+ *     padding added to the SoA pitch so that the 19 direction arrays do not
+ *     start at addresses that agree in their low bits.  Changes the buffer
+ *     sizes: the grid must be bound again afterwards.
+ * Errors: LBM_E_ARG for an unknown option or a value out of range. */
+enum { LBM_OPT_XCD_REMAP = 1, LBM_OPT_PITCH_PAD = 2 };
 int lbm_set_option(lbm_grid *g, int32_t option, int64_t value);
 
 /* Buffer sizes of `scheme` on this grid (host struct out).  For an indirect

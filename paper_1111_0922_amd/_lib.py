@@ -21,6 +21,7 @@ F64, F32, F16S = 0, 1, 2
 TS, OS_PUSH, OS_PULL, AA, ET, OS_NT, CG, SWAP = range(8)
 IDENTITY, BGK = 0, 1
 OPT_XCD_REMAP = 1
+OPT_PITCH_PAD = 2
 
 SCHEMES = {"ts": TS, "os_push": OS_PUSH, "os_pull": OS_PULL, "aa": AA, "et": ET,
            "os_nt": OS_NT, "cg": CG, "swap": SWAP}

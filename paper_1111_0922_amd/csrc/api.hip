@@ -65,6 +65,7 @@ struct lbm_grid {
     int64_t pitch = 0;
     int64_t t = 0;
     int remap = 0;
+    int64_t pitch_pad = 0; // extra SoA elements between direction arrays
 };
 
 namespace {
@@ -193,6 +194,12 @@ int lbm_set_option(lbm_grid *g, int32_t option, int64_t value)
         g->remap = value ? 1 : 0;
         return LBM_OK;
     }
+    if (option == LBM_OPT_PITCH_PAD) {
+        if (value < 0 || value > (1 << 20)) return fail(LBM_E_ARG, "pitch pad must lie in [0, 2^20]");
+        g->pitch_pad = round_up(value, 128);
+        g->scheme = -1; // buffer sizes change: bind again
+        return LBM_OK;
+    }
     return fail(LBM_E_ARG, "unknown option %d", option);
 }
 
@@ -216,7 +223,7 @@ int lbm_query_sizes(const lbm_grid *g, int32_t scheme, lbm_sizes *out)
     }
     const int64_t ns = storage_nodes(g, scheme);
     const int s = pdf_size(d.precision);
-    out->pitch = round_up(ns, 128);
+    out->pitch = round_up(ns, 128) + g->pitch_pad;
     out->pdf_bytes = d.layout == LBM_SOA ? Q * out->pitch * s : round_up(ns * Q * s, 256);
     out->pdf1_bytes = two_lattices(scheme) ? out->pdf_bytes : 0;
     out->scratch_bytes = round_up((int64_t)node_blocks(g) * 4 * 8, 256);

@@ -1,0 +1,77 @@
+"""FP32 and FP16-shifted storage against the oracle with the same storage rounding.
+
+The oracle computes each collision in FP64 and rounds the stored value to
+the storage format; the GPU computes in FP32.  Tolerances follow from that:
+  * FP32 storage: after one step a stored value may differ by the FP32
+    arithmetic error of one collision (a few ulp of f, f ~ w_i <= 1/3):
+    relative 1e-6 (16 ulp).  Over 100 steps the differences perturb the flow
+    and grow like a random walk: relative 2e-5.
+  * FP16 shifted storage h = (f - w_i) sigma: a stored code may round the
+    other way when the FP32 and FP64 values straddle a rounding boundary, one
+    binary16 ulp of h.  Here |f - w_i| < 2^-12, so |h| < 2^-12 sigma and one
+    ulp of h is at most 2^-23 sigma, i.e. 2^-23 in f whatever sigma is.
+    Bars: 4 such ulp (4.8e-7 in f) after one step, 8 after 100 steps.
+Also checked: the reduced-precision runs stay within the stated distance of
+the FP64 oracle, and mass stays conserved through the FP64 reduction.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from lbm_cases import ADDRESSING, LAYOUTS, config1, from_device, make_grid, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def case():
+    solid, f0, omega, g = config1()
+    f64_100 = oracle.fluid_view(oracle.run_ts(f0, solid, 100, omega, g), solid)
+    return solid, f0, omega, g, f64_100
+
+
+def _run(solid, scheme, precision, sigma, q0, steps, omega, g, addressing="direct", layout="soa"):
+    grid = make_grid(solid, scheme, addressing=addressing, layout=layout, precision=precision, omega=omega, g=g,
+                     f16_scale=sigma)
+    grid.set_pdfs(to_device(oracle.fluid_view(q0, solid)))
+    m0 = from_device(grid.moments())
+    grid.step(steps)
+    return from_device(grid.get_pdfs()), m0, from_device(grid.moments())
+
+
+@pytest.mark.parametrize("scheme", ["aa", "et", "ts", "os_pull"])
+@pytest.mark.parametrize("addressing", ADDRESSING)
+def test_fp32_storage(case, scheme, addressing):
+    solid, f0, omega, g, f64_100 = case
+    q0 = oracle.quantize(f0, solid, "f32")
+    for steps, bar in ((1, 1e-6), (100, 2e-5)):
+        want = oracle.fluid_view(oracle.run_ts(q0, solid, steps, omega, g, precision="f32"), solid)
+        got, m0, m1 = _run(solid, scheme, "f32", 1.0, q0, steps, omega, g, addressing)
+        assert float(np.max(np.abs(got - want) / np.abs(want))) <= bar, steps
+        assert abs(m1[0] - m0[0]) / m0[0] <= 1e-6
+    assert float(np.max(np.abs(got - f64_100) / f64_100)) <= 2e-5
+
+
+@pytest.mark.parametrize("sigma", [1.0, 1024.0])
+@pytest.mark.parametrize("scheme", ["aa", "et", "ts", "os_push"])
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_fp16_shifted_storage(case, sigma, scheme, layout):
+    solid, f0, omega, g, f64_100 = case
+    q0 = oracle.quantize(f0, solid, "f16s", sigma)
+    ulp = 2.0 ** -23
+    for steps, k in ((1, 4), (100, 8)):
+        want = oracle.fluid_view(oracle.run_ts(q0, solid, steps, omega, g, precision="f16s", sigma=sigma), solid)
+        got, m0, m1 = _run(solid, scheme, "f16s", sigma, q0, steps, omega, g, layout=layout)
+        assert float(np.max(np.abs(got - want))) <= k * ulp, steps
+    # distance to the full FP64 run after 100 steps
+    assert float(np.max(np.abs(got - f64_100) / f64_100)) <= (1e-5 if sigma == 1.0 else 1e-6)
+
+
+def test_fp16_scale_improves_accuracy(case):
+    solid, f0, omega, g, f64_100 = case
+    errs = {}
+    for sigma in (1.0, 1024.0):
+        q0 = oracle.quantize(f0, solid, "f16s", sigma)
+        got, _, _ = _run(solid, "aa", "f16s", sigma, q0, 100, omega, g)
+        errs[sigma] = float(np.max(np.abs(got - f64_100)))
+    assert errs[1024.0] < errs[1.0] / 4
