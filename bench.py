@@ -147,6 +147,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--only-main", action="store_true", help="headline AA run only (for profiling)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run the copy kernel on 1 GiB, 3 times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this library has no multi-GPU path "
@@ -157,6 +159,17 @@ def main():
 
     import torch
     import paper_1111_0922_amd as P
+
+    if args.calibrate_copy:
+        nbytes = 1 << 30
+        src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            P.stream_copy(src, dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "lbm_stream_copy", "bytes_read": nbytes, "bytes_written": nbytes,
+                          "launches": 3}), flush=True)
+        return
 
     n = 256
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731

@@ -143,8 +143,17 @@ int lbm_set_params(lbm_grid *g, double omega, const double g_acc[3]);
  *     padding added to the SoA pitch so that the 19 direction arrays do not
  *     start at addresses that agree in their low bits.  Changes the buffer
  *     sizes: the grid must be bound again afterwards.
+ *   LBM_OPT_WG_LDS (bytes in [0, 65536], or -1 = default): dynamic LDS
+ *     reserved by every update workgroup on top of what the kernel uses.  It
+ *     only limits how many workgroups a CU (160 KB of LDS) keeps resident,
+ *     which bounds the number of concurrent memory streams.  The default is
+ *     36864 for FP64, 40960 for FP32 and 0 for FP16 storage.
+ *   LBM_OPT_ROW_STAGE (0/1, default 1): on a direct SoA grid whose nx is a
+ *     power of two no larger than 256, every workgroup holds whole x-rows and
+ *     moves the x-shifted PDFs through LDS, so that all global accesses are
+ *     aligned; 0 forces the plain kernels.
  * Errors: LBM_E_ARG for an unknown option or a value out of range. */
-enum { LBM_OPT_XCD_REMAP = 1, LBM_OPT_PITCH_PAD = 2 };
+enum { LBM_OPT_XCD_REMAP = 1, LBM_OPT_PITCH_PAD = 2, LBM_OPT_WG_LDS = 3, LBM_OPT_ROW_STAGE = 4 };
 int lbm_set_option(lbm_grid *g, int32_t option, int64_t value);
 
 /* Buffer sizes of `scheme` on this grid (host struct out).  For an indirect

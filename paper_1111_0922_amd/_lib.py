@@ -12,7 +12,8 @@ import os
 import torch  # noqa: F401  (loads the HIP runtime the library binds to)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblbm355.so")
+# LBM355_LIB selects an alternative build of the same library (measurements of build variants)
+LIB_PATH = os.environ.get("LBM355_LIB") or os.path.join(HERE, "liblbm355.so")
 
 LBM_OK, LBM_E_ARG, LBM_E_STATE, LBM_E_HIP, LBM_E_UNSUPPORTED, LBM_E_DIVERGED = 0, -1, -2, -3, -4, -5
 DIRECT, INDIRECT = 0, 1
@@ -22,6 +23,8 @@ TS, OS_PUSH, OS_PULL, AA, ET, OS_NT, CG, SWAP = range(8)
 IDENTITY, BGK = 0, 1
 OPT_XCD_REMAP = 1
 OPT_PITCH_PAD = 2
+OPT_WG_LDS = 3
+OPT_ROW_STAGE = 4
 
 SCHEMES = {"ts": TS, "os_push": OS_PUSH, "os_pull": OS_PULL, "aa": AA, "et": ET,
            "os_nt": OS_NT, "cg": CG, "swap": SWAP}

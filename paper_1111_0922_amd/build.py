@@ -21,22 +21,25 @@ FLAGS = [
 ]
 
 
-def _compile(src: str, obj: str) -> subprocess.Popen:
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(src: str, obj: str, extra=()) -> subprocess.Popen:
+    cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     return subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
 
 
-def build(verbose: bool = False) -> str:
-    """Compiles every source (in parallel) and links the shared library; returns its path."""
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = False, defines=(), out: str = LIB, build_dir: str = BUILD) -> str:
+    """Compiles every source (in parallel) and links the shared library; returns its path.
+
+    `defines` (e.g. ["LBM_NT_LOAD=0"]) and `out` build alternative variants for measurements.
+    """
+    os.makedirs(build_dir, exist_ok=True)
     procs = []
     for src in SOURCES:
-        obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-        procs.append((src, obj, _compile(src, obj)))
+        obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
+        procs.append((src, obj, _compile(src, obj, [f"-D{d}" for d in defines])))
     objs, failed = [], []
     for src, obj, p in procs:
-        out, _ = p.communicate()
-        lines = [ln for ln in out.splitlines() if "packed-fp32-ops" not in ln]
+        text, _ = p.communicate()
+        lines = [ln for ln in text.splitlines() if "packed-fp32-ops" not in ln]
         if p.returncode != 0:
             failed.append((src, "\n".join(lines)))
         elif verbose and lines:
@@ -45,10 +48,10 @@ def build(verbose: bool = False) -> str:
     if failed:
         msg = "\n".join(f"--- {s}\n{o}" for s, o in failed)
         raise RuntimeError(f"hipcc failed:\n{msg}")
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     subprocess.run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp], check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

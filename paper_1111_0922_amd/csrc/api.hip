@@ -66,6 +66,8 @@ struct lbm_grid {
     int64_t t = 0;
     int remap = 0;
     int64_t pitch_pad = 0; // extra SoA elements between direction arrays
+    int64_t wg_lds = -1;   // dynamic LDS reserved per update workgroup (-1: per-precision default)
+    int row_stage = 1;     // allow the row-staged direct SoA kernels
 };
 
 namespace {
@@ -101,6 +103,14 @@ KArgs base_args(const lbm_grid *g)
     a.dvx = make_fastdiv((uint32_t)d.nx);
     a.dvy = make_fastdiv((uint32_t)d.ny);
     a.remap = g->remap;
+    // Measured on MI355X (256^3 channel): FP64 update workgroups run best with
+    // about two resident per CU for the row-staged kernels (20 KB static LDS +
+    // 36 KB) and four for the others; FP32 likes 40 KB; FP16 wants no cap.
+    a.lds_bytes = (uint32_t)(g->wg_lds >= 0 ? g->wg_lds
+                                           : (d.precision == LBM_F64 ? 36864 : (d.precision == LBM_F32 ? 40960 : 0)));
+    // whole x-rows per workgroup: nx a power of two dividing the workgroup size
+    a.row_staged = (d.addressing == LBM_DIRECT && d.layout == LBM_SOA && g->row_stage && d.nx <= BLOCK &&
+                    (d.nx & (d.nx - 1)) == 0) ? 1 : 0;
     a.omega = d.omega;
     a.gx = d.g[0];
     a.gy = d.g[1];
@@ -192,6 +202,15 @@ int lbm_set_option(lbm_grid *g, int32_t option, int64_t value)
     if (!g) return fail(LBM_E_ARG, "null grid");
     if (option == LBM_OPT_XCD_REMAP) {
         g->remap = value ? 1 : 0;
+        return LBM_OK;
+    }
+    if (option == LBM_OPT_ROW_STAGE) {
+        g->row_stage = value ? 1 : 0;
+        return LBM_OK;
+    }
+    if (option == LBM_OPT_WG_LDS) {
+        if (value < -1 || value > 65536) return fail(LBM_E_ARG, "workgroup LDS must be -1 or lie in [0, 65536] bytes");
+        g->wg_lds = value;
         return LBM_OK;
     }
     if (option == LBM_OPT_PITCH_PAD) {

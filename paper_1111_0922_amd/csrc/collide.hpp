@@ -20,6 +20,10 @@
 
 namespace lbm {
 
+// fused multiply-add in the arithmetic type (one rounding)
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename T>
 struct CollideParams {
     T omega, gx, gy, gz;
@@ -29,6 +33,10 @@ struct CollideParams {
 template <typename T, bool SHIFTED>
 __device__ __forceinline__ void collide_bgk(T (&v)[Q], const CollideParams<T> &p)
 {
+    // No implicit contraction: the fused multiply-adds are written out, so
+    // every kernel this is inlined into rounds identically and all schemes,
+    // layouts and addressings produce bit-identical states.
+#pragma clang fp contract(off)
     // moments, fixed summation order
     T s = T(0), jx = T(0), jy = T(0), jz = T(0);
 #pragma unroll
@@ -64,13 +72,9 @@ __device__ __forceinline__ void collide_bgk(T (&v)[Q], const CollideParams<T> &p
     const T sc = SHIFTED ? p.sigma : T(1);      // scale of the stored form
     const T base = SHIFTED ? drho : rho;        // rho (plain) or rho - 1 (shifted)
 
-    // rest direction
-    {
-        constexpr T w0 = T(1.0 / 3.0);
-        const T eq = sc * w0 * (base - rho * T(1.5) * uu);
-        const T src = sc * kf * w0 * (T(-3) * uF);
-        v[0] = v[0] - om * (v[0] - eq) + src;
-    }
+    // moving directions, in pairs of opposites; the sum of the new values is
+    // kept to close the rest direction below
+    T moving = T(0);
 #pragma unroll
     for (int i = 1; i < Q; i += 2) {
         const int k = i + 1; // opposite of i
@@ -87,9 +91,17 @@ __device__ __forceinline__ void collide_bgk(T (&v)[Q], const CollideParams<T> &p
         const T src_even = sc * kf * w * (T(9) * cu * cF - T(3) * uF);
         const T src_odd = sc * kf * w * T(3) * cF;
         const T vi = v[i], vk = v[k];
-        v[i] = vi - om * (vi - (eq_even + eq_odd)) + (src_even + src_odd);
-        v[k] = vk - om * (vk - (eq_even - eq_odd)) + (src_even - src_odd);
+        // f* = f - omega (f - f^eq) + S
+        v[i] = fmadd(-om, vi - (eq_even + eq_odd), vi) + (src_even + src_odd);
+        v[k] = fmadd(-om, vk - (eq_even - eq_odd), vk) + (src_even - src_odd);
+        moving += v[i] + v[k];
     }
+    // Rest direction by mass conservation: the BGK update with the Guo term
+    // leaves sum_i f_i unchanged, so f_0* = rho - sum_{i>0} f_i* (shifted:
+    // v_0* = sigma (rho - 1) - sum_{i>0} v_i*).  Equal to the direct formula
+    // in exact arithmetic; in floating point it keeps the rounded weights
+    // (whose FP32 sum exceeds 1 by 1.5e-8) from creating mass every step.
+    v[0] = sc * base - moving;
 }
 
 } // namespace lbm

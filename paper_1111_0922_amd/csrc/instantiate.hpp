@@ -8,7 +8,7 @@ namespace lbm {
 template <int A, int L, int P, int K, int C>
 void launch_update(const KArgs &a, uint32_t blocks, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_update<A, L, P, K, C>), dim3(blocks), dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL((k_update<A, L, P, K, C>), dim3(blocks), dim3(BLOCK), a.lds_bytes, s, a);
 }
 template <int A, int L, int P, int R>
 void launch_get(const KArgs &a, uint32_t blocks, hipStream_t s)

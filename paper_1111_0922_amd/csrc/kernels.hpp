@@ -116,6 +116,8 @@ struct KArgs {
     int32_t nx, ny, nz, z0, wall;
     FastDiv dvx, dvy;
     int32_t remap;         // XCD-aware block order
+    uint32_t lds_bytes;    // dynamic LDS reserved per update workgroup (caps residency)
+    int32_t row_staged;    // direct SoA, nx divides BLOCK: x-shifted accesses go through LDS
     double omega, gx, gy, gz, sigma;
     // canonical transfer / reductions
     double *canon;
@@ -281,6 +283,166 @@ __device__ __forceinline__ void write_slot(const N &nd, int i, int &j, int64_t &
     }
 }
 
+// ------------------------------------------------------------------ maps as offsets (direct grids)
+// The same maps as above, giving the slot as (array j, cell offset s) with
+// cell = x + s.  On a direct grid solidity depends on z only, so for a given
+// direction the slot is the same for every node of an x-row.
+template <int R, class N>
+__device__ __forceinline__ void read_off(const N &nd, int i, int &j, int &sx, int &sy, int &sz)
+{
+    sx = sy = sz = 0;
+    if constexpr (R == R_LOCAL) {
+        j = i;
+    } else if constexpr (R == R_PULL || R == R_AAODD) {
+        const int o = opp(i);
+        const bool pull = (R == R_PULL);
+        if (i == 0) {
+            j = 0;
+        } else if (nd.solid(o)) {
+            j = pull ? o : i;
+        } else {
+            j = pull ? i : o;
+            sx = -cx(i);
+            sy = -cy(i);
+            sz = -cz(i);
+        }
+    } else {
+        constexpr bool odd = (R == R_ET1);
+        j = odd ? opp(i) : i;
+        sx = ox(i);
+        sy = oy(i);
+        sz = oz(i);
+    }
+}
+
+template <int W, class N>
+__device__ __forceinline__ void write_off(const N &nd, int i, int &j, int &sx, int &sy, int &sz)
+{
+    sx = sy = sz = 0;
+    if constexpr (W == W_LOCAL) {
+        j = i;
+    } else if constexpr (W == W_PUSH) {
+        if (i == 0) {
+            j = 0;
+        } else if (nd.solid(i)) {
+            j = opp(i);
+        } else {
+            j = i;
+            sx = cx(i);
+            sy = cy(i);
+            sz = cz(i);
+        }
+    } else if constexpr (W == W_AAEVEN) {
+        j = opp(i);
+    } else {
+        constexpr bool odd = (W == W_ET1);
+        const int o = opp(i);
+        sx = ox(o);
+        sy = oy(o);
+        sz = oz(o);
+        const bool s = (i != 0) && nd.et_solid(i);
+        j = s ? (odd ? o : i) : (odd ? i : o);
+    }
+}
+
+// LDS row of the directions with cx != 0 (the only ones an x-shift can touch)
+__host__ __device__ constexpr int xslot(int i)
+{
+    return i == 1 ? 0 : i == 2 ? 1 : (i >= 7 && i <= 14) ? i - 5 : -1;
+}
+constexpr int NXSLOT = 10;
+
+// Direct SoA update with whole x-rows per workgroup (nx divides BLOCK; rows
+// of a workgroup are consecutive nodes).  Every global access is made at the
+// node's own x, so a wavefront touches whole aligned cache lines; an x-shift
+// of +-1 becomes a cyclic shift inside the row, done through LDS:
+//   read  slot x + sx:  thread x loads cell (x, y+sy, z+sz), the consumer
+//                       x - sx picks it up from LDS;
+//   write slot x + sx:  thread x deposits its value at LDS position x + sx,
+//                       the owner of that position stores it at its own x.
+// Threads past n_nodes form whole rows; they skip memory but join barriers.
+template <int PREC, int KIND, int COLL>
+__device__ __forceinline__ void update_direct_staged(const KArgs &a)
+{
+    using S = Store<PREC>;
+    using st = typename S::st;
+    using ct = typename S::ct;
+    constexpr int R = rmap_of(KIND);
+    constexpr int W = wmap_of(KIND);
+    __shared__ st xs[NXSLOT][BLOCK];
+    const uint32_t t = threadIdx.x;
+    const uint32_t n = logical_block(a.remap) * BLOCK + t;
+    const bool valid = n < a.n_nodes;
+    const uint32_t nx = (uint32_t)a.nx; // power of two dividing BLOCK
+    const uint32_t xl = t & (nx - 1), row = t - xl;
+    Node<A_DIRECT, 0> nd;
+    nd.init(a, valid ? n : 0);
+    const st *src = static_cast<const st *>(a.src);
+    st *dst = static_cast<st *>(a.dst);
+    // All 19 loads first (each at the node's own x), so they are in flight
+    // together.  They are unconditional: a thread past n_nodes addresses node
+    // 0 (in bounds) and never stores what it loaded.
+    typename S::rt raw[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        int j, sx, sy, sz;
+        read_off<R>(nd, i, j, sx, sy, sz);
+        raw[i] = pdf_load_raw<S>(src + elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch));
+    }
+    ct v[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        int j, sx, sy, sz;
+        read_off<R>(nd, i, j, sx, sy, sz);
+        if (xslot(i) >= 0 && sx != 0) {
+            xs[xslot(i) < 0 ? 0 : xslot(i)][t] = S::unraw(raw[i]);
+        } else {
+            v[i] = S::load_raw(raw[i]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        if (xslot(i) >= 0) {
+            int j, sx, sy, sz;
+            read_off<R>(nd, i, j, sx, sy, sz);
+            if (sx != 0) v[i] = S::load(xs[xslot(i) < 0 ? 0 : xslot(i)][row + ((xl + (uint32_t)sx) & (nx - 1))]);
+        }
+    }
+    __syncthreads();
+    if constexpr (COLL == 1 && KIND != K_TS_STREAM) {
+        CollideParams<ct> p;
+        p.omega = (ct)a.omega;
+        p.gx = (ct)a.gx;
+        p.gy = (ct)a.gy;
+        p.gz = (ct)a.gz;
+        p.sigma = (ct)a.sigma;
+        p.inv_sigma = (ct)(1.0 / a.sigma);
+        collide_bgk<ct, S::shifted>(v, p);
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        int j, sx, sy, sz;
+        write_off<W>(nd, i, j, sx, sy, sz);
+        if (xslot(i) >= 0) {
+            if (sx != 0) {
+                xs[xslot(i) < 0 ? 0 : xslot(i)][row + ((xl + (uint32_t)sx) & (nx - 1))] = S::save(v[i]);
+                continue;
+            }
+        }
+        if (valid) pdf_store(dst + elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch), S::save(v[i]));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        if (xslot(i) >= 0) {
+            int j, sx, sy, sz;
+            write_off<W>(nd, i, j, sx, sy, sz);
+            if (sx != 0 && valid) pdf_store(dst + elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch), xs[xslot(i) < 0 ? 0 : xslot(i)][t]);
+        }
+    }
+}
+
 // ------------------------------------------------------------------ update kernel
 template <int ADDR, int LAY, int PREC, int KIND, int COLL>
 __global__ void __launch_bounds__(BLOCK) k_update(KArgs a)
@@ -290,6 +452,14 @@ __global__ void __launch_bounds__(BLOCK) k_update(KArgs a)
     using ct = typename S::ct;
     constexpr int R = rmap_of(KIND);
     constexpr int W = wmap_of(KIND);
+    // kernels whose maps never shift along x need no staging
+    constexpr bool shifts = !(R == R_LOCAL && (W == W_LOCAL || W == W_AAEVEN));
+    if constexpr (ADDR == A_DIRECT && LAY == L_SOA && shifts) {
+        if (a.row_staged) {
+            update_direct_staged<PREC, KIND, COLL>(a);
+            return;
+        }
+    }
     const uint32_t n = logical_block(a.remap) * BLOCK + threadIdx.x;
     if (n >= a.n_nodes) return;
     Node<ADDR, need_r(R) | need_w(W)> nd;
@@ -302,7 +472,7 @@ __global__ void __launch_bounds__(BLOCK) k_update(KArgs a)
         int j;
         int64_t c;
         read_slot<R>(nd, i, j, c);
-        v[i] = S::load(src[elem<LAY>(j, c, a.pitch)]);
+        v[i] = S::load(pdf_load(src + elem<LAY>(j, c, a.pitch)));
     }
     if constexpr (COLL == 1 && KIND != K_TS_STREAM) {
         CollideParams<ct> p;
@@ -319,7 +489,7 @@ __global__ void __launch_bounds__(BLOCK) k_update(KArgs a)
         int j;
         int64_t c;
         write_slot<W>(nd, i, j, c);
-        dst[elem<LAY>(j, c, a.pitch)] = S::save(v[i]);
+        pdf_store(dst + elem<LAY>(j, c, a.pitch), S::save(v[i]));
     }
 }
 

@@ -20,10 +20,17 @@ enum Lay : int { L_SOA = 0, L_AOS = 1 };
 template <int P>
 struct Store;
 
+// rt: the register a raw stored value is held in between its load and its
+// conversion.  binary16 values stay in a full 32-bit register (zero-extended
+// 16-bit load): packing two of them per register would chain the loads.
 template <>
 struct Store<P_F64> {
     using st = double;
     using ct = double;
+    using rt = double;
+    __device__ static rt raw(st x) { return x; }
+    __device__ static st unraw(rt r) { return r; }
+    __device__ static ct load_raw(rt r) { return r; }
     static constexpr bool shifted = false;
     __device__ static ct load(st x) { return x; }
     __device__ static st save(ct v) { return v; }
@@ -35,6 +42,10 @@ template <>
 struct Store<P_F32> {
     using st = float;
     using ct = float;
+    using rt = float;
+    __device__ static rt raw(st x) { return x; }
+    __device__ static st unraw(rt r) { return r; }
+    __device__ static ct load_raw(rt r) { return r; }
     static constexpr bool shifted = false;
     __device__ static ct load(st x) { return x; }
     __device__ static st save(ct v) { return v; }
@@ -46,6 +57,10 @@ template <>
 struct Store<P_F16S> {
     using st = _Float16;
     using ct = float;
+    using rt = uint32_t;
+    __device__ static rt raw(st x) { return (uint32_t)__builtin_bit_cast(uint16_t, x); }
+    __device__ static st unraw(rt r) { return __builtin_bit_cast(_Float16, (uint16_t)r); }
+    __device__ static ct load_raw(rt r) { return (float)unraw(r); }
     static constexpr bool shifted = true;
     __device__ static ct load(st x) { return (float)x; }
     __device__ static st save(ct v) { return (_Float16)v; }
@@ -54,6 +69,52 @@ struct Store<P_F16S> {
     // h = (f - w_i) * sigma, rounded once from FP64 to binary16
     __device__ static st from_canon(double f, int i, double sigma) { return (_Float16)((f - wd(i)) * sigma); }
 };
+
+// PDF traffic of the update kernels streams through the caches once per
+// step; loads and stores carry the nontemporal hint unless disabled at build
+// time (LBM_NT_LOAD / LBM_NT_STORE = 0).
+#ifndef LBM_NT_LOAD
+#define LBM_NT_LOAD 1
+#endif
+#ifndef LBM_NT_STORE
+#define LBM_NT_STORE 1
+#endif
+
+template <typename T>
+__device__ __forceinline__ T pdf_load(const T *p)
+{
+#if LBM_NT_LOAD
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+
+// load of one stored PDF into its raw register
+template <class S>
+__device__ __forceinline__ typename S::rt pdf_load_raw(const typename S::st *p)
+{
+    if constexpr (sizeof(typename S::st) == 2) {
+        const uint16_t *q = reinterpret_cast<const uint16_t *>(p);
+#if LBM_NT_LOAD
+        return (uint32_t)__builtin_nontemporal_load(q);
+#else
+        return (uint32_t)*q;
+#endif
+    } else {
+        return pdf_load(p);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void pdf_store(T *p, T v)
+{
+#if LBM_NT_STORE
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
 
 template <int L>
 __device__ __forceinline__ int64_t elem(int j, int64_t a, int64_t pitch)

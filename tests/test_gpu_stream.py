@@ -33,6 +33,10 @@ def _geometries():
     rng = np.random.default_rng(2)
     yield "channel_12x10x9", lbm_inputs.channel_mask(12, 10, 9)
     yield "periodic_7x5x6", np.zeros((6, 5, 7), np.uint8)
+    # nx a power of two: direct SoA grids take the row-staged kernels
+    yield "channel_16x6x7", lbm_inputs.channel_mask(16, 6, 7)
+    yield "periodic_4x3x5", np.zeros((5, 3, 4), np.uint8)
+    yield "periodic_1x4x3", np.zeros((3, 4, 1), np.uint8)
     yield "porous_13x11x10", (rng.random((10, 11, 13)) < 0.3).astype(np.uint8)
 
 
