@@ -230,6 +230,51 @@ int64_t lbm_time(const lbm_grid *g);
  * M NaN.  Uses the bound scratch.  Asynchronous. */
 int lbm_reduce_moments(lbm_grid *g, double *d_out4, void *stream);
 
+/* ---------------------------------------------------------------- batches
+ * Continuous batching of porous-media solves: many lattices of uneven sizes
+ * (indirect SoA grids bound to the AA pattern, one storage precision) share
+ * one persistent batched AA kernel.  A device workspace holds the slot table,
+ * the tile list (tiles of 256 nodes, contiguous per slot), the reduction
+ * partials and the per-slot moments; the launch shape is fixed, so one
+ * captured graph stays valid while slots are added and removed.  A lattice's
+ * update and moments are bit-identical to running it alone with lbm_step and
+ * lbm_reduce_moments.  Slots that share a batch must not be stepped through
+ * lbm_step meanwhile.  Callers serialise calls on one batch. */
+typedef struct lbm_batch lbm_batch;
+
+/* Device workspace bytes for max_slots slots and max_tiles tiles in total. */
+int lbm_batch_workspace_bytes(int32_t max_slots, int64_t max_tiles, int64_t *bytes);
+
+/* Creates a batch over the caller's workspace (device memory, at least
+ * lbm_batch_workspace_bytes, alive until lbm_batch_destroy).  Creates one
+ * internal HIP stream used only to capture the run graph. */
+int lbm_batch_create(int32_t max_slots, int64_t max_tiles, int32_t precision, void *d_workspace, lbm_batch **out);
+
+int lbm_batch_destroy(lbm_batch *b);
+
+/* Adds a grid (indirect, SoA, bound to LBM_AA, the batch's precision, state
+ * initialised) in the first free slot, written to *slot_out.  The grid keeps
+ * its step counter; its parity decides which AA kernel each of its nodes
+ * runs.  Errors: LBM_E_STATE when no slot or tile space is left,
+ * LBM_E_UNSUPPORTED for other grid kinds. */
+int lbm_batch_add(lbm_batch *b, lbm_grid *g, int32_t *slot_out);
+
+/* Empties a slot; the grid's state stays where it is. */
+int lbm_batch_remove(lbm_batch *b, int32_t slot);
+
+/* Advances every active slot by k_steps AA time steps, then reduces each
+ * slot's FP64 moments (M, Jx, Jy, Jz as lbm_reduce_moments) into the
+ * workspace and, when h_moments is not NULL, copies them to h_moments
+ * (pinned host memory, max_slots * 4 doubles; rows of empty slots are left
+ * stale).  use_graph = 1 replays a captured graph (recaptured when k_steps or
+ * h_moments change).  Asynchronous on `stream`: synchronise before reading
+ * h_moments. */
+int lbm_batch_run(lbm_batch *b, int32_t k_steps, double *h_moments, int32_t use_graph, void *stream);
+
+/* Copies the last run's per-slot moments (max_slots * 4 doubles) to device
+ * memory d_out.  Asynchronous. */
+int lbm_batch_moments(lbm_batch *b, double *d_out, void *stream);
+
 /* Plain device copy of `bytes` (multiple of 16, 16-byte aligned pointers):
  * the STREAM-copy bandwidth calibration of Table 7.  Asynchronous. */
 int lbm_stream_copy(const void *d_src, void *d_dst, int64_t bytes, void *stream);

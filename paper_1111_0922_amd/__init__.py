@@ -7,7 +7,8 @@ is not built.
 from . import _lib
 from ._lib import LbmError, load
 from .grid import Grid, lattice, model_bytes, stream_copy
+from .batch import Batch
 
-__all__ = ["Grid", "LbmError", "lattice", "load", "model_bytes", "stream_copy", "_lib"]
+__all__ = ["Batch", "Grid", "LbmError", "lattice", "load", "model_bytes", "stream_copy", "_lib"]
 
 load()

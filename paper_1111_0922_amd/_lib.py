@@ -51,6 +51,8 @@ EXPORTS = [
     "lbm_last_error", "lbm_version", "lbm_lattice", "lbm_create_grid", "lbm_destroy_grid", "lbm_set_params",
     "lbm_set_option", "lbm_query_sizes", "lbm_build_idx", "lbm_bind", "lbm_set_pdfs", "lbm_get_pdfs",
     "lbm_init_equilibrium", "lbm_step", "lbm_time", "lbm_reduce_moments", "lbm_stream_copy", "lbm_model_bytes",
+    "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_destroy", "lbm_batch_add", "lbm_batch_remove",
+    "lbm_batch_run", "lbm_batch_moments",
 ]
 
 _lib = None
@@ -93,6 +95,13 @@ def load():
     lib.lbm_stream_copy.argtypes = [vp, vp, i64, vp]
     lib.lbm_model_bytes.argtypes = [i32, i32, i32, i32]
     lib.lbm_model_bytes.restype = dbl
+    lib.lbm_batch_workspace_bytes.argtypes = [i32, i64, ctypes.POINTER(i64)]
+    lib.lbm_batch_create.argtypes = [i32, i64, i32, vp, ctypes.POINTER(gp)]
+    lib.lbm_batch_destroy.argtypes = [gp]
+    lib.lbm_batch_add.argtypes = [gp, gp, ctypes.POINTER(i32)]
+    lib.lbm_batch_remove.argtypes = [gp, i32]
+    lib.lbm_batch_run.argtypes = [gp, i32, vp, i32, vp]
+    lib.lbm_batch_moments.argtypes = [gp, vp, vp]
     _lib = lib
     return lib
 

@@ -10,14 +10,16 @@
 
 #include "../../include/lbm355.h"
 #include "common.hpp"
+#include "grid_internal.hpp"
 
 using namespace lbm;
 
 namespace {
-
 thread_local std::string g_err;
+}
 
-int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+namespace lbm_host {
+
 int fail(int code, const char *fmt, ...)
 {
     char buf[512];
@@ -35,40 +37,21 @@ int hip_check(hipError_t e, const char *where)
     return fail(LBM_E_HIP, "%s: %s", where, hipGetErrorString(e));
 }
 
+} // namespace lbm_host
+
+using namespace lbm_host;
+
+namespace {
+
 constexpr int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 int pdf_size(int precision) { return precision == LBM_F64 ? 8 : (precision == LBM_F32 ? 4 : 2); }
-
-const PrecTable &table(int precision)
-{
-    return precision == LBM_F64 ? table_f64() : (precision == LBM_F32 ? table_f32() : table_f16s());
-}
 
 bool two_lattices(int scheme) { return scheme == LBM_TS || scheme == LBM_OS_PUSH || scheme == LBM_OS_PULL; }
 bool kernel_scheme(int scheme) { return scheme >= LBM_TS && scheme <= LBM_ET; }
 
 } // namespace
 
-struct lbm_grid {
-    lbm_grid_desc d;
-    int64_t n_cells = 0;
-    int64_t n_nodes = 0; // fluid nodes (direct: cells between the walls)
-    int64_t n_ghost = 0;
-    int idx_phase = 0;   // indirect: 1 after the cellmap pass, 2 after the fill pass
-    // bound state
-    int scheme = -1;
-    void *pdf[2] = {nullptr, nullptr};
-    int cur = 0;         // pdf[cur] holds the state of TS / OS
-    const int32_t *idx = nullptr;
-    const int32_t *aux = nullptr;
-    double *scratch = nullptr;
-    int64_t pitch = 0;
-    int64_t t = 0;
-    int remap = 0;
-    int64_t pitch_pad = 0; // extra SoA elements between direction arrays
-    int64_t wg_lds = -1;   // dynamic LDS reserved per update workgroup (-1: per-precision default)
-    int row_stage = 1;     // allow the row-staged direct SoA kernels
-};
 
 namespace {
 
@@ -76,6 +59,15 @@ int64_t storage_nodes(const lbm_grid *g, int scheme)
 {
     if (g->d.addressing == LBM_DIRECT) return g->n_cells;
     return g->n_nodes + (scheme == LBM_ET ? g->n_ghost : 0);
+}
+
+} // namespace
+
+namespace lbm_host {
+
+const PrecTable &table(int precision)
+{
+    return precision == LBM_F64 ? table_f64() : (precision == LBM_F32 ? table_f32() : table_f16s());
 }
 
 int64_t idx_pitch_of(const lbm_grid *g) { return round_up(g->n_nodes > 0 ? g->n_nodes : 1, 64); }
@@ -129,6 +121,10 @@ int state_rmap(const lbm_grid *g)
     default: return R_LOCAL;
     }
 }
+
+} // namespace lbm_host
+
+namespace {
 
 int check_bound(const lbm_grid *g)
 {

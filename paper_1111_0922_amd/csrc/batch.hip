@@ -1,0 +1,378 @@
+// batch.hip -- continuous batching of many indirect AA-pattern lattices.
+//
+// A batch holds up to max_slots lattices ("slots") of uneven sizes, each an
+// lbm_grid bound to the AA pattern on an indirect SoA grid.  Their nodes are
+// cut into tiles of BLOCK nodes; a device-resident tile list (slot, first
+// node) and slot table drive one persistent kernel that advances every active
+// slot by one time step per launch, each slot with its own parity (the AA
+// pattern alternates its even and odd kernels, Sec. 6).  Because the launch
+// shape is fixed and the tables live in device memory, one captured graph
+// (K step launches, the per-slot moment reduction and the copy of the
+// moments to the host) stays valid while slots come and go.
+//
+// Determinism: a slot's nodes are updated by the same per-node code as the
+// single-lattice kernels, and its moments are reduced tile by tile and then
+// in tile order exactly as lbm_reduce_moments does, so a lattice evolves to
+// the same bits alone or in any mix.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <vector>
+
+#include "common.hpp"
+#include "grid_internal.hpp"
+
+using namespace lbm;
+using namespace lbm_host;
+
+namespace lbm {
+
+struct SlotDesc {
+    void *pdf;
+    const int32_t *idx;
+    int64_t pitch;
+    int64_t idx_pitch;
+    double omega, gx, gy, gz, sigma;
+    uint32_t n_nodes;
+    int32_t t0;          // completed steps of the slot when the run starts
+    uint32_t tile_begin; // its tiles (and reduction partials) are contiguous
+    uint32_t n_tiles;
+    int32_t active;
+    int32_t pad_;
+};
+
+struct Tile {
+    uint32_t slot, node0;
+};
+
+__device__ __forceinline__ KArgs slot_args(const SlotDesc &sd)
+{
+    KArgs a;
+    a.src = sd.pdf;
+    a.dst = sd.pdf;
+    a.idx = sd.idx;
+    a.et = nullptr;
+    a.pitch = sd.pitch;
+    a.idx_pitch = sd.idx_pitch;
+    a.n_nodes = sd.n_nodes;
+    a.omega = sd.omega;
+    a.gx = sd.gx;
+    a.gy = sd.gy;
+    a.gz = sd.gz;
+    a.sigma = sd.sigma;
+    return a;
+}
+
+// One AA time step (step k of the run) of every active slot.
+template <int PREC>
+__global__ void __launch_bounds__(BLOCK) k_aa_batched(const SlotDesc *slots, const Tile *tiles, const uint32_t *hdr,
+                                                       int32_t k)
+{
+    const uint32_t nt = hdr[0];
+    for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+        const Tile tl = tiles[tile];
+        const SlotDesc sd = slots[tl.slot];
+        const KArgs a = slot_args(sd);
+        const uint32_t n = tl.node0 + threadIdx.x;
+        if (n < sd.n_nodes) {
+            if ((sd.t0 + k) & 1)
+                update_node<A_INDIRECT, L_SOA, PREC, K_AA_ODD, 1>(a, n);
+            else
+                update_node<A_INDIRECT, L_SOA, PREC, K_AA_EVEN, 1>(a, n);
+        }
+    }
+}
+
+// Per-tile FP64 moment partials of the state after `steps` steps.
+template <int PREC>
+__global__ void __launch_bounds__(BLOCK) k_seg_partials(const SlotDesc *slots, const Tile *tiles, const uint32_t *hdr,
+                                                         double *partials, int32_t steps)
+{
+    const uint32_t nt = hdr[0];
+    for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+        const Tile tl = tiles[tile];
+        const SlotDesc sd = slots[tl.slot];
+        const KArgs a = slot_args(sd);
+        const uint32_t n = tl.node0 + threadIdx.x;
+        double m[4] = {0.0, 0.0, 0.0, 0.0};
+        if (n < sd.n_nodes) {
+            if ((sd.t0 + steps) & 1)
+                node_moments<A_INDIRECT, L_SOA, PREC, R_AAODD>(a, n, m);
+            else
+                node_moments<A_INDIRECT, L_SOA, PREC, R_LOCAL>(a, n, m);
+        }
+        block_sum4(m, partials + 4 * (int64_t)tile);
+    }
+}
+
+// One workgroup per slot: the slot's partials in tile order (as k_reduce_final).
+__global__ void __launch_bounds__(BLOCK) k_seg_final(const SlotDesc *slots, const double *partials, double *moments)
+{
+    const SlotDesc sd = slots[blockIdx.x];
+    if (!sd.active) return;
+    double m[4] = {0.0, 0.0, 0.0, 0.0};
+    for (uint32_t b = threadIdx.x; b < sd.n_tiles; b += BLOCK) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) m[q] += partials[4 * ((int64_t)sd.tile_begin + b) + q];
+    }
+    block_sum4(m, moments + 4 * (int64_t)blockIdx.x);
+}
+
+} // namespace lbm
+
+struct lbm_batch {
+    int32_t max_slots = 0;
+    int64_t max_tiles = 0;
+    int32_t precision = LBM_F32;
+    // workspace regions (device)
+    uint32_t *d_hdr = nullptr;
+    SlotDesc *d_slots = nullptr;
+    Tile *d_tiles = nullptr;
+    double *d_partials = nullptr;
+    double *d_moments = nullptr;
+    // host mirror
+    std::vector<SlotDesc> slots;
+    std::vector<lbm_grid *> grids;
+    std::vector<Tile> tiles;
+    bool tiles_dirty = true;
+    uint32_t hdr_host[64] = {0};
+    uint32_t grid_blocks = 0;
+    // captured run
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int32_t graph_k = -1;
+    double *graph_out = nullptr;
+};
+
+namespace {
+
+constexpr int64_t rup(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+struct WsLayout {
+    int64_t hdr, slots, tiles, partials, moments, total;
+};
+
+WsLayout layout_of(int32_t max_slots, int64_t max_tiles)
+{
+    WsLayout w;
+    w.hdr = 0;
+    w.slots = 256;
+    w.tiles = w.slots + rup((int64_t)max_slots * (int64_t)sizeof(SlotDesc), 256);
+    w.partials = w.tiles + rup(max_tiles * (int64_t)sizeof(Tile), 256);
+    w.moments = w.partials + rup(max_tiles * 32, 256);
+    w.total = w.moments + rup((int64_t)max_slots * 32, 256);
+    return w;
+}
+
+void launch_batch_body(lbm_batch *b, int32_t k_steps, double *h_out, hipStream_t s)
+{
+    for (int32_t k = 0; k < k_steps; ++k) {
+        if (b->precision == LBM_F64)
+            hipLaunchKernelGGL(k_aa_batched<P_F64>, dim3(b->grid_blocks), dim3(BLOCK), 0, s, b->d_slots, b->d_tiles,
+                               b->d_hdr, k);
+        else if (b->precision == LBM_F32)
+            hipLaunchKernelGGL(k_aa_batched<P_F32>, dim3(b->grid_blocks), dim3(BLOCK), 0, s, b->d_slots, b->d_tiles,
+                               b->d_hdr, k);
+        else
+            hipLaunchKernelGGL(k_aa_batched<P_F16S>, dim3(b->grid_blocks), dim3(BLOCK), 0, s, b->d_slots, b->d_tiles,
+                               b->d_hdr, k);
+    }
+    if (b->precision == LBM_F64)
+        hipLaunchKernelGGL(k_seg_partials<P_F64>, dim3(b->grid_blocks), dim3(BLOCK), 0, s, b->d_slots, b->d_tiles,
+                           b->d_hdr, b->d_partials, k_steps);
+    else if (b->precision == LBM_F32)
+        hipLaunchKernelGGL(k_seg_partials<P_F32>, dim3(b->grid_blocks), dim3(BLOCK), 0, s, b->d_slots, b->d_tiles,
+                           b->d_hdr, b->d_partials, k_steps);
+    else
+        hipLaunchKernelGGL(k_seg_partials<P_F16S>, dim3(b->grid_blocks), dim3(BLOCK), 0, s, b->d_slots, b->d_tiles,
+                           b->d_hdr, b->d_partials, k_steps);
+    hipLaunchKernelGGL(k_seg_final, dim3((uint32_t)b->max_slots), dim3(BLOCK), 0, s, b->d_slots, b->d_partials,
+                       b->d_moments);
+    if (h_out)
+        (void)hipMemcpyAsync(h_out, b->d_moments, (size_t)b->max_slots * 4 * sizeof(double), hipMemcpyDeviceToHost, s);
+}
+
+void drop_graph(lbm_batch *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_k = -1;
+    b->graph_out = nullptr;
+}
+
+} // namespace
+
+extern "C" {
+
+int lbm_batch_workspace_bytes(int32_t max_slots, int64_t max_tiles, int64_t *bytes)
+{
+    if (max_slots <= 0 || max_tiles <= 0 || !bytes) return fail(LBM_E_ARG, "max_slots and max_tiles must be positive");
+    *bytes = layout_of(max_slots, max_tiles).total;
+    return LBM_OK;
+}
+
+int lbm_batch_create(int32_t max_slots, int64_t max_tiles, int32_t precision, void *d_workspace, lbm_batch **out)
+{
+    if (max_slots <= 0 || max_tiles <= 0 || max_tiles >= ((int64_t)1 << 31) || !d_workspace || !out)
+        return fail(LBM_E_ARG, "bad batch arguments");
+    if (precision < LBM_F64 || precision > LBM_F16S) return fail(LBM_E_ARG, "unknown precision");
+    int dev = 0, cus = 0;
+    int rc = hip_check(hipGetDevice(&dev), "lbm_batch_create");
+    if (rc) return rc;
+    rc = hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "lbm_batch_create");
+    if (rc) return rc;
+    lbm_batch *b = new lbm_batch();
+    b->max_slots = max_slots;
+    b->max_tiles = max_tiles;
+    b->precision = precision;
+    const WsLayout w = layout_of(max_slots, max_tiles);
+    char *ws = static_cast<char *>(d_workspace);
+    b->d_hdr = reinterpret_cast<uint32_t *>(ws + w.hdr);
+    b->d_slots = reinterpret_cast<SlotDesc *>(ws + w.slots);
+    b->d_tiles = reinterpret_cast<Tile *>(ws + w.tiles);
+    b->d_partials = reinterpret_cast<double *>(ws + w.partials);
+    b->d_moments = reinterpret_cast<double *>(ws + w.moments);
+    b->slots.assign(max_slots, SlotDesc{});
+    b->grids.assign(max_slots, nullptr);
+    b->grid_blocks = (uint32_t)(cus > 0 ? cus : 256) * 8;
+    rc = hip_check(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "lbm_batch_create (capture stream)");
+    if (rc) {
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+int lbm_batch_destroy(lbm_batch *b)
+{
+    if (!b) return LBM_OK;
+    drop_graph(b);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+    return LBM_OK;
+}
+
+int lbm_batch_add(lbm_batch *b, lbm_grid *g, int32_t *slot_out)
+{
+    if (!b || !g || !slot_out) return fail(LBM_E_ARG, "null argument");
+    if (g->d.addressing != LBM_INDIRECT || g->d.layout != LBM_SOA || g->scheme != LBM_AA)
+        return fail(LBM_E_UNSUPPORTED, "batched lattices are indirect SoA grids bound to the AA pattern");
+    if (g->d.precision != b->precision) return fail(LBM_E_ARG, "grid precision differs from the batch's");
+    if (g->n_nodes <= 0) return fail(LBM_E_STATE, "grid has no fluid nodes");
+    const int64_t need = (g->n_nodes + BLOCK - 1) / BLOCK;
+    int64_t used = 0;
+    int32_t free_slot = -1;
+    for (int32_t s = 0; s < b->max_slots; ++s) {
+        if (b->slots[s].active) {
+            used += b->slots[s].n_tiles;
+            if (b->grids[s] == g) return fail(LBM_E_STATE, "grid already in the batch (slot %d)", s);
+        } else if (free_slot < 0) {
+            free_slot = s;
+        }
+    }
+    if (free_slot < 0) return fail(LBM_E_STATE, "no free slot");
+    if (used + need > b->max_tiles) return fail(LBM_E_STATE, "tile list full (%lld + %lld > %lld)", (long long)used,
+                                                (long long)need, (long long)b->max_tiles);
+    SlotDesc sd;
+    std::memset(&sd, 0, sizeof sd);
+    const KArgs a = base_args(g);
+    sd.pdf = g->pdf[0];
+    sd.idx = g->idx;
+    sd.pitch = a.pitch;
+    sd.idx_pitch = a.idx_pitch;
+    sd.omega = a.omega;
+    sd.gx = a.gx;
+    sd.gy = a.gy;
+    sd.gz = a.gz;
+    sd.sigma = a.sigma;
+    sd.n_nodes = (uint32_t)g->n_nodes;
+    sd.n_tiles = (uint32_t)need;
+    sd.active = 1;
+    b->slots[free_slot] = sd;
+    b->grids[free_slot] = g;
+    b->tiles_dirty = true;
+    *slot_out = free_slot;
+    return LBM_OK;
+}
+
+int lbm_batch_remove(lbm_batch *b, int32_t slot)
+{
+    if (!b || slot < 0 || slot >= b->max_slots) return fail(LBM_E_ARG, "bad slot");
+    if (!b->slots[slot].active) return fail(LBM_E_STATE, "slot %d is empty", slot);
+    std::memset(&b->slots[slot], 0, sizeof(SlotDesc));
+    b->grids[slot] = nullptr;
+    b->tiles_dirty = true;
+    return LBM_OK;
+}
+
+int lbm_batch_run(lbm_batch *b, int32_t k_steps, double *h_moments, int32_t use_graph, void *stream)
+{
+    if (!b || k_steps <= 0) return fail(LBM_E_ARG, "k_steps must be positive");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // refresh the per-run fields of the slot table (parity base) and, after
+    // admissions or retirements, the compacted tile list
+    if (b->tiles_dirty) {
+        b->tiles.clear();
+        for (int32_t sl = 0; sl < b->max_slots; ++sl) {
+            SlotDesc &sd = b->slots[sl];
+            if (!sd.active) continue;
+            sd.tile_begin = (uint32_t)b->tiles.size();
+            for (uint32_t t = 0; t < sd.n_tiles; ++t) b->tiles.push_back(Tile{(uint32_t)sl, t * (uint32_t)BLOCK});
+        }
+        b->hdr_host[0] = (uint32_t)b->tiles.size();
+        if (!b->tiles.empty()) {
+            int rc = hip_check(hipMemcpyAsync(b->d_tiles, b->tiles.data(), b->tiles.size() * sizeof(Tile),
+                                              hipMemcpyHostToDevice, s), "lbm_batch_run (tiles)");
+            if (rc) return rc;
+        }
+        int rc = hip_check(hipMemcpyAsync(b->d_hdr, b->hdr_host, sizeof b->hdr_host, hipMemcpyHostToDevice, s),
+                           "lbm_batch_run (header)");
+        if (rc) return rc;
+        b->tiles_dirty = false;
+    }
+    for (int32_t sl = 0; sl < b->max_slots; ++sl)
+        if (b->slots[sl].active) b->slots[sl].t0 = (int32_t)b->grids[sl]->t;
+    int rc = hip_check(hipMemcpyAsync(b->d_slots, b->slots.data(), b->slots.size() * sizeof(SlotDesc),
+                                      hipMemcpyHostToDevice, s), "lbm_batch_run (slots)");
+    if (rc) return rc;
+    if (use_graph) {
+        if (!b->exec || b->graph_k != k_steps || b->graph_out != h_moments) {
+            drop_graph(b);
+            rc = hip_check(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed), "lbm_batch_run (capture)");
+            if (rc) return rc;
+            launch_batch_body(b, k_steps, h_moments, b->cap);
+            rc = hip_check(hipStreamEndCapture(b->cap, &b->graph), "lbm_batch_run (end capture)");
+            if (rc) return rc;
+            rc = hip_check(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "lbm_batch_run (instantiate)");
+            if (rc) {
+                drop_graph(b);
+                return rc;
+            }
+            b->graph_k = k_steps;
+            b->graph_out = h_moments;
+        }
+        rc = hip_check(hipGraphLaunch(b->exec, s), "lbm_batch_run (graph launch)");
+        if (rc) return rc;
+    } else {
+        launch_batch_body(b, k_steps, h_moments, s);
+        rc = hip_check(hipGetLastError(), "lbm_batch_run (launch)");
+        if (rc) return rc;
+    }
+    for (int32_t sl = 0; sl < b->max_slots; ++sl)
+        if (b->slots[sl].active) b->grids[sl]->t += k_steps;
+    return LBM_OK;
+}
+
+int lbm_batch_moments(lbm_batch *b, double *d_out, void *stream)
+{
+    if (!b || !d_out) return fail(LBM_E_ARG, "null argument");
+    return hip_check(hipMemcpyAsync(d_out, b->d_moments, (size_t)b->max_slots * 4 * sizeof(double),
+                                    hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)),
+                     "lbm_batch_moments");
+}
+
+} // extern "C"

@@ -1,0 +1,43 @@
+// grid_internal.hpp -- host-side grid state shared by the C ABI units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/lbm355.h"
+#include "kernels.hpp"
+
+struct lbm_grid {
+    lbm_grid_desc d;
+    int64_t n_cells = 0;
+    int64_t n_nodes = 0; // fluid nodes (direct: cells between the walls)
+    int64_t n_ghost = 0;
+    int idx_phase = 0;   // indirect: 1 after the cellmap pass, 2 after the fill pass
+    // bound state
+    int scheme = -1;
+    void *pdf[2] = {nullptr, nullptr};
+    int cur = 0;         // pdf[cur] holds the state of TS / OS
+    const int32_t *idx = nullptr;
+    const int32_t *aux = nullptr;
+    double *scratch = nullptr;
+    int64_t pitch = 0;
+    int64_t t = 0;
+    int remap = 0;
+    int64_t pitch_pad = 0; // extra SoA elements between direction arrays
+    int64_t wg_lds = -1;   // dynamic LDS reserved per update workgroup (-1: per-precision default)
+    int row_stage = 1;     // allow the row-staged direct SoA kernels
+};
+
+namespace lbm_host {
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int hip_check(hipError_t e, const char *where);
+lbm::KArgs base_args(const lbm_grid *g);
+uint32_t node_blocks(const lbm_grid *g);
+int64_t idx_pitch_of(const lbm_grid *g);
+const lbm::PrecTable &table(int precision);
+int state_rmap(const lbm_grid *g);
+
+} // namespace lbm_host

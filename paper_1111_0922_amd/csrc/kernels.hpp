@@ -444,24 +444,15 @@ __device__ __forceinline__ void update_direct_staged(const KArgs &a)
 }
 
 // ------------------------------------------------------------------ update kernel
+// One node's update through the generic maps (any addressing and layout).
 template <int ADDR, int LAY, int PREC, int KIND, int COLL>
-__global__ void __launch_bounds__(BLOCK) k_update(KArgs a)
+__device__ __forceinline__ void update_node(const KArgs &a, uint32_t n)
 {
     using S = Store<PREC>;
     using st = typename S::st;
     using ct = typename S::ct;
     constexpr int R = rmap_of(KIND);
     constexpr int W = wmap_of(KIND);
-    // kernels whose maps never shift along x need no staging
-    constexpr bool shifts = !(R == R_LOCAL && (W == W_LOCAL || W == W_AAEVEN));
-    if constexpr (ADDR == A_DIRECT && LAY == L_SOA && shifts) {
-        if (a.row_staged) {
-            update_direct_staged<PREC, KIND, COLL>(a);
-            return;
-        }
-    }
-    const uint32_t n = logical_block(a.remap) * BLOCK + threadIdx.x;
-    if (n >= a.n_nodes) return;
     Node<ADDR, need_r(R) | need_w(W)> nd;
     nd.init(a, n);
     const st *src = static_cast<const st *>(a.src);
@@ -491,6 +482,24 @@ __global__ void __launch_bounds__(BLOCK) k_update(KArgs a)
         write_slot<W>(nd, i, j, c);
         pdf_store(dst + elem<LAY>(j, c, a.pitch), S::save(v[i]));
     }
+}
+
+template <int ADDR, int LAY, int PREC, int KIND, int COLL>
+__global__ void __launch_bounds__(BLOCK) k_update(KArgs a)
+{
+    constexpr int R = rmap_of(KIND);
+    constexpr int W = wmap_of(KIND);
+    // kernels whose maps never shift along x need no staging
+    constexpr bool shifts = !(R == R_LOCAL && (W == W_LOCAL || W == W_AAEVEN));
+    if constexpr (ADDR == A_DIRECT && LAY == L_SOA && shifts) {
+        if (a.row_staged) {
+            update_direct_staged<PREC, KIND, COLL>(a);
+            return;
+        }
+    }
+    const uint32_t n = logical_block(a.remap) * BLOCK + threadIdx.x;
+    if (n >= a.n_nodes) return;
+    update_node<ADDR, LAY, PREC, KIND, COLL>(a, n);
 }
 
 // ------------------------------------------------------------------ canonical transfer
@@ -590,34 +599,40 @@ __device__ __forceinline__ void block_sum4(double (&m)[4], double *out)
             out[k] = s;
         }
     }
+    __syncthreads(); // part[] may be reused by a following call in the same workgroup
+}
+
+// FP64 moments (M, Jx, Jy, Jz) of one node's canonical PDFs, read through map R.
+template <int ADDR, int LAY, int PREC, int R>
+__device__ __forceinline__ void node_moments(const KArgs &a, uint32_t n, double (&m)[4])
+{
+    using S = Store<PREC>;
+    using st = typename S::st;
+    Node<ADDR, need_r(R)> nd;
+    nd.init(a, n);
+    const st *src = static_cast<const st *>(a.src);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        int j;
+        int64_t c;
+        read_slot<R>(nd, i, j, c);
+        const double f = S::to_canon(src[elem<LAY>(j, c, a.pitch)], i, a.sigma);
+        m[0] += f;
+        if (cx(i) > 0) m[1] += f;
+        if (cx(i) < 0) m[1] -= f;
+        if (cy(i) > 0) m[2] += f;
+        if (cy(i) < 0) m[2] -= f;
+        if (cz(i) > 0) m[3] += f;
+        if (cz(i) < 0) m[3] -= f;
+    }
 }
 
 template <int ADDR, int LAY, int PREC, int R>
 __global__ void __launch_bounds__(BLOCK) k_reduce(KArgs a)
 {
-    using S = Store<PREC>;
-    using st = typename S::st;
     const uint32_t n = blockIdx.x * BLOCK + threadIdx.x;
     double m[4] = {0.0, 0.0, 0.0, 0.0};
-    if (n < a.n_nodes) {
-        Node<ADDR, need_r(R)> nd;
-        nd.init(a, n);
-        const st *src = static_cast<const st *>(a.src);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            int j;
-            int64_t c;
-            read_slot<R>(nd, i, j, c);
-            const double f = S::to_canon(src[elem<LAY>(j, c, a.pitch)], i, a.sigma);
-            m[0] += f;
-            if (cx(i) > 0) m[1] += f;
-            if (cx(i) < 0) m[1] -= f;
-            if (cy(i) > 0) m[2] += f;
-            if (cy(i) < 0) m[2] -= f;
-            if (cz(i) > 0) m[3] += f;
-            if (cz(i) < 0) m[3] -= f;
-        }
-    }
+    if (n < a.n_nodes) node_moments<ADDR, LAY, PREC, R>(a, n, m);
     block_sum4(m, a.partials + 4 * (int64_t)blockIdx.x);
 }
 

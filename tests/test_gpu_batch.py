@@ -1,0 +1,122 @@
+"""Batched AA executor: each lattice evolves to the same bits alone and in any mix."""
+import numpy as np
+import pytest
+import torch
+
+import lbm_inputs
+import oracle
+from lbm_cases import from_device, rel_err, to_device
+
+pytestmark = pytest.mark.gpu
+
+GEOMS = [((20, 20, 20), 3, 0.55, 11), ((28, 24, 31), 4, 0.45, 12), ((36, 36, 36), 5, 0.7, 13),
+         ((17, 9, 13), 2, 0.6, 14)]
+
+
+def _grid(shape, r, phi, seed, precision, omega=1.0, g=1e-5):
+    import paper_1111_0922_amd as P
+    solid = lbm_inputs.sphere_pack(shape, r, phi, seed)[0]
+    nz, ny, nx = solid.shape
+    grid = P.Grid(nx, ny, nz, addressing="indirect", precision=precision, omega=omega, g=(g, 0, 0))
+    grid.build_idx(torch.from_numpy(solid).cuda())
+    grid.bind("aa")
+    rho_u = lbm_inputs.rho_u_field(solid.shape, lbm_inputs.velocity_noise(solid.shape, 1e-3, seed=seed))
+    grid.init_equilibrium(to_device(rho_u.reshape(4, -1)[:, solid.reshape(-1) == 0]))
+    return grid, solid
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64", "f16s"])
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_alone_equals_mixed_bitwise(precision, use_graph):
+    import paper_1111_0922_amd as P
+    K = 20
+    # alone: lbm_step + lbm_reduce_moments, one lattice at a time (one starts at odd parity)
+    alone = []
+    for i, gm in enumerate(GEOMS):
+        grid, _ = _grid(*gm, precision)
+        if i == 1:
+            grid.step(1)
+        for _ in range(2):
+            grid.step(K)
+        alone.append((from_device(grid.get_pdfs()), from_device(grid.moments())))
+        del grid
+    # mixed: all in one batch, two runs of K steps
+    batch = P.Batch(8, 4096, precision, use_graph=use_graph)
+    grids = []
+    for i, gm in enumerate(GEOMS):
+        grid, _ = _grid(*gm, precision)
+        if i == 1:
+            grid.step(1)
+        grids.append((batch.add(grid), grid))
+    for _ in range(2):
+        m = batch.run(K)
+    for (slot, grid), (f_alone, m_alone) in zip(grids, alone):
+        assert np.array_equal(from_device(grid.get_pdfs()).view(np.int64), f_alone.view(np.int64)), slot
+        assert np.array_equal(m[slot].view(np.int64), m_alone.view(np.int64)), slot
+
+
+def test_slot_churn_reuses_graph_and_stays_exact():
+    import paper_1111_0922_amd as P
+    K = 10
+    batch = P.Batch(4, 2048, "f32", use_graph=True)
+    g0, _ = _grid(*GEOMS[0], "f32")
+    g1, _ = _grid(*GEOMS[1], "f32")
+    s0, s1 = batch.add(g0), batch.add(g1)
+    batch.run(K)
+    batch.remove(s1)                      # g1 leaves after K steps
+    g2, _ = _grid(*GEOMS[2], "f32")
+    s2 = batch.add(g2)                    # g2 joins at t = 0 while g0 is at t = K
+    assert s2 == s1                       # freed slot is reused
+    m = batch.run(K)
+    assert g0.t == 2 * K and g1.t == K and g2.t == K
+    # reference evolutions, one lattice each
+    for grid, gm, steps in ((g0, GEOMS[0], 2 * K), (g1, GEOMS[1], K), (g2, GEOMS[2], K)):
+        ref, _ = _grid(*gm, "f32")
+        ref.step(steps)
+        assert np.array_equal(from_device(grid.get_pdfs()).view(np.int64), from_device(ref.get_pdfs()).view(np.int64))
+    ref2, _ = _grid(*GEOMS[2], "f32")
+    ref2.step(K)
+    assert np.array_equal(m[s2], from_device(ref2.moments()))
+
+
+def test_batch_fp64_matches_oracle():
+    import paper_1111_0922_amd as P
+    (shape, r, phi, seed) = GEOMS[3]
+    grid, solid = _grid(shape, r, phi, seed, "f64", omega=1.6)
+    f0 = from_device(grid.get_pdfs())
+    batch = P.Batch(2, 64, "f64", use_graph=True)
+    slot = batch.add(grid)
+    m = batch.run(12)
+    dense = np.zeros((19,) + solid.shape)
+    dense.reshape(19, -1)[:, solid.reshape(-1) == 0] = f0
+    want = oracle.run_ts(dense, solid, 12, 1.6, (1e-5, 0, 0))
+    assert rel_err(from_device(grid.get_pdfs()), oracle.fluid_view(want, solid)) <= 1e-12
+    mo = oracle.moments(want, solid)
+    assert abs(m[slot][0] - mo[0]) / mo[0] <= 1e-13
+
+
+def test_batch_rejects_unsupported_grids():
+    import paper_1111_0922_amd as P
+    batch = P.Batch(2, 64, "f32")
+    direct = P.Grid(8, 8, 8, precision="f32", wall_z=True)
+    direct.bind("aa")
+    with pytest.raises(P.LbmError):
+        batch.add(direct)
+    g64, _ = _grid(*GEOMS[0], "f64")
+    with pytest.raises(P.LbmError):
+        batch.add(g64)
+
+
+def test_serving_end_to_end_small():
+    """A few real requests through the scheduler and the GPU executor (steps capped)."""
+    from paper_1111_0922_amd.serve import GpuExecutor, Request, Scheduler
+    ex = GpuExecutor(max_slots=4, max_tiles=1 << 16, precision="f32")
+    sch = Scheduler(ex, hbm_budget=8 << 30, max_slots=4, k_steps=100, tol=1e-6, max_steps=600, prep_threads=2)
+    reqs = [Request(rid=i, seed=7000 + i, arrival=0.02 * i) for i in range(5)]
+    out = sch.serve(reqs)
+    rep = sch.report(out)
+    assert rep["requests"] == 5
+    for r in out:
+        assert r.steps > 0 and r.finished is not None
+        assert np.isfinite(r.permeability) and r.permeability > 0
+    assert sch.peak_used <= 8 << 30
