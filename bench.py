@@ -140,6 +140,80 @@ def cpu_baseline(budget_s=12.0):
             "sample": f"256^3 channel, FP64 two-step (pull), {steps} steps, {threads} threads, {dt:.1f} s"}
 
 
+def serving_bench(log, n_requests, seed_base=100000):
+    """Config 5: porous permeability solves of uneven sizes, FP32 AA indirect, continuous batching."""
+    from paper_1111_0922_amd.serve import GpuExecutor, Request, Scheduler, poisson_arrivals
+
+    def run(rate, seed0, n):
+        ex = GpuExecutor(max_slots=64, max_tiles=1 << 20, precision="f32", omega=1.0, g=1e-6)
+        sch = Scheduler(ex, hbm_budget=64 << 30, max_slots=64, k_steps=100, tol=1e-6, max_steps=20000,
+                        omega=1.0, g=1e-6, prep_threads=8)
+        arr = poisson_arrivals(n, rate, seed=seed0)
+        reqs = [Request(rid=i, seed=seed0 + i, arrival=float(a)) for i, a in enumerate(arr)]
+        out = sch.serve(reqs)
+        rep = sch.report(out, warmup=min(4, n // 8))
+        rep["rate_per_s"] = rate
+        rep["steps_mean"] = float(np.mean([r.steps for r in out]))
+        return rep
+
+    log(f"[bench] serving: saturated ({n_requests} requests at t=0)")
+    sat = run(float("inf"), seed_base, n_requests)
+    out = {"saturated": sat}
+    for frac in (0.5, 0.9):
+        lam = frac * sat["solves_per_s"]
+        log(f"[bench] serving: Poisson rate {lam:.2f}/s ({frac} x saturated)")
+        out[f"poisson_{frac}"] = run(lam, seed_base + 1000 * int(frac * 10), n_requests)
+    out["requests_per_run"] = n_requests
+    out["budget_bytes"] = 64 << 30
+    out["max_slots"] = 64
+    return out
+
+
+def precision_study(log, n=384, radius=8, porosity=0.6, seed=4, tol=1e-7, max_steps=60000, k=100):
+    """Config 4: AA indirect to steady state in FP64, FP32 and FP16-shifted storage; permeability errors."""
+    import torch
+    import lbm_inputs
+    import paper_1111_0922_amd as P
+    mask, spheres = lbm_inputs.sphere_pack(n, radius, porosity, seed)
+    mt = torch.from_numpy(mask).cuda()
+    phi = float(1 - mask.mean())
+    g = 1e-6
+    res = {"lattice": f"{n}^3", "radius": radius, "porosity": phi, "spheres": spheres, "tol": tol}
+    for prec, sigma in (("f64", 1.0), ("f32", 1.0), ("f32s", 1.0), ("f16s", 1.0), ("f16s", 1024.0)):
+        grid = P.Grid(n, n, n, addressing="indirect", precision=prec, omega=1.0, g=(g, 0, 0), f16_scale=sigma)
+        nf = grid.build_idx(mt)
+        grid.bind("aa")
+        grid.init_equilibrium()
+        m0 = grid.moments().cpu().numpy()
+        prev, steps = None, 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while steps < max_steps:
+            grid.step(k)
+            steps += k
+            m = grid.moments().cpu().numpy()
+            U = (m[1] + 0.5 * m[0] * g) / m[0]
+            if prev is not None and U != 0 and abs(U - prev) / abs(U) < tol:
+                break
+            if steps % 5000 == 0:
+                log(f"[precision] {prec} sigma {sigma}: step {steps}, U {U:.9e}, "
+                    f"change {abs(U - prev) / abs(U) if prev else float('nan'):.2e}")
+            prev = U
+        dt = time.perf_counter() - t0
+        nu = (1.0 / 1.0 - 0.5) / 3.0
+        key = prec if prec not in ("f16s",) else f"f16s_sigma{int(sigma)}"
+        res[key] = {"steps": steps, "U": U, "permeability": nu * phi * U / g, "MFLUP/s": nf * steps / dt / 1e6,
+                    "mass_drift": float(abs(m[0] - m0[0]) / m0[0]), "converged": steps < max_steps}
+        log(f"[precision] {key}: {steps} steps, k = {res[key]['permeability']:.6g}, {res[key]['MFLUP/s']:.0f} MFLUP/s")
+        del grid
+        torch.cuda.empty_cache()
+    k64 = res["f64"]["permeability"]
+    for key in list(res):
+        if isinstance(res[key], dict) and "permeability" in res[key]:
+            res[key]["rel_err_vs_f64"] = abs(res[key]["permeability"] - k64) / abs(k64)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +221,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--only-main", action="store_true", help="headline AA run only (for profiling)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--serving-requests", type=int, default=48, help="requests per serving run (0 = skip)")
+    ap.add_argument("--precision-study", action="store_true",
+                    help="only the 384^3 steady-state precision study (FP64 / FP32 / FP16-shifted)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the copy kernel on 1 GiB, 3 times (counter calibration)")
     args = ap.parse_args()
@@ -171,8 +248,12 @@ def main():
                           "launches": 3}), flush=True)
         return
 
-    n = 256
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+    if args.precision_study:
+        print(json.dumps({"precision_study": precision_study(log)}), flush=True)
+        return
+
+    n = 256
     log(f"[bench] AA SoA FP64 256^3 channel: warmup {args.warmup}, steps {args.steps}")
     grid = channel_grid(P, torch, n, "aa", "soa")
     nf = grid.n_nodes
@@ -224,6 +305,18 @@ def main():
                 del g
                 torch.cuda.empty_cache()
                 log(f"[bench]   {scheme}/{layout}: {mf:.0f} MFLUP/s")
+        for prec in ("f32", "f32s", "f16s"):
+            g = P.Grid(n, n, n, precision=prec, wall_z=True, omega=1.6, g=(1e-6, 0.0, 0.0), f16_scale=1024.0)
+            g.bind("aa")
+            g.init_equilibrium()
+            dts = time_steps(torch, g, 200, 10)
+            mf = g.n_nodes * 200 / dts / 1e6
+            bl = P.model_bytes("aa", "direct", prec)
+            table[f"aa/soa/{prec}"] = {"MFLUP/s": round(mf, 1), "GB/s": round(mf * bl / 1e3, 1), "bytes_per_lup": bl,
+                                       "frac_hbm": round(mf * bl / 1e3 / HBM_PEAK_GBS, 4)}
+            del g
+            torch.cuda.empty_cache()
+            log(f"[bench]   aa/soa/{prec}: {mf:.0f} MFLUP/s")
         result["schemes"] = table
 
         log("[bench] 512^3 sphere pack (r 8, porosity 0.40), indirect, FP64")
@@ -248,6 +341,10 @@ def main():
             torch.cuda.empty_cache()
             log(f"[bench]   {scheme}: {mf:.0f} MFLUP/s")
         result["porous512"] = porous
+        del mask_t
+        torch.cuda.empty_cache()
+        if args.serving_requests > 0:
+            result["serving"] = serving_bench(log, args.serving_requests)
 
     if not args.no_cpu and not args.only_main:
         log("[bench] CPU oracle baseline")

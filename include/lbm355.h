@@ -12,8 +12,8 @@
  * each on a directly addressed full grid and on an indirectly addressed
  * sparse grid of fluid nodes with an 18-entry neighbour index array (Sec. 1),
  * in SoA and AoS layouts (Sec. 1).  The collision is BGK with the Guo body
- * force; PDFs are stored in FP64, FP32, or FP16 as shifted deviations
- * (f_i - w_i) * sigma with FP32 arithmetic.
+ * force; PDFs are stored in FP64, FP32, or as shifted deviations
+ * (f_i - w_i) * sigma in FP16 or FP32 (FP32 arithmetic).
  *
  * Conventions shared by every call:
  *   - All functions return an int status (LBM_OK or a negative LBM_E_*);
@@ -62,7 +62,7 @@ enum {
 /* ---------------------------------------------------------------- enums */
 enum lbm_addressing { LBM_DIRECT = 0, LBM_INDIRECT = 1 };
 enum lbm_layout { LBM_SOA = 0, LBM_AOS = 1 };
-enum lbm_precision { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2 };
+enum lbm_precision { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_F32S = 3 };
 enum lbm_scheme {
     LBM_TS = 0,      /* two-step two-grid, Sec. 2                        */
     LBM_OS_PUSH = 1, /* one-step two-grid, push, Sec. 3                   */
@@ -92,7 +92,7 @@ typedef struct {
                             solid cells the esoteric twist stores PDFs in.      */
     double omega;        /* BGK relaxation rate, 0 < omega < 2                   */
     double g[3];         /* body-force acceleration (force density rho * g)      */
-    double f16_scale;    /* sigma of the FP16 shifted form (> 0); else ignored    */
+    double f16_scale;    /* sigma of the shifted forms F16S, F32S (> 0); else ignored */
 } lbm_grid_desc;
 
 typedef struct {
@@ -147,7 +147,8 @@ int lbm_set_params(lbm_grid *g, double omega, const double g_acc[3]);
  *     reserved by every update workgroup on top of what the kernel uses.  It
  *     only limits how many workgroups a CU (160 KB of LDS) keeps resident,
  *     which bounds the number of concurrent memory streams.  The default is
- *     36864 for FP64, 40960 for FP32 and 0 for FP16 storage.
+ *     36864 for FP64, 40960 for FP32 and 0 for FP16 storage on direct SoA
+ *     grids, and 0 for indirect or AoS grids.
  *   LBM_OPT_ROW_STAGE (0/1, default 1): on a direct SoA grid whose nx is a
  *     power of two no larger than 256, every workgroup holds whole x-rows and
  *     moves the x-shifted PDFs through LDS, so that all global accesses are
@@ -283,7 +284,7 @@ int lbm_stream_copy(const void *d_src, void *d_dst, int64_t bytes, void *stream)
  * model of Tables 1-6 and 8.  model = 0: the paper's counts (write-allocate
  * included, 8-byte PDFs, 4-byte IDX entries, precision ignored).  model = 1:
  * GPU algorithmic bytes of this library (no write-allocate, PDF size of
- * `precision`, this library's IDX use).  Returns < 0 for combinations the
+ * `precision` (8, 4, 2, 4 bytes), this library's IDX use).  Returns < 0 for combinations the
  * model does not cover. */
 double lbm_model_bytes(int32_t scheme, int32_t addressing, int32_t precision, int32_t model);
 

@@ -92,7 +92,7 @@ def _vec3(v):
     return (ctypes.c_double * 3)(*[float(x) for x in v])
 
 
-QUANT = {None: 0, "f64": 0, "f32": 1, "f16s": 2}
+QUANT = {None: 0, "f64": 0, "f32": 1, "f16s": 2, "f32s": 3}
 COLLIDER = {"identity": 0, "bgk": 1}
 
 

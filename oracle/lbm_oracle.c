@@ -29,7 +29,8 @@
  *
  * Optional storage rounding ("quant") mimics the reduced-precision storage
  * forms: 1 = each stored value rounded to binary32; 2 = the shifted deviation
- * (f_i - w_i)*sigma rounded to binary16 (IEEE 754 round-to-nearest-even).
+ * (f_i - w_i)*sigma rounded to binary16; 3 = that deviation rounded to
+ * binary32 (IEEE 754 round-to-nearest-even throughout).
  * The arithmetic itself is always FP64.
  *
  * Parity pins for every function here live in tests/test_oracle.py.
@@ -163,6 +164,7 @@ static double quantize_value(double v, int i, int quant, double sigma)
 {
     if (quant == 1) return (double)(float)v;
     if (quant == 2) return WV[i] + ora_round_half((v - WV[i]) * sigma) / sigma;
+    if (quant == 3) return WV[i] + (double)(float)((v - WV[i]) * sigma) / sigma;
     return v;
 }
 

@@ -18,7 +18,7 @@ LIB_PATH = os.environ.get("LBM355_LIB") or os.path.join(HERE, "liblbm355.so")
 LBM_OK, LBM_E_ARG, LBM_E_STATE, LBM_E_HIP, LBM_E_UNSUPPORTED, LBM_E_DIVERGED = 0, -1, -2, -3, -4, -5
 DIRECT, INDIRECT = 0, 1
 SOA, AOS = 0, 1
-F64, F32, F16S = 0, 1, 2
+F64, F32, F16S, F32S = 0, 1, 2, 3
 TS, OS_PUSH, OS_PULL, AA, ET, OS_NT, CG, SWAP = range(8)
 IDENTITY, BGK = 0, 1
 OPT_XCD_REMAP = 1
@@ -30,7 +30,7 @@ SCHEMES = {"ts": TS, "os_push": OS_PUSH, "os_pull": OS_PULL, "aa": AA, "et": ET,
            "os_nt": OS_NT, "cg": CG, "swap": SWAP}
 ADDRESSING = {"direct": DIRECT, "indirect": INDIRECT}
 LAYOUTS = {"soa": SOA, "aos": AOS}
-PRECISIONS = {"f64": F64, "f32": F32, "f16s": F16S}
+PRECISIONS = {"f64": F64, "f32": F32, "f16s": F16S, "f32s": F32S}
 COLLIDERS = {"identity": IDENTITY, "bgk": BGK}
 
 

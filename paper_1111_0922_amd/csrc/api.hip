@@ -45,7 +45,7 @@ namespace {
 
 constexpr int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
-int pdf_size(int precision) { return precision == LBM_F64 ? 8 : (precision == LBM_F32 ? 4 : 2); }
+int pdf_size(int precision) { return precision == LBM_F64 ? 8 : (precision == LBM_F16S ? 2 : 4); }
 
 bool two_lattices(int scheme) { return scheme == LBM_TS || scheme == LBM_OS_PUSH || scheme == LBM_OS_PULL; }
 bool kernel_scheme(int scheme) { return scheme >= LBM_TS && scheme <= LBM_ET; }
@@ -67,7 +67,12 @@ namespace lbm_host {
 
 const PrecTable &table(int precision)
 {
-    return precision == LBM_F64 ? table_f64() : (precision == LBM_F32 ? table_f32() : table_f16s());
+    switch (precision) {
+    case LBM_F64: return table_f64();
+    case LBM_F32: return table_f32();
+    case LBM_F16S: return table_f16s();
+    default: return table_f32s();
+    }
 }
 
 int64_t idx_pitch_of(const lbm_grid *g) { return round_up(g->n_nodes > 0 ? g->n_nodes : 1, 64); }
@@ -95,11 +100,16 @@ KArgs base_args(const lbm_grid *g)
     a.dvx = make_fastdiv((uint32_t)d.nx);
     a.dvy = make_fastdiv((uint32_t)d.ny);
     a.remap = g->remap;
-    // Measured on MI355X (256^3 channel): FP64 update workgroups run best with
+    // Measured on MI355X (256^3 channel): FP64 direct SoA workgroups run best with
     // about two resident per CU for the row-staged kernels (20 KB static LDS +
     // 36 KB) and four for the others; FP32 likes 40 KB; FP16 wants no cap.
+    // Indirect and AoS kernels keep full residency: their gathers need the
+    // parallelism to hide latency.
+    const bool streaming = d.addressing == LBM_DIRECT && d.layout == LBM_SOA;
     a.lds_bytes = (uint32_t)(g->wg_lds >= 0 ? g->wg_lds
-                                           : (d.precision == LBM_F64 ? 36864 : (d.precision == LBM_F32 ? 40960 : 0)));
+                                           : (!streaming ? 0
+                                                         : (d.precision == LBM_F64 ? 36864
+                                                                                   : ((d.precision == LBM_F32 || d.precision == LBM_F32S) ? 40960 : 0))));
     // whole x-rows per workgroup: nx a power of two dividing the workgroup size
     a.row_staged = (d.addressing == LBM_DIRECT && d.layout == LBM_SOA && g->row_stage && d.nx <= BLOCK &&
                     (d.nx & (d.nx - 1)) == 0) ? 1 : 0;
@@ -107,7 +117,7 @@ KArgs base_args(const lbm_grid *g)
     a.gx = d.g[0];
     a.gy = d.g[1];
     a.gz = d.g[2];
-    a.sigma = d.precision == LBM_F16S ? d.f16_scale : 1.0;
+    a.sigma = (d.precision == LBM_F16S || d.precision == LBM_F32S) ? d.f16_scale : 1.0;
     return a;
 }
 
@@ -165,9 +175,10 @@ int lbm_create_grid(const lbm_grid_desc *desc, lbm_grid **out)
     if (nc >= (int64_t)1 << 31) return fail(LBM_E_ARG, "box of %lld cells exceeds 2^31 - 1", (long long)nc);
     if (d.addressing != LBM_DIRECT && d.addressing != LBM_INDIRECT) return fail(LBM_E_ARG, "unknown addressing");
     if (d.layout != LBM_SOA && d.layout != LBM_AOS) return fail(LBM_E_ARG, "unknown layout");
-    if (d.precision < LBM_F64 || d.precision > LBM_F16S) return fail(LBM_E_ARG, "unknown precision");
+    if (d.precision < LBM_F64 || d.precision > LBM_F32S) return fail(LBM_E_ARG, "unknown precision");
     if (!(d.omega > 0.0 && d.omega < 2.0)) return fail(LBM_E_ARG, "omega must lie in (0, 2)");
-    if (d.precision == LBM_F16S && !(d.f16_scale > 0.0)) return fail(LBM_E_ARG, "f16_scale must be > 0");
+    if ((d.precision == LBM_F16S || d.precision == LBM_F32S) && !(d.f16_scale > 0.0))
+        return fail(LBM_E_ARG, "f16_scale (sigma of the shifted forms) must be > 0");
     if (d.addressing == LBM_DIRECT && d.wall_z && d.nz < 3) return fail(LBM_E_ARG, "walls need nz >= 3");
     if (nc * Q >= ((int64_t)1 << 40)) return fail(LBM_E_ARG, "box too large");
     lbm_grid *g = new lbm_grid();
@@ -453,7 +464,7 @@ double lbm_model_bytes(int32_t scheme, int32_t addressing, int32_t precision, in
         return pdfs * 8.0 + (ind ? idxs * 4.0 : 0.0);
     }
     if (model == 1) {
-        if (precision < LBM_F64 || precision > LBM_F16S) return -1.0;
+        if (precision < LBM_F64 || precision > LBM_F32S) return -1.0;
         const double s = pdf_size(precision);
         // no write-allocate on the GPU: each PDF is loaded once and stored once per kernel
         double pdfs, idxs;

@@ -174,8 +174,11 @@ void launch_batch_body(lbm_batch *b, int32_t k_steps, double *h_out, hipStream_t
         else if (b->precision == LBM_F32)
             hipLaunchKernelGGL(k_aa_batched<P_F32>, dim3(b->grid_blocks), dim3(BLOCK), 0, s, b->d_slots, b->d_tiles,
                                b->d_hdr, k);
-        else
+        else if (b->precision == LBM_F16S)
             hipLaunchKernelGGL(k_aa_batched<P_F16S>, dim3(b->grid_blocks), dim3(BLOCK), 0, s, b->d_slots, b->d_tiles,
+                               b->d_hdr, k);
+        else
+            hipLaunchKernelGGL(k_aa_batched<P_F32S>, dim3(b->grid_blocks), dim3(BLOCK), 0, s, b->d_slots, b->d_tiles,
                                b->d_hdr, k);
     }
     if (b->precision == LBM_F64)
@@ -184,8 +187,11 @@ void launch_batch_body(lbm_batch *b, int32_t k_steps, double *h_out, hipStream_t
     else if (b->precision == LBM_F32)
         hipLaunchKernelGGL(k_seg_partials<P_F32>, dim3(b->grid_blocks), dim3(BLOCK), 0, s, b->d_slots, b->d_tiles,
                            b->d_hdr, b->d_partials, k_steps);
-    else
+    else if (b->precision == LBM_F16S)
         hipLaunchKernelGGL(k_seg_partials<P_F16S>, dim3(b->grid_blocks), dim3(BLOCK), 0, s, b->d_slots, b->d_tiles,
+                           b->d_hdr, b->d_partials, k_steps);
+    else
+        hipLaunchKernelGGL(k_seg_partials<P_F32S>, dim3(b->grid_blocks), dim3(BLOCK), 0, s, b->d_slots, b->d_tiles,
                            b->d_hdr, b->d_partials, k_steps);
     hipLaunchKernelGGL(k_seg_final, dim3((uint32_t)b->max_slots), dim3(BLOCK), 0, s, b->d_slots, b->d_partials,
                        b->d_moments);
@@ -218,7 +224,7 @@ int lbm_batch_create(int32_t max_slots, int64_t max_tiles, int32_t precision, vo
 {
     if (max_slots <= 0 || max_tiles <= 0 || max_tiles >= ((int64_t)1 << 31) || !d_workspace || !out)
         return fail(LBM_E_ARG, "bad batch arguments");
-    if (precision < LBM_F64 || precision > LBM_F16S) return fail(LBM_E_ARG, "unknown precision");
+    if (precision < LBM_F64 || precision > LBM_F32S) return fail(LBM_E_ARG, "unknown precision");
     int dev = 0, cus = 0;
     int rc = hip_check(hipGetDevice(&dev), "lbm_batch_create");
     if (rc) return rc;

@@ -387,7 +387,7 @@ __device__ __forceinline__ void update_direct_staged(const KArgs &a)
     for (int i = 0; i < Q; ++i) {
         int j, sx, sy, sz;
         read_off<R>(nd, i, j, sx, sy, sz);
-        raw[i] = pdf_load_raw<S>(src + elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch));
+        raw[i] = pdf_load_raw<true, S>(src + elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch));
     }
     ct v[Q];
 #pragma unroll
@@ -430,7 +430,7 @@ __device__ __forceinline__ void update_direct_staged(const KArgs &a)
                 continue;
             }
         }
-        if (valid) pdf_store(dst + elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch), S::save(v[i]));
+        if (valid) pdf_store<true>(dst + elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch), S::save(v[i]));
     }
     __syncthreads();
 #pragma unroll
@@ -438,7 +438,7 @@ __device__ __forceinline__ void update_direct_staged(const KArgs &a)
         if (xslot(i) >= 0) {
             int j, sx, sy, sz;
             write_off<W>(nd, i, j, sx, sy, sz);
-            if (sx != 0 && valid) pdf_store(dst + elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch), xs[xslot(i) < 0 ? 0 : xslot(i)][t]);
+            if (sx != 0 && valid) pdf_store<true>(dst + elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch), xs[xslot(i) < 0 ? 0 : xslot(i)][t]);
         }
     }
 }
@@ -453,6 +453,7 @@ __device__ __forceinline__ void update_node(const KArgs &a, uint32_t n)
     using ct = typename S::ct;
     constexpr int R = rmap_of(KIND);
     constexpr int W = wmap_of(KIND);
+    constexpr bool NT = (ADDR == A_DIRECT && LAY == L_SOA);
     Node<ADDR, need_r(R) | need_w(W)> nd;
     nd.init(a, n);
     const st *src = static_cast<const st *>(a.src);
@@ -463,7 +464,7 @@ __device__ __forceinline__ void update_node(const KArgs &a, uint32_t n)
         int j;
         int64_t c;
         read_slot<R>(nd, i, j, c);
-        v[i] = S::load(pdf_load(src + elem<LAY>(j, c, a.pitch)));
+        v[i] = S::load(pdf_load<NT>(src + elem<LAY>(j, c, a.pitch)));
     }
     if constexpr (COLL == 1 && KIND != K_TS_STREAM) {
         CollideParams<ct> p;
@@ -480,7 +481,7 @@ __device__ __forceinline__ void update_node(const KArgs &a, uint32_t n)
         int j;
         int64_t c;
         write_slot<W>(nd, i, j, c);
-        pdf_store(dst + elem<LAY>(j, c, a.pitch), S::save(v[i]));
+        pdf_store<NT>(dst + elem<LAY>(j, c, a.pitch), S::save(v[i]));
     }
 }
 
@@ -654,5 +655,6 @@ struct PrecTable {
 const PrecTable &table_f64();
 const PrecTable &table_f32();
 const PrecTable &table_f16s();
+const PrecTable &table_f32s();
 
 } // namespace lbm

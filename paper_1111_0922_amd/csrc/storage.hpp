@@ -1,7 +1,8 @@
 // storage.hpp -- PDF storage precisions and memory layouts.
 //
-// Precisions: FP64 (compute FP64), FP32 (compute FP32), FP16S: the shifted
-// deviation h_i = (f_i - w_i) * sigma in binary16, computed in FP32.
+// Precisions: FP64 (compute FP64), FP32 (compute FP32), and the shifted
+// deviations h_i = (f_i - w_i) * sigma stored in binary16 (FP16S) or binary32
+// (F32S), both computed in FP32.
 // Layouts (Sec. 1): SoA keeps one array per direction, element j * pitch + a;
 // AoS keeps the 19 values of a cell together, element a * 19 + j.
 #pragma once
@@ -14,7 +15,7 @@
 
 namespace lbm {
 
-enum Prec : int { P_F64 = 0, P_F32 = 1, P_F16S = 2 };
+enum Prec : int { P_F64 = 0, P_F32 = 1, P_F16S = 2, P_F32S = 3 };
 enum Lay : int { L_SOA = 0, L_AOS = 1 };
 
 template <int P>
@@ -70,9 +71,12 @@ struct Store<P_F16S> {
     __device__ static st from_canon(double f, int i, double sigma) { return (_Float16)((f - wd(i)) * sigma); }
 };
 
-// PDF traffic of the update kernels streams through the caches once per
-// step; loads and stores carry the nontemporal hint unless disabled at build
-// time (LBM_NT_LOAD / LBM_NT_STORE = 0).
+// PDF traffic of the direct SoA update kernels streams through the caches
+// exactly once per step (every line is read and written whole), so their
+// loads and stores carry the nontemporal hint.  Indirect gathers and AoS
+// records reuse partly used lines across neighbouring nodes; there the hint
+// costs traffic and is not used.  LBM_NT_LOAD / LBM_NT_STORE = 0 at build
+// time disable it everywhere (measurements of build variants).
 #ifndef LBM_NT_LOAD
 #define LBM_NT_LOAD 1
 #endif
@@ -80,41 +84,50 @@ struct Store<P_F16S> {
 #define LBM_NT_STORE 1
 #endif
 
-template <typename T>
+template <bool NT, typename T>
 __device__ __forceinline__ T pdf_load(const T *p)
 {
-#if LBM_NT_LOAD
-    return __builtin_nontemporal_load(p);
-#else
-    return *p;
-#endif
+    if constexpr (NT && LBM_NT_LOAD)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
+template <bool NT, typename T>
+__device__ __forceinline__ void pdf_store(T *p, T v)
+{
+    if constexpr (NT && LBM_NT_STORE)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
 }
 
 // load of one stored PDF into its raw register
-template <class S>
+template <bool NT, class S>
 __device__ __forceinline__ typename S::rt pdf_load_raw(const typename S::st *p)
 {
     if constexpr (sizeof(typename S::st) == 2) {
         const uint16_t *q = reinterpret_cast<const uint16_t *>(p);
-#if LBM_NT_LOAD
-        return (uint32_t)__builtin_nontemporal_load(q);
-#else
-        return (uint32_t)*q;
-#endif
+        return (uint32_t)pdf_load<NT>(q);
     } else {
-        return pdf_load(p);
+        return pdf_load<NT>(p);
     }
 }
 
-template <typename T>
-__device__ __forceinline__ void pdf_store(T *p, T v)
-{
-#if LBM_NT_STORE
-    __builtin_nontemporal_store(v, p);
-#else
-    *p = v;
-#endif
-}
+template <>
+struct Store<P_F32S> {
+    using st = float;
+    using ct = float;
+    using rt = float;
+    static constexpr bool shifted = true;
+    __device__ static rt raw(st x) { return x; }
+    __device__ static st unraw(rt r) { return r; }
+    __device__ static ct load_raw(rt r) { return r; }
+    __device__ static ct load(st x) { return x; }
+    __device__ static st save(ct v) { return v; }
+    __device__ static double to_canon(st x, int i, double sigma) { return wd(i) + (double)x / sigma; }
+    __device__ static st from_canon(double f, int i, double sigma) { return (float)((f - wd(i)) * sigma); }
+};
 
 template <int L>
 __device__ __forceinline__ int64_t elem(int j, int64_t a, int64_t pitch)

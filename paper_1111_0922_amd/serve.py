@@ -197,7 +197,7 @@ class GpuExecutor:
         self.g = float(g)
         self.grids = {}
         self.masks = {}
-        self.pdf_size = {"f64": 8, "f32": 4, "f16s": 2}[precision]
+        self.pdf_size = {"f64": 8, "f32": 4, "f16s": 2, "f32s": 4}[precision]
 
     def prepare(self, req):
         import lbm_inputs

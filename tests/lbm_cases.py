@@ -8,7 +8,7 @@ import oracle
 SCHEMES = ["ts", "os_push", "os_pull", "aa", "et"]
 LAYOUTS = ["soa", "aos"]
 ADDRESSING = ["direct", "indirect"]
-PRECISIONS = ["f64", "f32", "f16s"]
+PRECISIONS = ["f64", "f32", "f16s", "f32s"]
 
 
 def make_grid(solid, scheme, *, addressing="direct", layout="soa", precision="f64", omega=1.0,

@@ -48,6 +48,7 @@ def test_fp32_storage(case, scheme, addressing):
         want = oracle.fluid_view(oracle.run_ts(q0, solid, steps, omega, g, precision="f32"), solid)
         got, m0, m1 = _run(solid, scheme, "f32", 1.0, q0, steps, omega, g, addressing)
         assert float(np.max(np.abs(got - want) / np.abs(want))) <= bar, steps
+        # plain FP32 storage: rounding of f ~ w_i repeats at steady state, mass drifts slowly
         assert abs(m1[0] - m0[0]) / m0[0] <= 1e-6
     assert float(np.max(np.abs(got - f64_100) / f64_100)) <= 2e-5
 
@@ -75,3 +76,21 @@ def test_fp16_scale_improves_accuracy(case):
         got, _, _ = _run(solid, "aa", "f16s", sigma, q0, 100, omega, g)
         errs[sigma] = float(np.max(np.abs(got - f64_100)))
     assert errs[1024.0] < errs[1.0] / 4
+
+
+@pytest.mark.parametrize("sigma", [1.0, 1024.0])
+@pytest.mark.parametrize("scheme", ["aa", "et", "os_pull"])
+@pytest.mark.parametrize("addressing", ADDRESSING)
+def test_fp32_shifted_storage(case, sigma, scheme, addressing):
+    """FP32 shifted storage h = (f - w_i) sigma: the stored code carries ~2^-24 of the deviation
+    (|f - w_i| < 2^-12 here, so < 2^-36 in f); the FP32 arithmetic of the deviation form adds a
+    few ulp of rho = 1 (2^-23) to the mass moment.  Bars: 2e-9 in f after one step, 2e-8 after
+    100 steps, and 2e-7 relative to the full FP64 run."""
+    solid, f0, omega, g, f64_100 = case
+    q0 = oracle.quantize(f0, solid, "f32s", sigma)
+    for steps, bar in ((1, 2e-9), (100, 2e-8)):
+        want = oracle.fluid_view(oracle.run_ts(q0, solid, steps, omega, g, precision="f32s", sigma=sigma), solid)
+        got, m0, m1 = _run(solid, scheme, "f32s", sigma, q0, steps, omega, g, addressing)
+        assert float(np.max(np.abs(got - want))) <= bar, steps
+        assert abs(m1[0] - m0[0]) / m0[0] <= 1e-9
+    assert float(np.max(np.abs(got - f64_100) / f64_100)) <= 2e-7

@@ -325,6 +325,9 @@ def test_quantize_forms():
     f = Wf[:, None, None, None] * (1 + 1e-3 * rng.standard_normal((19, 3, 3, 3)))
     np.testing.assert_array_equal(oracle.quantize(f, solid, "f32"), f.astype(np.float32).astype(np.float64))
     sigma = 1024.0
+    q32 = oracle.quantize(f, solid, "f32s", sigma)
+    d = ((f - Wf[:, None, None, None]) * sigma).astype(np.float32).astype(np.float64)
+    np.testing.assert_array_equal(q32, Wf[:, None, None, None] + d / sigma)
     q = oracle.quantize(f, solid, "f16s", sigma)
     h = ((f - Wf[:, None, None, None]) * sigma).astype(np.float16).astype(np.float64)
     np.testing.assert_array_equal(q, Wf[:, None, None, None] + h / sigma)
