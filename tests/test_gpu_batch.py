@@ -25,7 +25,7 @@ def _grid(shape, r, phi, seed, precision, omega=1.0, g=1e-5):
     return grid, solid
 
 
-@pytest.mark.parametrize("precision", ["f32", "f64", "f16s"])
+@pytest.mark.parametrize("precision", ["f32", "f64", "f16s", "f32s"])
 @pytest.mark.parametrize("use_graph", [True, False])
 def test_alone_equals_mixed_bitwise(precision, use_graph):
     import paper_1111_0922_amd as P
