@@ -27,10 +27,10 @@
  *     says it synchronises.  Launch errors are reported by the launching call;
  *     asynchronous faults surface at the caller's next synchronisation.
  *   - Canonical PDF arrays are FP64 [19][n_nodes] (row i = direction i of the
- *     ordering below, node n in lexicographic order with x fastest).  For a
- *     direct grid the nodes are the fluid cells (all cells, or the cells with
- *     1 <= z <= nz-2 when wall_z is set); for an indirect grid they are the
- *     fluid ids assigned by lbm_build_idx.
+ *     ordering below).  For a direct grid the nodes are the fluid cells in
+ *     lexicographic order, x fastest (all cells, or the cells with
+ *     1 <= z <= nz-2 when wall_z is set); for an indirect grid they are in
+ *     the order of the fluid ids assigned by lbm_build_idx.
  *
  * D3Q19 ordering (fixed convention of this library, each moving direction
  * followed by its opposite):
@@ -93,6 +93,15 @@ typedef struct {
     double omega;        /* BGK relaxation rate, 0 < omega < 2                   */
     double g[3];         /* body-force acceleration (force density rho * g)      */
     double f16_scale;    /* sigma of the shifted forms F16S, F32S (> 0); else ignored */
+    int32_t brick[3];    /* INDIRECT only: order of the fluid numbering.  Fluid ids
+                            follow bricks of brick[0] x brick[1] x brick[2] cells
+                            taken in lexicographic brick order, the cells of a brick
+                            lexicographically (x fastest).  0 (or the box size) in
+                            every entry: plain lexicographic order.  The paper
+                            compares such setups of the sparse representation
+                            (Sec. 10); blocked orders keep most neighbours of a
+                            workgroup's nodes in its own cache lines.             */
+    int32_t reserved;    /* set to 0 */
 } lbm_grid_desc;
 
 typedef struct {
@@ -167,9 +176,9 @@ int lbm_query_sizes(const lbm_grid *g, int32_t scheme, lbm_sizes *out);
  * neighbours).  Two calls:
  *   1. d_idx == NULL: reads d_mask (uint8[n_cells], 1 = solid, x fastest),
  *      writes d_cellmap (int32[n_cells]): the fluid id of each fluid cell in
- *      lexicographic order, -1 for a solid cell, or -2 - k for the solid cell
- *      holding esoteric-twist storage entry k (et_ghosts only, ghosts numbered
- *      in lexicographic order).  Stores N_f in *n_fluid_out (host) and keeps
+ *      the numbering order of desc.brick (lexicographic by default), -1 for a
+ *      solid cell, or -2 - k for the solid cell holding esoteric-twist storage
+ *      entry k (et_ghosts only, ghosts numbered in the same order).  Stores N_f in *n_fluid_out (host) and keeps
  *      N_f and the ghost count in the grid.  Synchronises `stream` once.
  *   2. d_idx != NULL: reads d_cellmap, writes d_idx (int32[18][idx_pitch]):
  *      IDX[k][n] = fluid id of the cell at x_n + c_{k+1} (periodic wrap) or -1

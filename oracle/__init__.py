@@ -69,6 +69,8 @@ def _load():
     lib.ora_init_equilibrium.argtypes = [dp, u8p, ip, dp]
     lib.ora_build_idx.argtypes = [u8p, ip, ip, i32p, i32p, ctypes.c_long]
     lib.ora_build_idx.restype = ctypes.c_long
+    lib.ora_build_idx_brick.argtypes = [u8p, ip, ip, ip, i32p, i32p, ctypes.c_long]
+    lib.ora_build_idx_brick.restype = ctypes.c_long
     lib.ora_num_threads.argtypes = [ctypes.c_int]
     lib.ora_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -216,18 +218,36 @@ def macroscopic(f, solid, g):
     return out[0], out[1:]
 
 
-def build_idx(solid, periodic=(1, 1, 1), with_idx=True):
-    """(cellmap int32[nz,ny,nx], idx int32[18, N_f] or None, N_f)."""
+def build_idx(solid, periodic=(1, 1, 1), with_idx=True, brick=None):
+    """(cellmap int32[nz,ny,nx], idx int32[18, N_f] or None, N_f).
+
+    brick = (bx, by, bz) numbers the fluid cells brick by brick (bricks in
+    lexicographic order, cells inside a brick likewise); None = lexicographic.
+    """
     lib = _load()
     solid = np.ascontiguousarray(solid, dtype=np.uint8)
     cellmap = np.zeros(solid.shape, dtype=np.int32)
     nf = int((solid == 0).sum())
     idx = np.zeros((18, max(nf, 1)), dtype=np.int32) if with_idx else None
-    got = lib.ora_build_idx(_p(solid, ctypes.c_uint8), _dims(solid), _per(periodic),
-                            _p(cellmap, ctypes.c_int32),
-                            _p(idx, ctypes.c_int32) if with_idx else None, max(nf, 1))
+    b = (ctypes.c_int * 3)(*(brick if brick is not None else (0, 0, 0)))
+    got = lib.ora_build_idx_brick(_p(solid, ctypes.c_uint8), _dims(solid), _per(periodic), b,
+                                  _p(cellmap, ctypes.c_int32),
+                                  _p(idx, ctypes.c_int32) if with_idx else None, max(nf, 1))
     assert got == nf
     return cellmap, (idx[:, :nf] if with_idx else None), nf
+
+
+def node_order(cellmap):
+    """Flat cell index of each fluid id (inverse of the cellmap)."""
+    flat = cellmap.reshape(-1)
+    order = np.empty(int((flat >= 0).sum()), dtype=np.int64)
+    order[flat[flat >= 0]] = np.flatnonzero(flat >= 0)
+    return order
+
+
+def ordered_view(f, order):
+    """PDFs of the fluid cells in fluid-id order, float64[19, N_f]."""
+    return np.ascontiguousarray(f.reshape(19, -1)[:, order])
 
 
 def num_threads(threads=0):

@@ -322,18 +322,34 @@ void ora_init_equilibrium(const double *rho_u, const uint8_t *solid, const int d
     }
 }
 
-/* Index array of indirect addressing.  cellmap[c] = fluid id (lexicographic
- * rank among fluid cells) or -1.  idx (optional, 18 rows of idx_pitch):
+/* Index array of indirect addressing.  Fluid ids number the fluid cells in
+ * a traversal order: bricks of bx*by*bz cells taken in lexicographic brick
+ * order, the cells of a brick in lexicographic order, cells outside the box
+ * skipped (the paper benchmarks several such setups of the sparse
+ * representation, Sec. 10).  A brick equal to the whole box (or 0 in any
+ * dimension) is the plain lexicographic order, x fastest.
+ * cellmap[c] = fluid id or -1.  idx (optional, 18 rows of idx_pitch):
  * idx[k][n] = id of the cell at x_n + c_{k+1}, -1 if solid or outside a
  * non-periodic axis.  Returns the number of fluid nodes. */
-long ora_build_idx(const uint8_t *solid, const int dims[3], const int periodic[3], int32_t *cellmap,
-                   int32_t *idx, long idx_pitch)
+long ora_build_idx_brick(const uint8_t *solid, const int dims[3], const int periodic[3], const int brick[3],
+                         int32_t *cellmap, int32_t *idx, long idx_pitch)
 {
     init_tables();
     const int nx = dims[0], ny = dims[1], nz = dims[2];
     const long ncell = (long)nx * ny * nz;
+    int b[3];
+    for (int a = 0; a < 3; ++a) b[a] = (brick && brick[a] > 0) ? brick[a] : dims[a];
     long nf = 0;
-    for (long c = 0; c < ncell; ++c) cellmap[c] = solid[c] ? -1 : (int32_t)nf++;
+    for (long c = 0; c < ncell; ++c) cellmap[c] = -1;
+    for (int Bz = 0; Bz < nz; Bz += b[2])
+        for (int By = 0; By < ny; By += b[1])
+            for (int Bx = 0; Bx < nx; Bx += b[0])
+                for (int z = Bz; z < Bz + b[2] && z < nz; ++z)
+                    for (int y = By; y < By + b[1] && y < ny; ++y)
+                        for (int x = Bx; x < Bx + b[0] && x < nx; ++x) {
+                            long c = x + (long)nx * (y + (long)ny * z);
+                            if (!solid[c]) cellmap[c] = (int32_t)nf++;
+                        }
     if (!idx) return nf;
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
@@ -357,6 +373,13 @@ long ora_build_idx(const uint8_t *solid, const int dims[3], const int periodic[3
                 }
             }
     return nf;
+}
+
+/* Lexicographic order (x fastest): the whole box is one brick. */
+long ora_build_idx(const uint8_t *solid, const int dims[3], const int periodic[3], int32_t *cellmap,
+                   int32_t *idx, long idx_pitch)
+{
+    return ora_build_idx_brick(solid, dims, periodic, 0, cellmap, idx, idx_pitch);
 }
 
 int ora_num_threads(int nthreads)

@@ -38,7 +38,8 @@ class GridDesc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("addressing", ctypes.c_int32), ("layout", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("wall_z", ctypes.c_int32), ("et_ghosts", ctypes.c_int32),
-                ("omega", ctypes.c_double), ("g", ctypes.c_double * 3), ("f16_scale", ctypes.c_double)]
+                ("omega", ctypes.c_double), ("g", ctypes.c_double * 3), ("f16_scale", ctypes.c_double),
+                ("brick", ctypes.c_int32 * 3), ("reserved", ctypes.c_int32)]
 
 
 class Sizes(ctypes.Structure):

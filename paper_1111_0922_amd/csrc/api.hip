@@ -181,6 +181,8 @@ int lbm_create_grid(const lbm_grid_desc *desc, lbm_grid **out)
         return fail(LBM_E_ARG, "f16_scale (sigma of the shifted forms) must be > 0");
     if (d.addressing == LBM_DIRECT && d.wall_z && d.nz < 3) return fail(LBM_E_ARG, "walls need nz >= 3");
     if (nc * Q >= ((int64_t)1 << 40)) return fail(LBM_E_ARG, "box too large");
+    for (int k = 0; k < 3; ++k)
+        if (d.brick[k] < 0) return fail(LBM_E_ARG, "brick sizes must be >= 0");
     lbm_grid *g = new lbm_grid();
     g->d = d;
     g->n_cells = nc;
@@ -240,7 +242,13 @@ int lbm_query_sizes(const lbm_grid *g, int32_t scheme, lbm_sizes *out)
     out->n_ghost = (scheme == LBM_ET) ? g->n_ghost : 0;
     if (d.addressing == LBM_INDIRECT) {
         out->cellmap_bytes = round_up(g->n_cells * 4, 256);
-        const int64_t nb = (g->n_cells + IDX_CELLS - 1) / IDX_CELLS;
+        const int32_t dims[3] = {d.nx, d.ny, d.nz};
+        int64_t nv = 1;
+        for (int k = 0; k < 3; ++k) {
+            const int64_t bk = (d.brick[k] > 0 && d.brick[k] < dims[k]) ? d.brick[k] : dims[k];
+            nv *= (dims[k] + bk - 1) / bk * bk;
+        }
+        const int64_t nb = (nv + IDX_CELLS - 1) / IDX_CELLS;
         out->build_scratch_bytes = round_up(nb * 2 * 4, 256) + (2 * nb + 2) * 8;
         if (g->idx_phase == 0) return LBM_OK;
         out->idx_pitch = idx_pitch_of(g);
@@ -273,7 +281,26 @@ int lbm_build_idx(lbm_grid *g, const uint8_t *d_mask, int32_t *d_cellmap, int32_
     b.dvx = make_fastdiv((uint32_t)b.nx);
     b.dvy = make_fastdiv((uint32_t)b.ny);
     b.n_cells = (uint32_t)g->n_cells;
-    b.n_blocks = (uint32_t)((g->n_cells + IDX_CELLS - 1) / IDX_CELLS);
+    const int32_t dims[3] = {g->d.nx, g->d.ny, g->d.nz};
+    int32_t br[3];
+    for (int k = 0; k < 3; ++k) br[k] = (g->d.brick[k] > 0 && g->d.brick[k] < dims[k]) ? g->d.brick[k] : dims[k];
+    b.bx = br[0];
+    b.by = br[1];
+    b.bz = br[2];
+    b.nbx = (dims[0] + br[0] - 1) / br[0];
+    b.nby = (dims[1] + br[1] - 1) / br[1];
+    const int64_t nbz = (dims[2] + br[2] - 1) / br[2];
+    const int64_t bv = (int64_t)br[0] * br[1] * br[2];
+    const int64_t nv = (int64_t)b.nbx * b.nby * nbz * bv;
+    if (nv >= ((int64_t)1 << 31)) return fail(LBM_E_ARG, "brick grid of %lld positions exceeds 2^31 - 1", (long long)nv);
+    b.bv = (uint32_t)bv;
+    b.n_virtual = (uint32_t)nv;
+    b.dv_bv = make_fastdiv(b.bv);
+    b.dv_bx = make_fastdiv((uint32_t)b.bx);
+    b.dv_by = make_fastdiv((uint32_t)b.by);
+    b.dv_nbx = make_fastdiv((uint32_t)b.nbx);
+    b.dv_nby = make_fastdiv((uint32_t)b.nby);
+    b.n_blocks = (uint32_t)((nv + IDX_CELLS - 1) / IDX_CELLS);
     b.et_on = g->d.et_ghosts ? 1 : 0;
     if (!d_idx) {
         if (!d_mask || !d_scratch) return fail(LBM_E_ARG, "d_mask and d_scratch are required");

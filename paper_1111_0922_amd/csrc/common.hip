@@ -53,10 +53,32 @@ void launch_stream_copy(const void *src, void *dst, int64_t bytes, hipStream_t s
 }
 
 // ------------------------------------------------------------------ index build
-// Cells are processed in chunks of IDX_CELLS (IDX_PER_THREAD consecutive
-// cells per thread), so a block's fluid cells are numbered in lexicographic
-// order by (block offset) + (exclusive prefix over its threads) + (position
-// inside the thread's run).
+// Cells are visited in the numbering's traversal order v (bricks in
+// lexicographic brick order, cells of a brick lexicographically; one brick
+// spanning the box is the plain lexicographic order), in chunks of IDX_CELLS
+// (IDX_PER_THREAD consecutive v per thread).  A fluid cell's id is (chunk
+// offset) + (exclusive prefix over the chunk's threads) + (position inside
+// the thread's run).
+
+// cell of traversal index v; false for a padding position outside the box
+__device__ __forceinline__ bool traversal_cell(const BuildArgs &b, uint32_t v, uint32_t &c)
+{
+    if (v >= b.n_virtual) return false;
+    const uint32_t brick = fdiv(v, b.dv_bv);
+    const uint32_t local = v - brick * b.bv;
+    const uint32_t q = fdiv(local, b.dv_bx);
+    const uint32_t lx = local - q * (uint32_t)b.bx;
+    const uint32_t lz = fdiv(q, b.dv_by);
+    const uint32_t ly = q - lz * (uint32_t)b.by;
+    const uint32_t q2 = fdiv(brick, b.dv_nbx);
+    const uint32_t Bx = brick - q2 * (uint32_t)b.nbx;
+    const uint32_t Bz = fdiv(q2, b.dv_nby);
+    const uint32_t By = q2 - Bz * (uint32_t)b.nby;
+    const uint32_t x = Bx * b.bx + lx, y = By * b.by + ly, z = Bz * b.bz + lz;
+    if (x >= (uint32_t)b.nx || y >= (uint32_t)b.ny || z >= (uint32_t)b.nz) return false;
+    c = x + (uint32_t)b.nx * (y + (uint32_t)b.ny * z);
+    return true;
+}
 
 __device__ __forceinline__ void cell_xyz(const BuildArgs &b, uint32_t c, int &x, int &y, int &z)
 {
@@ -88,11 +110,11 @@ __device__ __forceinline__ bool needs_ghost(const BuildArgs &b, uint32_t c)
     return false;
 }
 
-__device__ __forceinline__ void cell_flags(const BuildArgs &b, uint32_t c, int &fluid, int &ghost)
+__device__ __forceinline__ void cell_flags(const BuildArgs &b, uint32_t v, int &fluid, int &ghost, uint32_t &c)
 {
     fluid = 0;
     ghost = 0;
-    if (c >= b.n_cells) return;
+    if (!traversal_cell(b, v, c)) return;
     if (!b.mask[c])
         fluid = 1;
     else if (b.et_on)
@@ -132,7 +154,8 @@ __global__ void __launch_bounds__(BLOCK) k_idx_count(BuildArgs b)
 #pragma unroll
     for (int u = 0; u < IDX_PER_THREAD; ++u) {
         int f, g;
-        cell_flags(b, c0 + u, f, g);
+        uint32_t c;
+        cell_flags(b, c0 + u, f, g, c);
         nf += f;
         ng += g;
     }
@@ -189,11 +212,12 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_idx_scan(BuildArgs b)
 __global__ void __launch_bounds__(BLOCK) k_idx_cellmap(BuildArgs b)
 {
     int fl[IDX_PER_THREAD], gh[IDX_PER_THREAD];
+    uint32_t cell[IDX_PER_THREAD];
     int nf = 0, ng = 0;
     const uint32_t c0 = blockIdx.x * IDX_CELLS + threadIdx.x * IDX_PER_THREAD;
 #pragma unroll
     for (int u = 0; u < IDX_PER_THREAD; ++u) {
-        cell_flags(b, c0 + u, fl[u], gh[u]);
+        cell_flags(b, c0 + u, fl[u], gh[u], cell[u]);
         nf += fl[u];
         ng += gh[u];
     }
@@ -203,8 +227,8 @@ __global__ void __launch_bounds__(BLOCK) k_idx_cellmap(BuildArgs b)
     int64_t idg = b.offsets[b.n_blocks + blockIdx.x] + ng;
 #pragma unroll
     for (int u = 0; u < IDX_PER_THREAD; ++u) {
-        const uint32_t c = c0 + u;
-        if (c >= b.n_cells) break;
+        uint32_t c;
+        if (!traversal_cell(b, c0 + u, c)) continue;
         int32_t v = -1;
         if (fl[u])
             v = (int32_t)idf++;

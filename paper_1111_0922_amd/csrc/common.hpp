@@ -18,7 +18,14 @@ struct BuildArgs {
     int32_t nx, ny, nz;
     FastDiv dvx, dvy;
     uint32_t n_cells;
-    uint32_t n_blocks;    // ceil(n_cells / IDX_CELLS)
+    // traversal order of the fluid numbering: bricks bx*by*bz in lexicographic
+    // brick order, cells of a brick lexicographically; v runs over the padded
+    // brick grid (n_virtual = nbx*nby*nbz*bx*by*bz), cells outside the box skipped
+    int32_t bx, by, bz, nbx, nby;
+    uint32_t bv;          // bx * by * bz
+    uint32_t n_virtual;
+    FastDiv dv_bv, dv_bx, dv_by, dv_nbx, dv_nby;
+    uint32_t n_blocks;    // ceil(n_virtual / IDX_CELLS)
     int64_t idx_pitch;
     int64_t n_fluid;
     int32_t et_on;

@@ -181,6 +181,7 @@ struct Node<A_DIRECT, NEED> {
     // storage cell x + (ox, oy, oz), ox, oy, oz in {0, 1}
     __device__ __forceinline__ int64_t at(int sx, int sy, int sz) const { return shift(sx, sy, sz); }
     __device__ __forceinline__ bool et_solid(int i) const { return solid(i); }
+    __device__ __forceinline__ void refresh() {}
 };
 
 // Indirect addressing (Sec. 1): node ids of fluid nodes; neighbours from
@@ -214,6 +215,23 @@ struct Node<A_INDIRECT, NEED> {
         return c == 0 ? a : (int64_t)e[c - 1];
     }
     __device__ __forceinline__ bool et_solid(int i) const { return (mask >> (i - 1)) & 1u; }
+    // Opaque redefinition of the node's index registers (an empty asm, no
+    // memory access).  Called between gather and scatter, it keeps the
+    // compiler from holding 19 wide gather addresses live across the
+    // collision to reuse them for the scatter: the 32-bit ids are enough to
+    // rebuild them, which halves the registers of the in-place kernels.
+    __device__ __forceinline__ void refresh()
+    {
+        if constexpr ((NEED & NEED_NB) != 0) {
+#pragma unroll
+            for (int q = 0; q < 18; ++q) asm volatile("" : "+v"(m[q]));
+        }
+        if constexpr ((NEED & NEED_ET) != 0) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) asm volatile("" : "+v"(e[q]));
+            asm volatile("" : "+v"(mask));
+        }
+    }
 };
 
 // ------------------------------------------------------------------ maps
@@ -453,7 +471,10 @@ __device__ __forceinline__ void update_node(const KArgs &a, uint32_t n)
     using ct = typename S::ct;
     constexpr int R = rmap_of(KIND);
     constexpr int W = wmap_of(KIND);
-    constexpr bool NT = (ADDR == A_DIRECT && LAY == L_SOA);
+    // nontemporal hint where every touched line is read or written whole by
+    // this workgroup: direct SoA, and node-local kernels on indirect SoA grids
+    constexpr bool local = (R == R_LOCAL && (W == W_LOCAL || W == W_AAEVEN));
+    constexpr bool NT = (LAY == L_SOA) && (ADDR == A_DIRECT || local);
     Node<ADDR, need_r(R) | need_w(W)> nd;
     nd.init(a, n);
     const st *src = static_cast<const st *>(a.src);
@@ -476,6 +497,7 @@ __device__ __forceinline__ void update_node(const KArgs &a, uint32_t n)
         p.inv_sigma = (ct)(1.0 / a.sigma);
         collide_bgk<ct, S::shifted>(v, p);
     }
+    if constexpr (need_r(R) != 0 && need_w(W) != 0) nd.refresh(); // gather and scatter both use the ids
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         int j;

@@ -71,11 +71,12 @@ struct Store<P_F16S> {
     __device__ static st from_canon(double f, int i, double sigma) { return (_Float16)((f - wd(i)) * sigma); }
 };
 
-// PDF traffic of the direct SoA update kernels streams through the caches
-// exactly once per step (every line is read and written whole), so their
-// loads and stores carry the nontemporal hint.  Indirect gathers and AoS
-// records reuse partly used lines across neighbouring nodes; there the hint
-// costs traffic and is not used.  LBM_NT_LOAD / LBM_NT_STORE = 0 at build
+// PDF traffic of the direct SoA update kernels, and of node-local kernels on
+// indirect SoA grids, streams through the caches exactly once per step
+// (every line is read and written whole), so their loads and stores carry
+// the nontemporal hint.  Indirect gathers and AoS records reuse partly used
+// lines across neighbouring nodes; there the hint costs traffic and is not
+// used.  LBM_NT_LOAD / LBM_NT_STORE = 0 at build
 // time disable it everywhere (measurements of build variants).
 #ifndef LBM_NT_LOAD
 #define LBM_NT_LOAD 1

@@ -24,7 +24,20 @@ def _masks():
     yield "one_fluid_cell", m
 
 
-def _expected_et(solid, cellmap, nf):
+def _traversal(shape, brick):
+    """Flat cell indices in numbering order: bricks lexicographically, cells in a brick likewise."""
+    nz, ny, nx = shape
+    bx, by, bz = brick if brick is not None else (nx, ny, nz)
+    cells = np.arange(nx * ny * nz).reshape(shape)
+    out = []
+    for z0 in range(0, nz, bz):
+        for y0 in range(0, ny, by):
+            for x0 in range(0, nx, bx):
+                out.append(cells[z0:z0 + bz, y0:y0 + by, x0:x0 + bx].reshape(-1))
+    return np.concatenate(out)
+
+
+def _expected_et(solid, cellmap, nf, brick=None):
     """ET storage addresses and solid masks from the definitions (test-side, integer)."""
     nz, ny, nx = solid.shape
     flat = cellmap.reshape(-1)
@@ -34,20 +47,30 @@ def _expected_et(solid, cellmap, nf):
         # s = x + o is a ghost when s is solid and x = s - o is fluid
         ghost |= (solid == 1) & np.roll(fluid, (o[2], o[1], o[0]), axis=(0, 1, 2))
     gid = np.full(solid.size, -1, np.int64)
-    gid[ghost.reshape(-1)] = np.arange(int(ghost.sum()))
+    order = _traversal(solid.shape, brick)
+    gcells = order[ghost.reshape(-1)[order]]
+    gid[gcells] = np.arange(len(gcells))
     rows = []
+    by_id = oracle.node_order(cellmap)  # cell of each fluid id
     for o in OFFS:
         nb_cell = np.roll(np.arange(solid.size).reshape(solid.shape), (-o[2], -o[1], -o[0]), axis=(0, 1, 2))
-        nbc = nb_cell.reshape(-1)[fluid.reshape(-1)]
+        nbc = nb_cell.reshape(-1)[by_id]
         v = flat[nbc].astype(np.int64)
         rows.append(np.where(v >= 0, v, nf + gid[nbc]))
     return np.array(rows), int(ghost.sum())
 
 
+@pytest.mark.parametrize("brick", [None, (4, 4, 4), (8, 3, 2), (16, 8, 4)], ids=["lex", "b444", "b832", "b1684"])
 @pytest.mark.parametrize("name,solid", list(_masks()), ids=[n for n, _ in _masks()])
-def test_idx_bit_exact(name, solid):
-    cellmap_o, idx_o, nf = oracle.build_idx(solid)
-    grid = make_grid(solid, "et", addressing="indirect")
+def test_idx_bit_exact(name, solid, brick):
+    cellmap_o, idx_o, nf = oracle.build_idx(solid, brick=brick)
+    if brick is None:
+        # the traversal of the test agrees with the oracle's numbering
+        ids = cellmap_o.reshape(-1)[_traversal(solid.shape, None)]
+        assert np.array_equal(ids[ids >= 0], np.arange(nf))
+    ids = cellmap_o.reshape(-1)[_traversal(solid.shape, brick)]
+    assert np.array_equal(ids[ids >= 0], np.arange(nf))
+    grid = make_grid(solid, "et", addressing="indirect", brick=brick)
     torch.cuda.synchronize()
     assert grid.n_nodes == nf
     s = grid.sizes("et")
@@ -56,7 +79,7 @@ def test_idx_bit_exact(name, solid):
     idx = grid.idx.view(-1)[: 18 * s.idx_pitch].view(18, s.idx_pitch)[:, :nf].cpu().numpy()
     np.testing.assert_array_equal(idx, idx_o)
     et = grid.et.view(-1)[: 7 * s.idx_pitch].view(7, s.idx_pitch)[:, :nf].cpu().numpy()
-    want, n_ghost = _expected_et(solid, cellmap_o, nf)
+    want, n_ghost = _expected_et(solid, cellmap_o, nf, brick)
     assert s.n_ghost == n_ghost
     np.testing.assert_array_equal(et[:6].astype(np.int64), want)
     mask_bits = sum(((idx_o[k] < 0).astype(np.int64) << k) for k in range(18))

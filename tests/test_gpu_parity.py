@@ -181,3 +181,20 @@ def test_row_staged_kernels_bit_identical_to_plain(scheme, shape):
     assert np.array_equal(out[0].view(np.int64), out[1].view(np.int64))
     want = oracle.fluid_view(oracle.run_ts(dense_from_canon(f0, solid), solid, 5, 1.7, (1e-5, 2e-5, 0)), solid)
     assert rel_err(out[0], want) <= 1e-13
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("brick", [(4, 4, 4), (8, 2, 4)])
+def test_brick_ordered_indirect_matches_oracle(scheme, brick):
+    """Fluid ids in brick order: the canonical node order is the grid's id order."""
+    solid = lbm_inputs.sphere_pack((29, 21, 18), 3, 0.5, seed=6)[0]
+    ru = lbm_inputs.rho_u_field(solid.shape, lbm_inputs.velocity_noise(solid.shape, 1e-3, seed=5))
+    f0 = oracle.init_equilibrium(ru, solid)
+    g = (1e-5, 0, 0)
+    cellmap, _, nf = oracle.build_idx(solid, brick=brick)
+    order = oracle.node_order(cellmap)
+    want = oracle.ordered_view(oracle.run_ts(f0, solid, 21, 1.6, g), order)
+    grid = make_grid(solid, scheme, addressing="indirect", omega=1.6, g=g, brick=brick)
+    grid.set_pdfs(to_device(oracle.ordered_view(f0, order)))
+    grid.step(21)
+    assert rel_err(from_device(grid.get_pdfs()), want) <= 1e-12

@@ -331,3 +331,25 @@ def test_quantize_forms():
     q = oracle.quantize(f, solid, "f16s", sigma)
     h = ((f - Wf[:, None, None, None]) * sigma).astype(np.float16).astype(np.float64)
     np.testing.assert_array_equal(q, Wf[:, None, None, None] + h / sigma)
+
+
+def test_brick_ordering_is_a_renumbering():
+    """Brick-ordered ids number the same fluid cells; links map onto each other under the renumbering."""
+    solid, _ = lbm_inputs.sphere_pack((10, 9, 7), 2, 0.5, seed=1)
+    cm0, idx0, nf = oracle.build_idx(solid)
+    cm1, idx1, nf1 = oracle.build_idx(solid, brick=(4, 3, 2))
+    assert nf1 == nf
+    assert np.array_equal(cm0 >= 0, cm1 >= 0)
+    # id of brick (0,0,0)'s first fluid cell is 0; cells of brick (0,0,0) come first
+    first = cm1[:2, :3, :4]
+    assert sorted(first[first >= 0].ravel().tolist()) == list(range(int((first >= 0).sum())))
+    # renumbering map new -> old
+    new_to_old = np.empty(nf, np.int64)
+    new_to_old[cm1[cm1 >= 0]] = cm0[cm1 >= 0]
+    old_to_new = np.empty(nf, np.int64)
+    old_to_new[new_to_old] = np.arange(nf)
+    mapped = np.where(idx0 >= 0, old_to_new[np.maximum(idx0, 0)], -1)
+    np.testing.assert_array_equal(idx1[:, old_to_new], mapped)
+    # a brick covering the box is the lexicographic order
+    cm2, idx2, _ = oracle.build_idx(solid, brick=(10, 9, 7))
+    np.testing.assert_array_equal(cm2, cm0)
