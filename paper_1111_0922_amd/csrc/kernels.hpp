@@ -507,6 +507,87 @@ __device__ __forceinline__ void update_node(const KArgs &a, uint32_t n)
     }
 }
 
+// AoS update with the node-local side staged through LDS (Sec. 1: AoS keeps
+// a node's 19 PDFs together, so a workgroup's 256 consecutive nodes are one
+// contiguous block of 256 * 19 values).  A local read copies that block
+// into LDS with coalesced accesses and each lane then reads its record from
+// LDS; a local write goes the other way.  Non-local sides (gathers from or
+// scatters to neighbours) stay per lane.  Nodes past n_nodes skip memory but
+// join the barriers.
+template <int ADDR, int PREC, int KIND, int COLL>
+__device__ __forceinline__ void update_aos_staged(const KArgs &a)
+{
+    using S = Store<PREC>;
+    using st = typename S::st;
+    using ct = typename S::ct;
+    constexpr int R = rmap_of(KIND);
+    constexpr int W = wmap_of(KIND);
+    constexpr bool local_r = (R == R_LOCAL);
+    constexpr bool local_w = (W == W_LOCAL || W == W_AAEVEN);
+    __shared__ st rec[BLOCK * Q];
+    const uint32_t t = threadIdx.x;
+    const uint32_t n0 = logical_block(a.remap) * BLOCK;
+    const uint32_t cnt = min((uint32_t)BLOCK, a.n_nodes - n0); // the grid covers n_nodes, so n0 < n_nodes
+    const bool valid = t < cnt;
+    const uint32_t n = n0 + (valid ? t : 0);
+    Node<ADDR, need_r(R) | need_w(W)> nd;
+    nd.init(a, n);
+    const int64_t a0 = (ADDR == A_DIRECT) ? (int64_t)n0 + a.z0_offset : (int64_t)n0; // first record
+    const st *src = static_cast<const st *>(a.src);
+    st *dst = static_cast<st *>(a.dst);
+    ct v[Q];
+    if constexpr (local_r) {
+        const st *base = src + a0 * Q;
+        for (uint32_t e = t; e < cnt * Q; e += BLOCK) rec[e] = base[e];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < Q; ++i) v[i] = S::load(rec[t * Q + i]);
+        __syncthreads();
+    } else {
+        if (valid) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                int j;
+                int64_t c;
+                read_slot<R>(nd, i, j, c);
+                v[i] = S::load(src[elem<L_AOS>(j, c, a.pitch)]);
+            }
+        }
+    }
+    if (valid) {
+        if constexpr (COLL == 1 && KIND != K_TS_STREAM) {
+            CollideParams<ct> p;
+            p.omega = (ct)a.omega;
+            p.gx = (ct)a.gx;
+            p.gy = (ct)a.gy;
+            p.gz = (ct)a.gz;
+            p.sigma = (ct)a.sigma;
+            p.inv_sigma = (ct)(1.0 / a.sigma);
+            collide_bgk<ct, S::shifted>(v, p);
+        }
+    }
+    if constexpr (local_w) {
+        if (valid) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) rec[t * Q + (W == W_AAEVEN ? opp(i) : i)] = S::save(v[i]);
+        }
+        __syncthreads();
+        st *base = dst + a0 * Q;
+        for (uint32_t e = t; e < cnt * Q; e += BLOCK) base[e] = rec[e];
+    } else {
+        if (valid) {
+            if constexpr (need_r(R) != 0 && need_w(W) != 0) nd.refresh();
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                int j;
+                int64_t c;
+                write_slot<W>(nd, i, j, c);
+                dst[elem<L_AOS>(j, c, a.pitch)] = S::save(v[i]);
+            }
+        }
+    }
+}
+
 template <int ADDR, int LAY, int PREC, int KIND, int COLL>
 __global__ void __launch_bounds__(BLOCK) k_update(KArgs a)
 {
@@ -519,6 +600,12 @@ __global__ void __launch_bounds__(BLOCK) k_update(KArgs a)
             update_direct_staged<PREC, KIND, COLL>(a);
             return;
         }
+    }
+    // AoS kernels with a node-local side stage that side through LDS
+    constexpr bool aos_local = (R == R_LOCAL) || (W == W_LOCAL || W == W_AAEVEN);
+    if constexpr (LAY == L_AOS && aos_local) {
+        update_aos_staged<ADDR, PREC, KIND, COLL>(a);
+        return;
     }
     const uint32_t n = logical_block(a.remap) * BLOCK + threadIdx.x;
     if (n >= a.n_nodes) return;
