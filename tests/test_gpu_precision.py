@@ -94,3 +94,32 @@ def test_fp32_shifted_storage(case, sigma, scheme, addressing):
         assert float(np.max(np.abs(got - want))) <= bar, steps
         assert abs(m1[0] - m0[0]) / m0[0] <= 1e-9
     assert float(np.max(np.abs(got - f64_100) / f64_100)) <= 2e-7
+
+
+def test_permeability_chain_to_steady_state():
+    """Small sphere pack run to steady state by the oracle (FP64) and by the GPU AA pattern (indirect)
+    in every storage form; permeability within the stated bounds of the FP64 oracle."""
+    import lbm_inputs
+    solid = lbm_inputs.sphere_pack(32, 4, 0.6, seed=4)[0]
+    omega, g, K = 1.0, 1e-6, 100
+    phi = float((solid == 0).mean())
+    nu = (1.0 / omega - 0.5) / 3.0
+    f = oracle.init_equilibrium(lbm_inputs.rho_u_field(solid.shape), solid)
+    prev, steps = None, 0
+    while steps < 20000:
+        f = oracle.run_ts(f, solid, K, omega, (g, 0, 0))
+        steps += K
+        U = oracle.mean_velocity(oracle.moments(f, solid), (g, 0, 0))[0]
+        if prev is not None and abs(U - prev) / abs(U) < 1e-8:
+            break
+        prev = U
+    k_oracle = nu * phi * U / g
+    bounds = {"f64": 1e-10, "f32s": 1e-4, "f16s": 1e-2, "f32": 5e-2}
+    for precision, bound in bounds.items():
+        grid = make_grid(solid, "aa", addressing="indirect", precision=precision, omega=omega, g=(g, 0, 0),
+                         f16_scale=1024.0)
+        grid.init_equilibrium()
+        grid.step(steps)
+        m = from_device(grid.moments())
+        k = nu * phi * ((m[1] + 0.5 * m[0] * g) / m[0]) / g
+        assert abs(k - k_oracle) / k_oracle <= bound, (precision, k, k_oracle)
