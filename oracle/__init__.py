@@ -59,11 +59,12 @@ def _load():
     lib.ora_round_half.restype = ctypes.c_double
     lib.ora_round_half_array.argtypes = [dp, dp, ctypes.c_long]
     lib.ora_quantize_field.argtypes = [dp, u8p, ip, ctypes.c_int, ctypes.c_double]
-    lib.ora_collide.argtypes = [dp, dp, u8p, ip, ctypes.c_double, dp, ctypes.c_int, ctypes.c_int,
-                                ctypes.c_double, ctypes.c_int]
+    lib.ora_collide.argtypes = [dp, dp, u8p, ip, ctypes.c_double, ctypes.c_double, dp, ctypes.c_int,
+                                ctypes.c_int, ctypes.c_double, ctypes.c_int]
+    lib.ora_collide_node_trt.argtypes = [dp, ctypes.c_double, ctypes.c_double, dp, dp]
     lib.ora_stream.argtypes = [dp, dp, u8p, ip, ip, ctypes.c_int]
-    lib.ora_run_ts.argtypes = [dp, dp, u8p, ip, ip, ctypes.c_double, dp, ctypes.c_int, ctypes.c_int,
-                               ctypes.c_double, ctypes.c_long, ctypes.c_int]
+    lib.ora_run_ts.argtypes = [dp, dp, u8p, ip, ip, ctypes.c_double, ctypes.c_double, dp, ctypes.c_int,
+                               ctypes.c_int, ctypes.c_double, ctypes.c_long, ctypes.c_int]
     lib.ora_moments.argtypes = [dp, u8p, ip, dp]
     lib.ora_macroscopic.argtypes = [dp, u8p, ip, dp, dp]
     lib.ora_init_equilibrium.argtypes = [dp, u8p, ip, dp]
@@ -95,7 +96,7 @@ def _vec3(v):
 
 
 QUANT = {None: 0, "f64": 0, "f32": 1, "f16s": 2, "f32s": 3}
-COLLIDER = {"identity": 0, "bgk": 1}
+COLLIDER = {"identity": 0, "bgk": 1, "trt": 2}
 
 
 def tables():
@@ -122,13 +123,23 @@ def guo_source(rho, u, omega, g):
     return out
 
 
-def collide_node(f, omega, g, collider="bgk"):
+def collide_node(f, omega, g, collider="bgk", omega_minus=None):
+    """One node's collision; collider 'trt' relaxes odd moments with omega_minus."""
     lib = _load()
     f = np.ascontiguousarray(f, dtype=np.float64)
     out = np.zeros(19)
-    lib.ora_collide_node(_p(f, ctypes.c_double), float(omega), _vec3(g), COLLIDER[collider],
-                         _p(out, ctypes.c_double))
+    if collider == "trt":
+        lib.ora_collide_node_trt(_p(f, ctypes.c_double), float(omega), float(omega_minus), _vec3(g),
+                                 _p(out, ctypes.c_double))
+    else:
+        lib.ora_collide_node(_p(f, ctypes.c_double), float(omega), _vec3(g), COLLIDER[collider],
+                             _p(out, ctypes.c_double))
     return out
+
+
+def trt_omega_minus(omega, lam):
+    """w- from w+ = omega and Lambda = (1/w+ - 1/2)(1/w- - 1/2)."""
+    return 1.0 / (lam / (1.0 / omega - 0.5) + 0.5)
 
 
 def round_half(v):
@@ -161,15 +172,15 @@ def init_equilibrium(rho_u, solid):
     return f
 
 
-def collide(f, solid, omega, g, collider="bgk", precision=None, sigma=1.0, threads=0):
+def collide(f, solid, omega, g, collider="bgk", precision=None, sigma=1.0, threads=0, omega_minus=None):
     """Collision loop alone (post-collision state at the same cells)."""
     lib = _load()
     solid = np.ascontiguousarray(solid, dtype=np.uint8)
     A = np.ascontiguousarray(f, dtype=np.float64)
     B = np.zeros_like(A)
     lib.ora_collide(_p(A, ctypes.c_double), _p(B, ctypes.c_double), _p(solid, ctypes.c_uint8),
-                    _dims(solid), float(omega), _vec3(g), COLLIDER[collider], QUANT[precision],
-                    float(sigma), int(threads))
+                    _dims(solid), float(omega), float(omega if omega_minus is None else omega_minus), _vec3(g),
+                    COLLIDER[collider], QUANT[precision], float(sigma), int(threads))
     return B
 
 
@@ -185,15 +196,18 @@ def stream(fpost, solid, periodic=(1, 1, 1), threads=0):
 
 
 def run_ts(f, solid, steps, omega, g, periodic=(1, 1, 1), collider="bgk", precision=None,
-           sigma=1.0, threads=0):
-    """`steps` time steps of the two-step two-grid algorithm; returns f(t+steps)."""
+           sigma=1.0, threads=0, omega_minus=None):
+    """`steps` time steps of the two-step two-grid algorithm; returns f(t+steps).
+
+    collider: 'bgk', 'identity', or 'trt' (odd moments relaxed with omega_minus).
+    """
     lib = _load()
     solid = np.ascontiguousarray(solid, dtype=np.uint8)
     A = np.array(f, dtype=np.float64, order="C", copy=True)
     B = np.zeros_like(A)
     lib.ora_run_ts(_p(A, ctypes.c_double), _p(B, ctypes.c_double), _p(solid, ctypes.c_uint8),
-                   _dims(solid), _per(periodic), float(omega), _vec3(g), COLLIDER[collider],
-                   QUANT[precision], float(sigma), int(steps), int(threads))
+                   _dims(solid), _per(periodic), float(omega), float(omega if omega_minus is None else omega_minus),
+                   _vec3(g), COLLIDER[collider], QUANT[precision], float(sigma), int(steps), int(threads))
     return A
 
 

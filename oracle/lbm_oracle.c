@@ -18,8 +18,10 @@
  *     with half-way bounce-back A[i][x] = B[opp(i)][x] when x - c_i is solid
  *     or lies outside a non-periodic axis;
  *   - the collision is single-relaxation-time BGK with the Guo, Zheng & Shi
- *     (2002) body-force term.  The paper's own solver uses TRT (Sec. 10) and
- *     does not print a collision operator; BGK + Guo is the reading taken.
+ *     (2002) body-force term, or the two-relaxation-time (TRT) collision the
+ *     paper's own solver uses (Sec. 10, ref. [15]) with the same force term
+ *     split into even and odd parts.  The paper prints no operator; these are
+ *     the readings taken.
  *   - the index array of indirect addressing (Sec. 1): fluid nodes numbered
  *     in lexicographic order (x fastest), IDX[k][n] = id of the neighbour in
  *     direction c_{k+1}, -1 when that neighbour is solid.
@@ -116,6 +118,32 @@ void ora_guo_source(double rho, const double u[3], double omega, const double g[
     }
 }
 
+/* TRT (Ginzburg): split each pair of opposite directions i, i' into even and
+ * odd parts a^+ = (a_i + a_i')/2, a^- = (a_i - a_i')/2 and relax them with w+
+ * and w-; the Guo source S (computed with omega = 0, i.e. without its
+ * prefactor) gets (1 - w+/2) on its even and (1 - w-/2) on its odd part. */
+void ora_collide_node_trt(const double f[Q], double wp, double wm, const double g[3], double out[Q])
+{
+    init_tables();
+    double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < Q; ++i) {
+        rho += f[i];
+        for (int a = 0; a < 3; ++a) j[a] += CV[i][a] * f[i];
+    }
+    double u[3];
+    for (int a = 0; a < 3; ++a) u[a] = (j[a] + 0.5 * rho * g[a]) / rho;
+    double feq[Q], S[Q];
+    ora_equilibrium(rho, u, feq);
+    ora_guo_source(rho, u, 0.0, g, S);
+    for (int i = 0; i < Q; ++i) {
+        int o = OPPV[i];
+        double fp = 0.5 * (f[i] + f[o]), fm = 0.5 * (f[i] - f[o]);
+        double ep = 0.5 * (feq[i] + feq[o]), em = 0.5 * (feq[i] - feq[o]);
+        double sp = 0.5 * (S[i] + S[o]), sm = 0.5 * (S[i] - S[o]);
+        out[i] = f[i] - wp * (fp - ep) - wm * (fm - em) + (1.0 - 0.5 * wp) * sp + (1.0 - 0.5 * wm) * sm;
+    }
+}
+
 /* One node: collider 1 = BGK + Guo, 0 = identity (stream-only runs). */
 void ora_collide_node(const double f[Q], double omega, const double g[3], int collider, double out[Q])
 {
@@ -191,7 +219,7 @@ void ora_quantize_field(double *A, const uint8_t *solid, const int dims[3], int 
 
 /* Collision loop of the two-step algorithm: A -> B at the same location. */
 void ora_collide(const double *A, double *B, const uint8_t *solid, const int dims[3], double omega,
-                 const double g[3], int collider, int quant, double sigma, int nthreads)
+                 double omega_minus, const double g[3], int collider, int quant, double sigma, int nthreads)
 {
     init_tables();
     const int nx = dims[0], ny = dims[1], nz = dims[2];
@@ -206,7 +234,10 @@ void ora_collide(const double *A, double *B, const uint8_t *solid, const int dim
                 if (solid[c]) continue;
                 double f[Q], fs[Q];
                 for (int i = 0; i < Q; ++i) f[i] = A[i * ncell + c];
-                ora_collide_node(f, omega, g, collider, fs);
+                if (collider == 2)
+                    ora_collide_node_trt(f, omega, omega_minus, g, fs);
+                else
+                    ora_collide_node(f, omega, g, collider, fs);
                 for (int i = 0; i < Q; ++i) B[i * ncell + c] = quantize_value(fs[i], i, quant, sigma);
             }
         }
@@ -257,11 +288,11 @@ void ora_stream(const double *B, double *A, const uint8_t *solid, const int dims
 /* nsteps full time steps of the two-step algorithm; A holds f(t) before and
  * f(t + nsteps) after; B is the intermediate lattice. */
 void ora_run_ts(double *A, double *B, const uint8_t *solid, const int dims[3], const int periodic[3],
-                double omega, const double g[3], int collider, int quant, double sigma, long nsteps,
-                int nthreads)
+                double omega, double omega_minus, const double g[3], int collider, int quant, double sigma,
+                long nsteps, int nthreads)
 {
     for (long t = 0; t < nsteps; ++t) {
-        ora_collide(A, B, solid, dims, omega, g, collider, quant, sigma, nthreads);
+        ora_collide(A, B, solid, dims, omega, omega_minus, g, collider, quant, sigma, nthreads);
         ora_stream(B, A, solid, dims, periodic, nthreads);
     }
 }

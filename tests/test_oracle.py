@@ -6,6 +6,8 @@ against a retyped copy of its own formulas:
   * equilibrium     -- its velocity moments up to second order;
   * Guo forcing     -- its moments (zero mass, (1-w/2)F momentum, stress term);
   * collision       -- exact mass conservation and momentum gain F per node;
+                       TRT: equal rates reduce to BGK, even and odd
+                       non-equilibrium parts decay by (1 - w+) and (1 - w-);
   * propagation     -- an exact permutation, built here with numpy rolls;
   * whole runs      -- mass conservation, momentum growth M g per step,
                        the rest state, Poiseuille flow (closed form, exact at
@@ -109,6 +111,43 @@ def test_identity_collider_is_identity():
     np.testing.assert_array_equal(oracle.collide_node(f, 1.3, G, "identity"), f)
 
 
+def _odd_even_perturbation(seed):
+    """A zero-mass, zero-momentum perturbation split into its even and odd parts."""
+    rng = np.random.default_rng(seed)
+    d = rng.standard_normal(19) * 1e-3
+    # project out mass and momentum (weighted least squares onto 1, c_x, c_y, c_z)
+    B = np.column_stack([np.ones(19), C])
+    d -= B @ np.linalg.lstsq(B, d, rcond=None)[0]
+    opp = np.array([0] + [i + 1 if i % 2 else i - 1 for i in range(1, 19)])
+    return 0.5 * (d + d[opp]), 0.5 * (d - d[opp])
+
+
+@pytest.mark.parametrize("omega", [0.7, 1.0, 1.7])
+def test_trt_equal_rates_is_bgk(omega):
+    rng = np.random.default_rng(31)
+    f = Wf * (1.0 + 0.01 * rng.standard_normal(19))
+    g = np.array([2e-4, -1e-4, 5e-5])
+    np.testing.assert_allclose(oracle.collide_node(f, omega, g, "trt", omega_minus=omega),
+                               oracle.collide_node(f, omega, g), rtol=0, atol=4e-17)
+
+
+@pytest.mark.parametrize("wp,wm", [(1.2, 0.4), (0.8, 1.9), (1.5, 1.5)])
+def test_trt_even_and_odd_parts_relax_at_their_rates(wp, wm):
+    """At equilibrium plus a mass- and momentum-free perturbation, rho and u do not
+    move, so the even part of the perturbation leaves scaled by 1 - w+ and the odd
+    part by 1 - w-; mass and momentum (+ rho g) stay exact."""
+    rho, u = 1.03, np.array([0.02, -0.01, 0.015])
+    feq = oracle.equilibrium(rho, u)
+    de, do = _odd_even_perturbation(7)
+    out = oracle.collide_node(feq + de + do, wp, (0, 0, 0), "trt", omega_minus=wm)
+    np.testing.assert_allclose(out, feq + (1 - wp) * de + (1 - wm) * do, rtol=0, atol=6e-17)
+    g = np.array([1e-4, 3e-5, -2e-4])
+    f = feq + de + do
+    fs = oracle.collide_node(f, wp, g, "trt", omega_minus=wm)
+    assert abs(fs.sum() - f.sum()) <= 4 * np.finfo(float).eps * rho
+    np.testing.assert_allclose(C.T @ fs, C.T @ f + f.sum() * g, rtol=0, atol=4e-16)
+
+
 # ---------------------------------------------------------------- propagation = permutation
 def _numpy_pull_permutation(B, solid):
     """A[i][x] = B[i][x - c_i], or B[opp i][x] when x - c_i is solid (periodic box)."""
@@ -205,13 +244,14 @@ def test_rest_state_is_fixed_point():
     np.testing.assert_allclose(f, f0, rtol=0, atol=2e-16)
 
 
-def _poiseuille(omega, nz=32, steps=None):
+def _poiseuille(omega, nz=32, steps=None, omega_minus=None):
     solid = lbm_inputs.channel_mask(2, 2, nz)
     nu = (1.0 / omega - 0.5) / 3.0
     H = nz - 2
     steps = steps or int(5 * H * H / nu)
     f = oracle.init_equilibrium(lbm_inputs.rho_u_field(solid.shape), solid)
-    f = oracle.run_ts(f, solid, steps, omega, G)
+    collider = "bgk" if omega_minus is None else "trt"
+    f = oracle.run_ts(f, solid, steps, omega, G, collider=collider, omega_minus=omega_minus)
     _, u = oracle.macroscopic(f, solid, G)
     ux = u[0, 1:-1, 0, 0]
     z = np.arange(1, nz - 1, dtype=np.float64)
@@ -241,6 +281,24 @@ def test_poiseuille_exact_at_magic_relaxation():
     assert np.abs(ux - exact).max() / exact.max() < 1e-9
 
 
+@pytest.mark.parametrize("omega", [0.8, 1.0, 1.6])
+def test_trt_poiseuille_exact_at_lambda_3_16(omega):
+    """With TRT the bounce-back wall position depends only on Lambda: at
+    Lambda = 3/16 the half-way parabola is exact for any w+."""
+    wm = oracle.trt_omega_minus(omega, 3.0 / 16.0)
+    _, _, ux, exact, _ = _poiseuille(omega, omega_minus=wm)
+    assert np.abs(ux - exact).max() / exact.max() < 1e-9
+
+
+def test_trt_poiseuille_slip_follows_lambda():
+    """Away from 3/16 the slip is (g/nu)(16 Lambda - 3)/24, set by w- at fixed w+."""
+    omega = 1.0
+    for lam in (0.05, 0.5):
+        _, _, ux, exact, nu = _poiseuille(omega, omega_minus=oracle.trt_omega_minus(omega, lam))
+        slip = (ux - exact).mean()
+        assert abs(slip / (G[0] / nu * (16 * lam - 3) / 24) - 1) < 5e-3
+
+
 def test_slit_permeability_closed_form():
     """Darcy k of a slit of width H in a box of height nz: H^3/(12 nz) (1 + 1/(2 H^2))."""
     omega = 1.0 / (0.5 + math.sqrt(3.0) / 4.0)
@@ -253,8 +311,11 @@ def test_slit_permeability_closed_form():
     assert abs(k / want - 1) < 1e-9
 
 
-@pytest.mark.parametrize("omega,tol", [(1.0, 1e-5), (1.6, 3e-3)])
-def test_shear_wave_viscosity(omega, tol):
+@pytest.mark.parametrize("omega,tol,omega_minus", [(1.0, 1e-5, None), (1.6, 3e-3, None), (1.0, 3e-3, 1.6),
+                                                   (1.0, 5e-3, 0.5)])
+def test_shear_wave_viscosity(omega, tol, omega_minus):
+    """Decay rate nu k^2 (up to O(k^2) relative terms) with nu = (1/w - 1/2)/3;
+    under TRT only w+ sets nu (w- would change it four-fold here)."""
     L = 64
     solid = np.zeros((L, 1, 1), np.uint8)
     z = np.arange(L)
@@ -267,9 +328,10 @@ def test_shear_wave_viscosity(omega, tol):
         _, u = oracle.macroscopic(f, solid, (0, 0, 0))
         return (u[0, :, 0, 0] * np.sin(k * z)).sum() * 2 / L
 
-    f = oracle.run_ts(f, solid, 200, omega, (0, 0, 0))
+    kw = dict(collider="bgk" if omega_minus is None else "trt", omega_minus=omega_minus)
+    f = oracle.run_ts(f, solid, 200, omega, (0, 0, 0), **kw)
     a1 = amp(f)
-    f = oracle.run_ts(f, solid, 2000, omega, (0, 0, 0))
+    f = oracle.run_ts(f, solid, 2000, omega, (0, 0, 0), **kw)
     a2 = amp(f)
     nu = (1.0 / omega - 0.5) / 3.0
     assert abs(-math.log(a2 / a1) / (k * k * 2000) / nu - 1) < tol
