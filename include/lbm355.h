@@ -12,8 +12,9 @@
  * each on a directly addressed full grid and on an indirectly addressed
  * sparse grid of fluid nodes with an 18-entry neighbour index array (Sec. 1),
  * in SoA and AoS layouts (Sec. 1).  The collision is BGK with the Guo body
- * force; PDFs are stored in FP64, FP32, or as shifted deviations
- * (f_i - w_i) * sigma in FP16 or FP32 (FP32 arithmetic).
+ * force, or the two-relaxation-time (TRT) collision of the paper's solver
+ * (Sec. 10) with the same force; PDFs are stored in FP64, FP32, or as shifted
+ * deviations (f_i - w_i) * sigma in FP16 or FP32 (FP32 arithmetic).
  *
  * Conventions shared by every call:
  *   - All functions return an int status (LBM_OK or a negative LBM_E_*);
@@ -74,7 +75,7 @@ enum lbm_scheme {
     LBM_CG = 6,      /* compressed grid, Sec. 4                            */
     LBM_SWAP = 7     /* swap algorithm, Sec. 5                             */
 };
-enum lbm_collider { LBM_IDENTITY = 0, LBM_BGK = 1 };
+enum lbm_collider { LBM_IDENTITY = 0, LBM_BGK = 1, LBM_TRT = 2 };
 
 /* ---------------------------------------------------------------- grid */
 typedef struct lbm_grid lbm_grid;
@@ -102,6 +103,9 @@ typedef struct {
                             (Sec. 10); blocked orders keep most neighbours of a
                             workgroup's nodes in its own cache lines.             */
     int32_t reserved;    /* set to 0 */
+    double trt_lambda;   /* TRT parameter Lambda = (1/w+ - 1/2)(1/w- - 1/2) > 0
+                            used by the LBM_TRT collider (w+ = omega); 3/16
+                            makes half-way bounce-back exact for Poiseuille flow */
 } lbm_grid_desc;
 
 typedef struct {
@@ -226,8 +230,12 @@ int lbm_init_equilibrium(lbm_grid *g, const double *d_rho_u, void *stream);
  * and propagation kernels (Sec. 2); OS push/pull one fused kernel followed by
  * the lattice swap (Sec. 3); AA the even kernel at even t and the odd kernel
  * at odd t (Sec. 6); ET one kernel with the parity's direction table, the
- * swap of opposing directions being the parity flip (Sec. 7).  LBM_IDENTITY
- * replaces the collision by the identity (pure propagation).  Asynchronous. */
+ * swap of opposing directions being the parity flip (Sec. 7).  LBM_BGK
+ * relaxes every non-equilibrium part with omega; LBM_TRT relaxes the parts
+ * even in c with w+ = omega and the odd parts with w- = 1/(Lambda/(1/omega -
+ * 1/2) + 1/2), Lambda = desc.trt_lambda (LBM_E_ARG unless > 0); the force
+ * term is split the same way.  LBM_IDENTITY replaces the collision by the
+ * identity (pure propagation).  Asynchronous. */
 int lbm_step(lbm_grid *g, int32_t scheme, int32_t collider, int64_t n_steps, void *stream);
 
 /* Number of completed time steps since bind/set/init. */
@@ -265,8 +273,9 @@ int lbm_batch_destroy(lbm_batch *b);
 /* Adds a grid (indirect, SoA, bound to LBM_AA, the batch's precision, state
  * initialised) in the first free slot, written to *slot_out.  The grid keeps
  * its step counter; its parity decides which AA kernel each of its nodes
- * runs.  Errors: LBM_E_STATE when no slot or tile space is left,
- * LBM_E_UNSUPPORTED for other grid kinds. */
+ * runs; its nodes collide with BGK at the grid's omega and force.  Errors:
+ * LBM_E_STATE when no slot or tile space is left, LBM_E_UNSUPPORTED for
+ * other grid kinds. */
 int lbm_batch_add(lbm_batch *b, lbm_grid *g, int32_t *slot_out);
 
 /* Empties a slot; the grid's state stays where it is. */

@@ -20,7 +20,7 @@ DIRECT, INDIRECT = 0, 1
 SOA, AOS = 0, 1
 F64, F32, F16S, F32S = 0, 1, 2, 3
 TS, OS_PUSH, OS_PULL, AA, ET, OS_NT, CG, SWAP = range(8)
-IDENTITY, BGK = 0, 1
+IDENTITY, BGK, TRT = 0, 1, 2
 OPT_XCD_REMAP = 1
 OPT_PITCH_PAD = 2
 OPT_WG_LDS = 3
@@ -31,7 +31,7 @@ SCHEMES = {"ts": TS, "os_push": OS_PUSH, "os_pull": OS_PULL, "aa": AA, "et": ET,
 ADDRESSING = {"direct": DIRECT, "indirect": INDIRECT}
 LAYOUTS = {"soa": SOA, "aos": AOS}
 PRECISIONS = {"f64": F64, "f32": F32, "f16s": F16S, "f32s": F32S}
-COLLIDERS = {"identity": IDENTITY, "bgk": BGK}
+COLLIDERS = {"identity": IDENTITY, "bgk": BGK, "trt": TRT}
 
 
 class GridDesc(ctypes.Structure):
@@ -39,7 +39,7 @@ class GridDesc(ctypes.Structure):
                 ("addressing", ctypes.c_int32), ("layout", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("wall_z", ctypes.c_int32), ("et_ghosts", ctypes.c_int32),
                 ("omega", ctypes.c_double), ("g", ctypes.c_double * 3), ("f16_scale", ctypes.c_double),
-                ("brick", ctypes.c_int32 * 3), ("reserved", ctypes.c_int32)]
+                ("brick", ctypes.c_int32 * 3), ("reserved", ctypes.c_int32), ("trt_lambda", ctypes.c_double)]
 
 
 class Sizes(ctypes.Structure):

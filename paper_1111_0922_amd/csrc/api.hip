@@ -118,6 +118,7 @@ KArgs base_args(const lbm_grid *g)
     a.gy = d.g[1];
     a.gz = d.g[2];
     a.sigma = (d.precision == LBM_F16S || d.precision == LBM_F32S) ? d.f16_scale : 1.0;
+    a.omega_minus = d.omega; // BGK; lbm_step sets the TRT rate
     return a;
 }
 
@@ -406,13 +407,18 @@ int lbm_step(lbm_grid *g, int32_t scheme, int32_t collider, int64_t n_steps, voi
     int rc = check_bound(g);
     if (rc) return rc;
     if (scheme != g->scheme) return fail(LBM_E_STATE, "scheme %d requested, %d bound", scheme, g->scheme);
-    if (collider != LBM_BGK && collider != LBM_IDENTITY) return fail(LBM_E_ARG, "unknown collider");
+    if (collider != LBM_BGK && collider != LBM_IDENTITY && collider != LBM_TRT) return fail(LBM_E_ARG, "unknown collider");
+    if (collider == LBM_TRT && !(g->d.trt_lambda > 0.0)) return fail(LBM_E_ARG, "TRT needs trt_lambda > 0");
     if (n_steps < 0) return fail(LBM_E_ARG, "negative step count");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const PrecTable &tb = table(g->d.precision);
-    const int A = g->d.addressing, L = g->d.layout, C = collider;
+    const int A = g->d.addressing, L = g->d.layout, C = collider == LBM_IDENTITY ? 0 : 1;
     const uint32_t nb = node_blocks(g);
     KArgs a = base_args(g);
+    if (collider == LBM_TRT) {
+        // Lambda = (1/w+ - 1/2)(1/w- - 1/2)
+        a.omega_minus = 1.0 / (g->d.trt_lambda / (1.0 / g->d.omega - 0.5) + 0.5);
+    }
     for (int64_t k = 0; k < n_steps; ++k) {
         switch (g->scheme) {
         case LBM_TS:

@@ -33,6 +33,7 @@ struct SlotDesc {
     int64_t pitch;
     int64_t idx_pitch;
     double omega, gx, gy, gz, sigma;
+    double omega_minus;
     uint32_t n_nodes;
     int32_t t0;          // completed steps of the slot when the run starts
     uint32_t tile_begin; // its tiles (and reduction partials) are contiguous
@@ -60,6 +61,7 @@ __device__ __forceinline__ KArgs slot_args(const SlotDesc &sd)
     a.gy = sd.gy;
     a.gz = sd.gz;
     a.sigma = sd.sigma;
+    a.omega_minus = sd.omega_minus;
     return a;
 }
 
@@ -295,6 +297,7 @@ int lbm_batch_add(lbm_batch *b, lbm_grid *g, int32_t *slot_out)
     sd.gy = a.gy;
     sd.gz = a.gz;
     sd.sigma = a.sigma;
+    sd.omega_minus = a.omega_minus;
     sd.n_nodes = (uint32_t)g->n_nodes;
     sd.n_tiles = (uint32_t)need;
     sd.active = 1;

@@ -1,13 +1,19 @@
-// collide.hpp -- BGK collision with the Guo body force, in registers.
+// collide.hpp -- BGK / TRT collision with the Guo body force, in registers.
 //
-// The paper's solver uses a TRT collision (Sec. 10) and does not print an
-// operator; this library implements single-relaxation BGK:
+// The paper's solver uses a two-relaxation-time (TRT) collision (Sec. 10,
+// ref. [15]) and does not print an operator.  With
 //   rho = sum f_i,  j = sum c_i f_i,  u = (j + rho g / 2) / rho
 //   f_i^eq = w_i rho (1 + 3 c_i.u + 9/2 (c_i.u)^2 - 3/2 u.u)
-//   S_i = (1 - omega/2) w_i [3 (c_i - u) + 9 (c_i.u) c_i] . (rho g)      (Guo, Zheng & Shi 2002)
-//   f_i* = f_i - omega (f_i - f_i^eq) + S_i
-// evaluated per pair of opposite directions, whose equilibria and sources
-// split into a part even in c_i (shared) and a part odd in c_i (sign flip).
+//   S_i    = w_i [3 (c_i - u) + 9 (c_i.u) c_i] . (rho g)              (Guo, Zheng & Shi 2002)
+// and the even/odd parts of a pair of opposite directions i, i',
+//   a^+ = (a_i + a_i')/2,  a^- = (a_i - a_i')/2,
+// the update is
+//   f_i* = f_i - w+ (f^+ - eq^+) - w- (f^- - eq^-) + (1 - w+/2) S^+ + (1 - w-/2) S^-
+// with w+ = omega (viscosity nu = (1/omega - 1/2)/3) and w- set by the
+// parameter Lambda = (1/w+ - 1/2)(1/w- - 1/2).  BGK is the case w- = w+,
+// evaluated by the same code, so BGK and TRT with equal rates agree bit for
+// bit.  The even and odd parts of the equilibrium and of the source are
+// formed directly (they are the terms of even and odd degree in c_i).
 //
 // SHIFTED = true works on v_i = sigma (f_i - w_i) (the FP16 storage form):
 //   rho = 1 + sum v / sigma, j = sum c v / sigma,
@@ -20,21 +26,18 @@
 
 namespace lbm {
 
-// fused multiply-add in the arithmetic type (one rounding)
-__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
 template <typename T>
 struct CollideParams {
-    T omega, gx, gy, gz;
+    T omega, gx, gy, gz;   // omega = w+ (shear relaxation)
     T sigma, inv_sigma;
+    T omega_minus;         // w- (odd moments); equal to omega for BGK
 };
 
 template <typename T, bool SHIFTED>
 __device__ __forceinline__ void collide_bgk(T (&v)[Q], const CollideParams<T> &p)
 {
-    // No implicit contraction: the fused multiply-adds are written out, so
-    // every kernel this is inlined into rounds identically and all schemes,
+    // No implicit contraction: every operation rounds as written, so every
+    // kernel this is inlined into computes identical bits and all schemes,
     // layouts and addressings produce bit-identical states.
 #pragma clang fp contract(off)
     // moments, fixed summation order
@@ -67,10 +70,12 @@ __device__ __forceinline__ void collide_bgk(T (&v)[Q], const CollideParams<T> &p
     const T Fx = rho * p.gx, Fy = rho * p.gy, Fz = rho * p.gz;
     const T uu = ux * ux + uy * uy + uz * uz;
     const T uF = ux * Fx + uy * Fy + uz * Fz;
-    const T om = p.omega;
-    const T kf = T(1) - T(0.5) * om;            // Guo prefactor (1 - omega/2)
-    const T sc = SHIFTED ? p.sigma : T(1);      // scale of the stored form
-    const T base = SHIFTED ? drho : rho;        // rho (plain) or rho - 1 (shifted)
+    const T om = p.omega;                        // w+
+    const T omm = p.omega_minus;                 // w-
+    const T kf = T(1) - T(0.5) * om;             // Guo prefactor of the even source part (1 - w+/2)
+    const T kfm = T(1) - T(0.5) * omm;           // and of the odd part (1 - w-/2)
+    const T sc = SHIFTED ? p.sigma : T(1);       // scale of the stored form
+    const T base = SHIFTED ? drho : rho;         // rho (plain) or rho - 1 (shifted)
 
     // moving directions, in pairs of opposites; the sum of the new values is
     // kept to close the rest direction below
@@ -89,11 +94,14 @@ __device__ __forceinline__ void collide_bgk(T (&v)[Q], const CollideParams<T> &p
         const T eq_even = sc * w * (base + rho * (T(4.5) * cu * cu - T(1.5) * uu));
         const T eq_odd = sc * w * rho * T(3) * cu;
         const T src_even = sc * kf * w * (T(9) * cu * cF - T(3) * uF);
-        const T src_odd = sc * kf * w * T(3) * cF;
+        const T src_odd = sc * kfm * w * T(3) * cF;
         const T vi = v[i], vk = v[k];
-        // f* = f - omega (f - f^eq) + S
-        v[i] = fmadd(-om, vi - (eq_even + eq_odd), vi) + (src_even + src_odd);
-        v[k] = fmadd(-om, vk - (eq_even - eq_odd), vk) + (src_even - src_odd);
+        const T ve = T(0.5) * (vi + vk), vo = T(0.5) * (vi - vk);
+        // relaxation of the even and odd parts: r = w+ (f^+ - eq^+), s = w- (f^- - eq^-)
+        const T r = om * (ve - eq_even);
+        const T q = omm * (vo - eq_odd);
+        v[i] = ((vi - r) - q) + (src_even + src_odd);
+        v[k] = ((vk - r) + q) + (src_even - src_odd);
         moving += v[i] + v[k];
     }
     // Rest direction by mass conservation: the BGK update with the Guo term

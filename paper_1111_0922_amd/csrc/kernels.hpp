@@ -119,6 +119,7 @@ struct KArgs {
     uint32_t lds_bytes;    // dynamic LDS reserved per update workgroup (caps residency)
     int32_t row_staged;    // direct SoA, nx divides BLOCK: x-shifted accesses go through LDS
     double omega, gx, gy, gz, sigma;
+    double omega_minus;    // TRT odd-moment rate (== omega for BGK)
     // canonical transfer / reductions
     double *canon;
     const double *canon_in;
@@ -436,6 +437,7 @@ __device__ __forceinline__ void update_direct_staged(const KArgs &a)
         p.gz = (ct)a.gz;
         p.sigma = (ct)a.sigma;
         p.inv_sigma = (ct)(1.0 / a.sigma);
+        p.omega_minus = (ct)a.omega_minus;
         collide_bgk<ct, S::shifted>(v, p);
     }
 #pragma unroll
@@ -495,6 +497,7 @@ __device__ __forceinline__ void update_node(const KArgs &a, uint32_t n)
         p.gz = (ct)a.gz;
         p.sigma = (ct)a.sigma;
         p.inv_sigma = (ct)(1.0 / a.sigma);
+        p.omega_minus = (ct)a.omega_minus;
         collide_bgk<ct, S::shifted>(v, p);
     }
     if constexpr (need_r(R) != 0 && need_w(W) != 0) nd.refresh(); // gather and scatter both use the ids
@@ -563,6 +566,7 @@ __device__ __forceinline__ void update_aos_staged(const KArgs &a)
             p.gz = (ct)a.gz;
             p.sigma = (ct)a.sigma;
             p.inv_sigma = (ct)(1.0 / a.sigma);
+        p.omega_minus = (ct)a.omega_minus;
             collide_bgk<ct, S::shifted>(v, p);
         }
     }

@@ -53,7 +53,7 @@ class Grid:
     """One lattice on one GPU: geometry, index, bound buffers of one scheme."""
 
     def __init__(self, nx, ny, nz, *, addressing="direct", layout="soa", precision="f64", wall_z=False,
-                 et_ghosts=False, omega=1.0, g=(0.0, 0.0, 0.0), f16_scale=1.0, brick=None, device=None):
+                 et_ghosts=False, omega=1.0, g=(0.0, 0.0, 0.0), f16_scale=1.0, brick=None, trt_lambda=3.0 / 16.0, device=None):
         self.lib = L.load()
         self.device = torch.device(device) if device is not None else torch.device("cuda")
         d = L.GridDesc()
@@ -69,6 +69,7 @@ class Grid:
         d.f16_scale = float(f16_scale)
         for k in range(3):
             d.brick[k] = int(brick[k]) if brick is not None else 0
+        d.trt_lambda = float(trt_lambda)
         self.desc = d
         self.shape = (int(nz), int(ny), int(nx))
         self.addressing, self.layout, self.precision = addressing, layout, precision

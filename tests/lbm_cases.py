@@ -12,7 +12,7 @@ PRECISIONS = ["f64", "f32", "f16s", "f32s"]
 
 
 def make_grid(solid, scheme, *, addressing="direct", layout="soa", precision="f64", omega=1.0,
-              g=(0.0, 0.0, 0.0), f16_scale=1.0, wall_z=None, brick=None):
+              g=(0.0, 0.0, 0.0), f16_scale=1.0, wall_z=None, brick=None, trt_lambda=3.0 / 16.0):
     """Grid whose fluid nodes are the fluid cells of `solid` (uint8[nz, ny, nx]).
 
     Direct grids support a fully periodic box or the channel (solid planes
@@ -27,7 +27,8 @@ def make_grid(solid, scheme, *, addressing="direct", layout="soa", precision="f6
             assert not solid.any(), "direct grids hold a periodic box or a channel"
     grid = P.Grid(nx, ny, nz, addressing=addressing, layout=layout, precision=precision,
                   wall_z=bool(wall_z) if addressing == "direct" else False,
-                  et_ghosts=(scheme == "et"), omega=omega, g=g, f16_scale=f16_scale, brick=brick)
+                  et_ghosts=(scheme == "et"), omega=omega, g=g, f16_scale=f16_scale, brick=brick,
+                  trt_lambda=trt_lambda)
     if addressing == "indirect":
         grid.build_idx(torch.from_numpy(np.ascontiguousarray(solid, dtype=np.uint8)).cuda())
     grid.bind(scheme)
