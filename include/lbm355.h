@@ -166,8 +166,12 @@ int lbm_set_params(lbm_grid *g, double omega, const double g_acc[3]);
  *     power of two no larger than 256, every workgroup holds whole x-rows and
  *     moves the x-shifted PDFs through LDS, so that all global accesses are
  *     aligned; 0 forces the plain kernels.
+ *   LBM_OPT_PAIR (0/1, default 1): on a direct SoA grid with FP16 storage
+ *     whose nx is a power of two in [2, 512], every lane updates two
+ *     x-neighbours and moves them as one 32-bit word per direction; 0 forces
+ *     one node per lane.
  * Errors: LBM_E_ARG for an unknown option or a value out of range. */
-enum { LBM_OPT_XCD_REMAP = 1, LBM_OPT_PITCH_PAD = 2, LBM_OPT_WG_LDS = 3, LBM_OPT_ROW_STAGE = 4 };
+enum { LBM_OPT_XCD_REMAP = 1, LBM_OPT_PITCH_PAD = 2, LBM_OPT_WG_LDS = 3, LBM_OPT_ROW_STAGE = 4, LBM_OPT_PAIR = 5 };
 int lbm_set_option(lbm_grid *g, int32_t option, int64_t value);
 
 /* Buffer sizes of `scheme` on this grid (host struct out).  For an indirect

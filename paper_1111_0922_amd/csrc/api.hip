@@ -113,12 +113,16 @@ KArgs base_args(const lbm_grid *g)
     // whole x-rows per workgroup: nx a power of two dividing the workgroup size
     a.row_staged = (d.addressing == LBM_DIRECT && d.layout == LBM_SOA && g->row_stage && d.nx <= BLOCK &&
                     (d.nx & (d.nx - 1)) == 0) ? 1 : 0;
+    // two nodes per lane for 16-bit storage: nx a power of two dividing 2 * BLOCK
+    a.pair = (d.addressing == LBM_DIRECT && d.layout == LBM_SOA && d.precision == LBM_F16S && g->pair &&
+              d.nx >= 2 && d.nx <= 2 * BLOCK && (d.nx & (d.nx - 1)) == 0) ? 1 : 0;
     a.omega = d.omega;
     a.gx = d.g[0];
     a.gy = d.g[1];
     a.gz = d.g[2];
     a.sigma = (d.precision == LBM_F16S || d.precision == LBM_F32S) ? d.f16_scale : 1.0;
     a.omega_minus = d.omega; // BGK; lbm_step sets the TRT rate
+    set_collision(a);
     return a;
 }
 
@@ -216,6 +220,10 @@ int lbm_set_option(lbm_grid *g, int32_t option, int64_t value)
     }
     if (option == LBM_OPT_ROW_STAGE) {
         g->row_stage = value ? 1 : 0;
+        return LBM_OK;
+    }
+    if (option == LBM_OPT_PAIR) {
+        g->pair = value ? 1 : 0;
         return LBM_OK;
     }
     if (option == LBM_OPT_WG_LDS) {
@@ -413,11 +421,12 @@ int lbm_step(lbm_grid *g, int32_t scheme, int32_t collider, int64_t n_steps, voi
     hipStream_t s = static_cast<hipStream_t>(stream);
     const PrecTable &tb = table(g->d.precision);
     const int A = g->d.addressing, L = g->d.layout, C = collider == LBM_IDENTITY ? 0 : 1;
-    const uint32_t nb = node_blocks(g);
     KArgs a = base_args(g);
+    const uint32_t nb = a.pair ? (uint32_t)((g->n_nodes + 2 * BLOCK - 1) / (2 * BLOCK)) : node_blocks(g);
     if (collider == LBM_TRT) {
         // Lambda = (1/w+ - 1/2)(1/w- - 1/2)
         a.omega_minus = 1.0 / (g->d.trt_lambda / (1.0 / g->d.omega - 0.5) + 0.5);
+        set_collision(a);
     }
     for (int64_t k = 0; k < n_steps; ++k) {
         switch (g->scheme) {

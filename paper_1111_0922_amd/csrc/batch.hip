@@ -34,6 +34,8 @@ struct SlotDesc {
     int64_t idx_pitch;
     double omega, gx, gy, gz, sigma;
     double omega_minus;
+    CollideParams<double> cpd;
+    CollideParams<float> cpf;
     uint32_t n_nodes;
     int32_t t0;          // completed steps of the slot when the run starts
     uint32_t tile_begin; // its tiles (and reduction partials) are contiguous
@@ -62,6 +64,8 @@ __device__ __forceinline__ KArgs slot_args(const SlotDesc &sd)
     a.gz = sd.gz;
     a.sigma = sd.sigma;
     a.omega_minus = sd.omega_minus;
+    a.cpd = sd.cpd;
+    a.cpf = sd.cpf;
     return a;
 }
 
@@ -298,6 +302,8 @@ int lbm_batch_add(lbm_batch *b, lbm_grid *g, int32_t *slot_out)
     sd.gz = a.gz;
     sd.sigma = a.sigma;
     sd.omega_minus = a.omega_minus;
+    sd.cpd = a.cpd;
+    sd.cpf = a.cpf;
     sd.n_nodes = (uint32_t)g->n_nodes;
     sd.n_tiles = (uint32_t)need;
     sd.active = 1;

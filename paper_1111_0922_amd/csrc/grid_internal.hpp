@@ -28,6 +28,7 @@ struct lbm_grid {
     int64_t pitch_pad = 0; // extra SoA elements between direction arrays
     int64_t wg_lds = -1;   // dynamic LDS reserved per update workgroup (-1: per-precision default)
     int row_stage = 1;     // allow the row-staged direct SoA kernels
+    int pair = 1;          // allow two nodes per lane (16-bit direct SoA)
 };
 
 namespace lbm_host {

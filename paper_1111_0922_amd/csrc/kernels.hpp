@@ -118,14 +118,33 @@ struct KArgs {
     int32_t remap;         // XCD-aware block order
     uint32_t lds_bytes;    // dynamic LDS reserved per update workgroup (caps residency)
     int32_t row_staged;    // direct SoA, nx divides BLOCK: x-shifted accesses go through LDS
+    int32_t pair;          // direct SoA, 16-bit storage, nx divides 2 * BLOCK: two nodes per lane
     double omega, gx, gy, gz, sigma;
     double omega_minus;    // TRT odd-moment rate (== omega for BGK)
+    CollideParams<double> cpd; // collision factors (set_collision) for FP64
+    CollideParams<float> cpf;  // and for FP32 compute
     // canonical transfer / reductions
     double *canon;
     const double *canon_in;
     const double *rho_u;
     double *partials;
 };
+
+// Collision factors from omega, omega_minus, g and sigma (host side).
+inline void set_collision(KArgs &a)
+{
+    a.cpd = collide_params<double>(a.omega, a.omega_minus, a.gx, a.gy, a.gz, a.sigma);
+    a.cpf = collide_params<float>(a.omega, a.omega_minus, a.gx, a.gy, a.gz, a.sigma);
+}
+
+template <typename T>
+__device__ __forceinline__ const CollideParams<T> &cparams(const KArgs &a)
+{
+    if constexpr (sizeof(T) == 8)
+        return a.cpd;
+    else
+        return a.cpf;
+}
 
 // ------------------------------------------------------------------ block order
 // Workgroups are dispatched round-robin over the 8 XCDs (block b on XCD
@@ -430,15 +449,8 @@ __device__ __forceinline__ void update_direct_staged(const KArgs &a)
     }
     __syncthreads();
     if constexpr (COLL == 1 && KIND != K_TS_STREAM) {
-        CollideParams<ct> p;
-        p.omega = (ct)a.omega;
-        p.gx = (ct)a.gx;
-        p.gy = (ct)a.gy;
-        p.gz = (ct)a.gz;
-        p.sigma = (ct)a.sigma;
-        p.inv_sigma = (ct)(1.0 / a.sigma);
-        p.omega_minus = (ct)a.omega_minus;
-        collide_bgk<ct, S::shifted>(v, p);
+        const CollideParams<ct> &p = cparams<ct>(a);
+        collide_node<ct, S::shifted>(v, p);
     }
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -459,6 +471,110 @@ __device__ __forceinline__ void update_direct_staged(const KArgs &a)
             int j, sx, sy, sz;
             write_off<W>(nd, i, j, sx, sy, sz);
             if (sx != 0 && valid) pdf_store<true>(dst + elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch), xs[xslot(i) < 0 ? 0 : xslot(i)][t]);
+        }
+    }
+}
+
+// Direct SoA update of two x-neighbours (x even, x + 1) per lane, for 16-bit
+// storage: the pair's values of one direction form one aligned 32-bit word,
+// so each load or store of a wavefront covers 256 contiguous bytes instead of
+// 128.  Both nodes share y and z, hence every bounce-back decision.  nx is a
+// power of two dividing 2 * BLOCK, so a workgroup holds whole x-rows and the
+// x-shifts go through LDS as in update_direct_staged (each lane deposits or
+// picks up two 16-bit values).  Per node the arithmetic is that of the
+// one-node kernels, so the results are bit-identical.
+typedef uint16_t __attribute__((may_alias)) u16_alias;
+typedef uint32_t __attribute__((may_alias)) u32_alias;
+
+template <int PREC, int KIND, int COLL>
+__device__ __forceinline__ void update_direct_pair(const KArgs &a)
+{
+    using S = Store<PREC>;
+    using ct = typename S::ct;
+    static_assert(sizeof(typename S::st) == 2, "two 16-bit values per 32-bit word");
+    constexpr int R = rmap_of(KIND);
+    constexpr int W = wmap_of(KIND);
+    constexpr bool shifts = !(R == R_LOCAL && (W == W_LOCAL || W == W_AAEVEN));
+    constexpr uint32_t NP = 2 * BLOCK; // nodes per workgroup
+    __shared__ uint32_t xw[shifts ? NXSLOT : 1][shifts ? BLOCK : 1];
+    const uint32_t t = threadIdx.x;
+    const uint32_t p = 2 * t;          // the pair's first node within the workgroup
+    const uint32_t n = logical_block(a.remap) * NP + p;
+    const bool valid = n < a.n_nodes;  // n_nodes is a multiple of nx, so pairs are whole
+    const uint32_t nx = (uint32_t)a.nx;
+    const uint32_t xl = p & (nx - 1), row = p - xl;
+    Node<A_DIRECT, 0> nd;
+    nd.init(a, valid ? n : 0);
+    const uint32_t *src = static_cast<const uint32_t *>(a.src);
+    uint32_t *dst = static_cast<uint32_t *>(a.dst);
+    auto h2f = [](uint32_t h) { return S::load(__builtin_bit_cast(_Float16, (uint16_t)h)); };
+    auto f2h = [](ct v) { return (uint32_t)__builtin_bit_cast(uint16_t, S::save(v)); };
+    auto lds16 = [&](int slot) { return reinterpret_cast<u16_alias *>(&xw[slot][0]); };
+    // all 19 word loads first, at the pair's own x (unconditional: a lane
+    // past n_nodes addresses node 0 and never stores)
+    uint32_t raw[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        int j, sx, sy, sz;
+        read_off<R>(nd, i, j, sx, sy, sz);
+        raw[i] = pdf_load<true>(src + (elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch) >> 1));
+    }
+    ct v0[Q], v1[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        int j, sx, sy, sz;
+        read_off<R>(nd, i, j, sx, sy, sz);
+        if (shifts && xslot(i) >= 0 && sx != 0) {
+            reinterpret_cast<u32_alias *>(&xw[xslot(i) < 0 ? 0 : xslot(i)][0])[t] = raw[i];
+        } else {
+            v0[i] = h2f(raw[i] & 0xffffu);
+            v1[i] = h2f(raw[i] >> 16);
+        }
+    }
+    if constexpr (shifts) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            if (xslot(i) >= 0) {
+                int j, sx, sy, sz;
+                read_off<R>(nd, i, j, sx, sy, sz);
+                if (sx != 0) {
+                    const u16_alias *h = lds16(xslot(i) < 0 ? 0 : xslot(i));
+                    v0[i] = h2f(h[row + ((xl + (uint32_t)sx) & (nx - 1))]);
+                    v1[i] = h2f(h[row + ((xl + 1u + (uint32_t)sx) & (nx - 1))]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if constexpr (COLL == 1 && KIND != K_TS_STREAM) {
+        const CollideParams<ct> &cp = cparams<ct>(a);
+        collide_node<ct, S::shifted>(v0, cp);
+        collide_node<ct, S::shifted>(v1, cp);
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        int j, sx, sy, sz;
+        write_off<W>(nd, i, j, sx, sy, sz);
+        if (shifts && xslot(i) >= 0 && sx != 0) {
+            u16_alias *h = lds16(xslot(i) < 0 ? 0 : xslot(i));
+            h[row + ((xl + (uint32_t)sx) & (nx - 1))] = (uint16_t)f2h(v0[i]);
+            h[row + ((xl + 1u + (uint32_t)sx) & (nx - 1))] = (uint16_t)f2h(v1[i]);
+            continue;
+        }
+        if (valid) pdf_store<true>(dst + (elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch) >> 1), f2h(v0[i]) | (f2h(v1[i]) << 16));
+    }
+    if constexpr (shifts) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            if (xslot(i) >= 0) {
+                int j, sx, sy, sz;
+                write_off<W>(nd, i, j, sx, sy, sz);
+                if (sx != 0 && valid)
+                    pdf_store<true>(dst + (elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch) >> 1),
+                                    (uint32_t)reinterpret_cast<const u32_alias *>(&xw[xslot(i) < 0 ? 0 : xslot(i)][0])[t]);
+            }
         }
     }
 }
@@ -490,15 +606,8 @@ __device__ __forceinline__ void update_node(const KArgs &a, uint32_t n)
         v[i] = S::load(pdf_load<NT>(src + elem<LAY>(j, c, a.pitch)));
     }
     if constexpr (COLL == 1 && KIND != K_TS_STREAM) {
-        CollideParams<ct> p;
-        p.omega = (ct)a.omega;
-        p.gx = (ct)a.gx;
-        p.gy = (ct)a.gy;
-        p.gz = (ct)a.gz;
-        p.sigma = (ct)a.sigma;
-        p.inv_sigma = (ct)(1.0 / a.sigma);
-        p.omega_minus = (ct)a.omega_minus;
-        collide_bgk<ct, S::shifted>(v, p);
+        const CollideParams<ct> &p = cparams<ct>(a);
+        collide_node<ct, S::shifted>(v, p);
     }
     if constexpr (need_r(R) != 0 && need_w(W) != 0) nd.refresh(); // gather and scatter both use the ids
 #pragma unroll
@@ -559,15 +668,8 @@ __device__ __forceinline__ void update_aos_staged(const KArgs &a)
     }
     if (valid) {
         if constexpr (COLL == 1 && KIND != K_TS_STREAM) {
-            CollideParams<ct> p;
-            p.omega = (ct)a.omega;
-            p.gx = (ct)a.gx;
-            p.gy = (ct)a.gy;
-            p.gz = (ct)a.gz;
-            p.sigma = (ct)a.sigma;
-            p.inv_sigma = (ct)(1.0 / a.sigma);
-        p.omega_minus = (ct)a.omega_minus;
-            collide_bgk<ct, S::shifted>(v, p);
+            const CollideParams<ct> &p = cparams<ct>(a);
+            collide_node<ct, S::shifted>(v, p);
         }
     }
     if constexpr (local_w) {
@@ -599,6 +701,12 @@ __global__ void __launch_bounds__(BLOCK) k_update(KArgs a)
     constexpr int W = wmap_of(KIND);
     // kernels whose maps never shift along x need no staging
     constexpr bool shifts = !(R == R_LOCAL && (W == W_LOCAL || W == W_AAEVEN));
+    if constexpr (ADDR == A_DIRECT && LAY == L_SOA && sizeof(typename Store<PREC>::st) == 2) {
+        if (a.pair) {
+            update_direct_pair<PREC, KIND, COLL>(a);
+            return;
+        }
+    }
     if constexpr (ADDR == A_DIRECT && LAY == L_SOA && shifts) {
         if (a.row_staged) {
             update_direct_staged<PREC, KIND, COLL>(a);

@@ -123,3 +123,27 @@ def test_permeability_chain_to_steady_state():
         m = from_device(grid.moments())
         k = nu * phi * ((m[1] + 0.5 * m[0] * g) / m[0]) / g
         assert abs(k - k_oracle) / k_oracle <= bound, (precision, k, k_oracle)
+
+
+@pytest.mark.parametrize("scheme", ["ts", "os_push", "os_pull", "aa", "et"])
+@pytest.mark.parametrize("shape,walls", [((32, 32, 32), True), ((2, 3, 5), False), ((4, 4, 2), False),
+                                         ((64, 6, 5), True), ((512, 3, 4), True), ((256, 5, 3), False)])
+def test_fp16_pair_kernels_bit_identical_to_one_node(scheme, shape, walls):
+    """FP16 direct SoA grids with nx a power of two update two nodes per lane;
+    one node per lane must give the same bits, and both follow the oracle."""
+    import lbm_inputs
+    import paper_1111_0922_amd as P
+    nx, ny, nz = shape
+    solid = lbm_inputs.channel_mask(nx, ny, nz) if walls else np.zeros((nz, ny, nx), np.uint8)
+    ru = lbm_inputs.rho_u_field(solid.shape, lbm_inputs.velocity_noise(solid.shape, 1e-3, seed=13))
+    q0 = oracle.quantize(oracle.init_equilibrium(ru, solid), solid, "f16s", 256.0)
+    out = []
+    for pair in (1, 0):
+        grid = make_grid(solid, scheme, precision="f16s", omega=1.7, g=(1e-5, 2e-5, 0), f16_scale=256.0)
+        grid.set_option(P._lib.OPT_PAIR, pair)
+        grid.set_pdfs(to_device(oracle.fluid_view(q0, solid)))
+        grid.step(5)
+        out.append(from_device(grid.get_pdfs()))
+    assert np.array_equal(out[0].view(np.int64), out[1].view(np.int64))
+    want = oracle.fluid_view(oracle.run_ts(q0, solid, 5, 1.7, (1e-5, 2e-5, 0), precision="f16s", sigma=256.0), solid)
+    assert float(np.max(np.abs(out[0] - want))) <= 8 * 2.0 ** -23
