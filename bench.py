@@ -224,6 +224,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=48, help="requests per serving run (0 = skip)")
     ap.add_argument("--precision-study", action="store_true",
                     help="only the 384^3 steady-state precision study (FP64 / FP32 / FP16-shifted)")
+    ap.add_argument("--profile-aa", choices=["f64", "f32", "f32s", "f16s"], default=None,
+                    help="only the AA 256^3 channel run in this storage (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the copy kernel on 1 GiB, 3 times (counter calibration)")
     args = ap.parse_args()
@@ -249,6 +251,12 @@ def main():
         return
 
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+    if args.profile_aa:
+        grid = channel_grid(P, torch, 256, "aa", "soa", args.profile_aa)
+        dt = time_steps(torch, grid, args.steps, args.warmup)
+        print(json.dumps({"profile": f"AA SoA {args.profile_aa} 256^3 channel", "steps": args.steps,
+                          "MFLUP/s": round(grid.n_nodes * args.steps / dt / 1e6, 1)}), flush=True)
+        return
     if args.precision_study:
         print(json.dumps({"precision_study": precision_study(log)}), flush=True)
         return

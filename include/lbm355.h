@@ -160,7 +160,7 @@ int lbm_set_params(lbm_grid *g, double omega, const double g_acc[3]);
  *     reserved by every update workgroup on top of what the kernel uses.  It
  *     only limits how many workgroups a CU (160 KB of LDS) keeps resident,
  *     which bounds the number of concurrent memory streams.  The default is
- *     36864 for FP64, 40960 for FP32 and 0 for FP16 storage on direct SoA
+ *     45056 for FP64, 40960 for FP32 and 0 for FP16 storage on direct SoA
  *     grids, and 0 for indirect or AoS grids.
  *   LBM_OPT_ROW_STAGE (0/1, default 1): on a direct SoA grid whose nx is a
  *     power of two no larger than 256, every workgroup holds whole x-rows and

@@ -101,14 +101,14 @@ KArgs base_args(const lbm_grid *g)
     a.dvy = make_fastdiv((uint32_t)d.ny);
     a.remap = g->remap;
     // Measured on MI355X (256^3 channel): FP64 direct SoA workgroups run best with
-    // about two resident per CU for the row-staged kernels (20 KB static LDS +
-    // 36 KB) and four for the others; FP32 likes 40 KB; FP16 wants no cap.
+    // two resident per CU for the row-staged kernels (20 KB static LDS + 44 KB)
+    // and three for the others (44 KB); FP32 likes 40 KB; FP16 wants no cap.
     // Indirect and AoS kernels keep full residency: their gathers need the
     // parallelism to hide latency.
     const bool streaming = d.addressing == LBM_DIRECT && d.layout == LBM_SOA;
     a.lds_bytes = (uint32_t)(g->wg_lds >= 0 ? g->wg_lds
                                            : (!streaming ? 0
-                                                         : (d.precision == LBM_F64 ? 36864
+                                                         : (d.precision == LBM_F64 ? 45056
                                                                                    : ((d.precision == LBM_F32 || d.precision == LBM_F32S) ? 40960 : 0))));
     // whole x-rows per workgroup: nx a power of two dividing the workgroup size
     a.row_staged = (d.addressing == LBM_DIRECT && d.layout == LBM_SOA && g->row_stage && d.nx <= BLOCK &&
