@@ -62,9 +62,9 @@ def _load():
     lib.ora_collide.argtypes = [dp, dp, u8p, ip, ctypes.c_double, ctypes.c_double, dp, ctypes.c_int,
                                 ctypes.c_int, ctypes.c_double, ctypes.c_int]
     lib.ora_collide_node_trt.argtypes = [dp, ctypes.c_double, ctypes.c_double, dp, dp]
-    lib.ora_stream.argtypes = [dp, dp, u8p, ip, ip, ctypes.c_int]
+    lib.ora_stream.argtypes = [dp, dp, u8p, ip, ip, dp, ctypes.c_int]
     lib.ora_run_ts.argtypes = [dp, dp, u8p, ip, ip, ctypes.c_double, ctypes.c_double, dp, ctypes.c_int,
-                               ctypes.c_int, ctypes.c_double, ctypes.c_long, ctypes.c_int]
+                               ctypes.c_int, ctypes.c_double, dp, ctypes.c_long, ctypes.c_int]
     lib.ora_moments.argtypes = [dp, u8p, ip, dp]
     lib.ora_macroscopic.argtypes = [dp, u8p, ip, dp, dp]
     lib.ora_init_equilibrium.argtypes = [dp, u8p, ip, dp]
@@ -184,30 +184,49 @@ def collide(f, solid, omega, g, collider="bgk", precision=None, sigma=1.0, threa
     return B
 
 
-def stream(fpost, solid, periodic=(1, 1, 1), threads=0):
-    """Propagation loop alone: pull with half-way bounce-back."""
+BC_KIND = {"wall": 0, "velocity": 1, "pressure": 2}
+
+
+def _bc_table(bc):
+    """Boundary classes {class 1..4: (kind, rho, (ux, uy, uz))} as the flat [4][5] table, or NULL."""
+    if not bc:
+        return None
+    t = np.zeros((4, 5))
+    for cls, (kind, rho, u) in bc.items():
+        assert 1 <= cls <= 4
+        t[cls - 1] = (BC_KIND[kind], rho, u[0], u[1], u[2])
+    return t
+
+
+def stream(fpost, solid, periodic=(1, 1, 1), threads=0, bc=None):
+    """Propagation loop alone: pull with half-way bounce-back (and open boundaries, see run_ts)."""
     lib = _load()
     solid = np.ascontiguousarray(solid, dtype=np.uint8)
     B = np.ascontiguousarray(fpost, dtype=np.float64)
     A = np.zeros_like(B)
+    t = _bc_table(bc)
     lib.ora_stream(_p(B, ctypes.c_double), _p(A, ctypes.c_double), _p(solid, ctypes.c_uint8),
-                   _dims(solid), _per(periodic), int(threads))
+                   _dims(solid), _per(periodic), None if t is None else _p(t, ctypes.c_double), int(threads))
     return A
 
 
 def run_ts(f, solid, steps, omega, g, periodic=(1, 1, 1), collider="bgk", precision=None,
-           sigma=1.0, threads=0, omega_minus=None):
+           sigma=1.0, threads=0, omega_minus=None, bc=None):
     """`steps` time steps of the two-step two-grid algorithm; returns f(t+steps).
 
     collider: 'bgk', 'identity', or 'trt' (odd moments relaxed with omega_minus).
+    bc: open boundaries {class: (kind, rho, u)} for mask cells of value class + 1;
+    kind 'wall' (bounce-back), 'velocity' (moving wall) or 'pressure' (anti-bounce-back).
     """
     lib = _load()
     solid = np.ascontiguousarray(solid, dtype=np.uint8)
     A = np.array(f, dtype=np.float64, order="C", copy=True)
     B = np.zeros_like(A)
+    t = _bc_table(bc)
     lib.ora_run_ts(_p(A, ctypes.c_double), _p(B, ctypes.c_double), _p(solid, ctypes.c_uint8),
                    _dims(solid), _per(periodic), float(omega), float(omega if omega_minus is None else omega_minus),
-                   _vec3(g), COLLIDER[collider], QUANT[precision], float(sigma), int(steps), int(threads))
+                   _vec3(g), COLLIDER[collider], QUANT[precision], float(sigma),
+                   None if t is None else _p(t, ctypes.c_double), int(steps), int(threads))
     return A
 
 

@@ -22,6 +22,8 @@
  *     paper's own solver uses (Sec. 10, ref. [15]) with the same force term
  *     split into even and odd parts.  The paper prints no operator; these are
  *     the readings taken.
+ *   - open boundaries (velocity and pressure in-/outlets, Sec. 6) as link
+ *     rules on the bounced population, see boundary_value();
  *   - the index array of indirect addressing (Sec. 1): fluid nodes numbered
  *     in lexicographic order (x fastest), IDX[k][n] = id of the neighbour in
  *     direction c_{k+1}, -1 when that neighbour is solid.
@@ -259,8 +261,33 @@ static long pull_source(int x, int y, int z, int i, const int dims[3], const int
 }
 
 /* Propagation loop of the two-step algorithm (pull form), B -> A. */
+/* Open boundaries (the in-/outlet routines the AA pattern needs in both
+ * parities, Sec. 6).  A non-fluid cell with mask value m >= 2 belongs to
+ * boundary class m - 1; bc[5 (m - 2) + 0..4] = {kind, rho, ux, uy, uz}:
+ *   kind 0  wall: plain half-way bounce-back;
+ *   kind 1  velocity boundary, a wall moving with u (Ladd 1994): the
+ *           bounced population gains the momentum the moving wall imparts,
+ *             f_i(x, t+1) = f*_opp(i)(x, t) + 6 w_i rho c_i.u ;
+ *   kind 2  pressure boundary of density rho and velocity u, by
+ *           anti-bounce-back:
+ *             f_i(x, t+1) = -f*_opp(i)(x, t) + 2 w_i rho (1 + 9/2 (c_i.u)^2 - 3/2 u.u).
+ * Mask value 1, cells outside a non-periodic axis, and bc == NULL are plain
+ * walls.  `bounced` is f*_opp(i)(x, t), i the direction that arrives at x. */
+static double boundary_value(double bounced, int i, int m, const double *bc)
+{
+    if (m < 2 || !bc) return bounced;
+    const double *e = bc + 5 * (m - 2);
+    const int kind = (int)e[0];
+    const double rho = e[1];
+    const double cu = CV[i][0] * e[2] + CV[i][1] * e[3] + CV[i][2] * e[4];
+    const double uu = e[2] * e[2] + e[3] * e[3] + e[4] * e[4];
+    if (kind == 1) return bounced + 6.0 * WV[i] * rho * cu;
+    if (kind == 2) return -bounced + 2.0 * WV[i] * rho * (1.0 + 4.5 * cu * cu - 1.5 * uu);
+    return bounced;
+}
+
 void ora_stream(const double *B, double *A, const uint8_t *solid, const int dims[3], const int periodic[3],
-                int nthreads)
+                const double *bc, int nthreads)
 {
     init_tables();
     const int nx = dims[0], ny = dims[1], nz = dims[2];
@@ -275,8 +302,8 @@ void ora_stream(const double *B, double *A, const uint8_t *solid, const int dims
                 if (solid[c]) continue;
                 for (int i = 0; i < Q; ++i) {
                     long s = pull_source(x, y, z, i, dims, periodic);
-                    if (s < 0 || solid[s])
-                        A[i * ncell + c] = B[OPPV[i] * ncell + c]; /* half-way bounce-back */
+                    if (s < 0 || solid[s]) /* half-way bounce-back, or an open boundary */
+                        A[i * ncell + c] = boundary_value(B[OPPV[i] * ncell + c], i, s < 0 ? 1 : solid[s], bc);
                     else
                         A[i * ncell + c] = B[i * ncell + s];
                 }
@@ -289,11 +316,11 @@ void ora_stream(const double *B, double *A, const uint8_t *solid, const int dims
  * f(t + nsteps) after; B is the intermediate lattice. */
 void ora_run_ts(double *A, double *B, const uint8_t *solid, const int dims[3], const int periodic[3],
                 double omega, double omega_minus, const double g[3], int collider, int quant, double sigma,
-                long nsteps, int nthreads)
+                const double *bc, long nsteps, int nthreads)
 {
     for (long t = 0; t < nsteps; ++t) {
         ora_collide(A, B, solid, dims, omega, omega_minus, g, collider, quant, sigma, nthreads);
-        ora_stream(B, A, solid, dims, periodic, nthreads);
+        ora_stream(B, A, solid, dims, periodic, bc, nthreads);
     }
 }
 
@@ -361,7 +388,8 @@ void ora_init_equilibrium(const double *rho_u, const uint8_t *solid, const int d
  * dimension) is the plain lexicographic order, x fastest.
  * cellmap[c] = fluid id or -1.  idx (optional, 18 rows of idx_pitch):
  * idx[k][n] = id of the cell at x_n + c_{k+1}, -1 if solid or outside a
- * non-periodic axis.  Returns the number of fluid nodes. */
+ * non-periodic axis, -m for a boundary cell of mask value m >= 2.  Returns
+ * the number of fluid nodes. */
 long ora_build_idx_brick(const uint8_t *solid, const int dims[3], const int periodic[3], const int brick[3],
                          int32_t *cellmap, int32_t *idx, long idx_pitch)
 {
@@ -399,7 +427,10 @@ long ora_build_idx_brick(const uint8_t *solid, const int dims[3], const int peri
                         }
                     }
                     int32_t v = -1;
-                    if (!out) v = cellmap[p[0] + (long)nx * (p[1] + (long)ny * p[2])];
+                    if (!out) {
+                        long cc = p[0] + (long)nx * (p[1] + (long)ny * p[2]);
+                        v = solid[cc] ? -(int32_t)solid[cc] : cellmap[cc];
+                    }
                     idx[k * idx_pitch + n] = v;
                 }
             }

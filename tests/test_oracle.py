@@ -14,6 +14,11 @@ against a retyped copy of its own formulas:
                        the TRT 'magic' relaxation), shear-wave viscosity and the
                        slit permeability;
   * IDX             -- a hand-worked 4^3 example and the link symmetry;
+  * open boundaries -- uniform flow through a velocity inlet and a pressure
+                       outlet is fixed, Couette flow is exactly linear, a
+                       pressure box takes its density, pressure-driven slit
+                       flow is Poiseuille flow, resting wall classes are plain
+                       bounce-back;
   * binary16 rounding -- numpy's float16 conversion.
 """
 import math
@@ -415,3 +420,111 @@ def test_brick_ordering_is_a_renumbering():
     # a brick covering the box is the lexicographic order
     cm2, idx2, _ = oracle.build_idx(solid, brick=(10, 9, 7))
     np.testing.assert_array_equal(cm2, cm0)
+
+
+# ---------------------------------------------------------------- open boundaries
+def test_bc_uniform_flow_through_velocity_inlet_and_pressure_outlet_is_fixed():
+    """f = f^eq(1, U) everywhere is the steady state of a duct between a
+    velocity inlet (U) and a pressure outlet (rho 1, U): both link rules give
+    back exactly the equilibrium populations."""
+    nx, ny, nz = 10, 3, 4
+    U = (0.02, -0.004, 0.003)
+    m = np.zeros((nz, ny, nx), np.uint8)
+    m[:, :, 0] = 2
+    m[:, :, nx - 1] = 3
+    ru = lbm_inputs.rho_u_field(m.shape)
+    ru[1:] = np.array(U)[:, None, None, None]
+    f0 = oracle.init_equilibrium(ru, m)
+    bc = {1: ("velocity", 1.0, U), 2: ("pressure", 1.0, U)}
+    for collider, wm in (("bgk", None), ("trt", 0.7)):
+        f = oracle.run_ts(f0, m, 40, 1.3, (0, 0, 0), collider=collider, omega_minus=wm, bc=bc)
+        np.testing.assert_allclose(f, f0, rtol=0, atol=1e-15)  # f >= 0.02: a few ulp
+
+
+@pytest.mark.parametrize("omega", [0.8, 1.0, 1.6])
+def test_bc_couette_profile_is_linear_and_mass_conserved(omega):
+    """A lid moving tangentially at U over a fixed wall: the steady profile is
+    the straight line u = U (z - 1/2)/H between the half-way walls, which
+    bounce-back reproduces exactly, and the moving wall adds no mass."""
+    nz, Uw = 18, 0.01
+    H = nz - 2
+    nu = (1.0 / omega - 0.5) / 3.0
+    m = np.zeros((nz, 2, 2), np.uint8)
+    m[0] = 1
+    m[nz - 1] = 2
+    f = oracle.init_equilibrium(lbm_inputs.rho_u_field(m.shape), m)
+    M0 = oracle.moments(f, m)[0]
+    f = oracle.run_ts(f, m, int(6 * H * H / nu), omega, (0, 0, 0), bc={1: ("velocity", 1.0, (Uw, 0, 0))})
+    _, u = oracle.macroscopic(f, m, (0, 0, 0))
+    z = np.arange(1, nz - 1)
+    assert np.abs(u[0, 1:-1] - (Uw * (z - 0.5) / H)[:, None, None]).max() / Uw < 1e-10
+    assert abs(oracle.moments(f, m)[0] - M0) / M0 < 1e-11
+
+
+def test_bc_pressure_boundary_sets_the_density():
+    """A box enclosed by pressure cells of density 1.02 (u = 0) relaxes from
+    rest at rho = 1 to rho = 1.02; f^eq(1.02, 0) is an exact fixed point."""
+    nx, ny, nz = 7, 6, 5
+    m = np.full((nz, ny, nx), 2, np.uint8)
+    m[1:-1, 1:-1, 1:-1] = 0
+    bc = {1: ("pressure", 1.02, (0, 0, 0))}
+    f = oracle.init_equilibrium(lbm_inputs.rho_u_field(m.shape), m)
+    f = oracle.run_ts(f, m, 300, 1.0, (0, 0, 0), bc=bc)
+    rho, _ = oracle.macroscopic(f, m, (0, 0, 0))
+    assert np.abs(rho[m == 0] - 1.02).max() < 1e-14
+    ru = lbm_inputs.rho_u_field(m.shape)
+    ru[0] = 1.02
+    feq = oracle.init_equilibrium(ru, m)
+    np.testing.assert_allclose(oracle.run_ts(feq, m, 7, 1.4, (0, 0, 0), bc=bc), feq, rtol=0, atol=1e-15)
+
+
+def test_bc_pressure_driven_slit_is_poiseuille():
+    """Two pressure boundaries drive a slit flow: where it is developed, the
+    profile is the body-force Poiseuille parabola for the measured density
+    gradient, g = c_s^2 d(rho)/dx, up to the compressibility O(d rho)."""
+    nx, nz = 42, 10
+    H, L = nz - 2, nx - 2
+    omega = 1.0 / (0.5 + math.sqrt(3.0) / 4.0)
+    nu = (1.0 / omega - 0.5) / 3.0
+    drho = 1e-5
+    m = np.zeros((nz, 1, nx), np.uint8)
+    m[0] = 1
+    m[nz - 1] = 1
+    m[1:-1, :, 0] = 2
+    m[1:-1, :, nx - 1] = 3
+    f = oracle.init_equilibrium(lbm_inputs.rho_u_field(m.shape), m)
+    bc = {1: ("pressure", 1 + drho / 2, (0, 0, 0)), 2: ("pressure", 1 - drho / 2, (0, 0, 0))}
+    f = oracle.run_ts(f, m, int(6 * H * H / nu) + 8 * L * L, omega, (0, 0, 0), bc=bc)
+    rho, u = oracle.macroscopic(f, m, (0, 0, 0))
+    rm = rho[1:-1, 0, :].mean(axis=0)
+    x1, x2 = nx // 4, 3 * nx // 4
+    g = (rm[x1] - rm[x2]) / (x2 - x1) / 3.0
+    z = np.arange(1, nz - 1)
+    exact = g / (2 * nu) * (z - 0.5) * (H + 0.5 - z)
+    assert np.abs(u[0, 1:-1, 0, nx // 2] - exact).max() / exact.max() < 1e-4
+    assert rm[1] > rm[x1] > rm[x2] > rm[-2]
+
+
+def test_bc_still_wall_classes_are_plain_bounce_back():
+    solid = lbm_inputs.sphere_pack((12, 10, 9), 3, 0.6, seed=5)[0]
+    m = solid.copy()
+    m[solid == 1] = 2 + (np.arange(int(solid.sum())) % 3).astype(np.uint8)  # classes 1..3
+    ru = lbm_inputs.rho_u_field(solid.shape, lbm_inputs.velocity_noise(solid.shape, 1e-3, seed=3))
+    f0 = oracle.init_equilibrium(ru, solid)
+    want = oracle.run_ts(f0, solid, 9, 1.4, (1e-5, 0, 0))
+    bc = {1: ("wall", 1.0, (0.1, 0, 0)), 2: ("velocity", 1.0, (0, 0, 0)), 3: ("velocity", 1.3, (0, 0, 0))}
+    got = oracle.run_ts(f0, m, 9, 1.4, (1e-5, 0, 0), bc=bc)
+    assert np.array_equal(got, want)
+
+
+def test_bc_idx_codes():
+    """IDX holds -m for a neighbour cell of mask value m (-1 for plain solid)."""
+    m = np.zeros((4, 4, 4), np.uint8)
+    m[0, 0, 0] = 1
+    m[2, 1, 3] = 4
+    cellmap, idx, _ = oracle.build_idx(m)
+    # the fluid cell at (x, y, z) = (2, 1, 2) has the value-4 cell at +x (direction 1, row 0)
+    assert idx[0][cellmap[2, 1, 2]] == -4
+    # the fluid cell at (0, 0, 1) has the plain solid cell at -z (direction 6, row 5)
+    assert idx[5][cellmap[1, 0, 0]] == -1
+    assert sorted(set(idx[idx < 0].tolist())) == [-4, -1]
