@@ -147,6 +147,26 @@ int lbm_destroy_grid(lbm_grid *g);
 /* Replaces omega and g (host values) for subsequent steps. */
 int lbm_set_params(lbm_grid *g, double omega, const double g_acc[3]);
 
+/* Open boundaries: in- and outlets (Sec. 6 counts the in-/outlet routines
+ * among what the AA pattern needs in two versions).  Cells of mask value
+ * cls + 1 (cls = 1..4) of an indirect grid form boundary class cls.  A
+ * population f*_i that leaves fluid node x towards such a cell comes back to
+ * x as direction i' = opp(i):
+ *   LBM_BC_WALL      f_i' = f*_i                      (half-way bounce-back; default)
+ *   LBM_BC_VELOCITY  f_i' = f*_i + 6 w_i' rho c_i'.u  (a wall moving with u: velocity inlet/outlet)
+ *   LBM_BC_PRESSURE  f_i' = -f*_i + 2 w_i' rho (1 + 9/2 (c_i'.u)^2 - 3/2 u.u)
+ *                    (anti-bounce-back: pressure boundary of density rho, u the
+ *                    velocity in its quadratic terms, 0 for a resting reservoir)
+ * The rule applies in both AA parities (odd-step gather, odd-step scatter),
+ * in TS and OS, in lbm_get_pdfs / lbm_set_pdfs / lbm_init_equilibrium and in
+ * the moments.  Host values; takes effect at the next call.  Errors:
+ * LBM_E_UNSUPPORTED on a direct grid, or together with the esoteric twist
+ * (its kernels keep walls only; lbm_bind refuses ET while a class is open),
+ * LBM_E_ARG for cls outside 1..4, an unknown kind, rho <= 0 or a non-finite
+ * value.  Grids with open classes cannot join a batch. */
+enum lbm_bc_kind { LBM_BC_WALL = 0, LBM_BC_VELOCITY = 1, LBM_BC_PRESSURE = 2 };
+int lbm_set_boundary(lbm_grid *g, int32_t cls, int32_t kind, double rho, const double u[3]);
+
 /* Launch and layout options (host values; results are bit-identical for any
  * setting):
  *   LBM_OPT_XCD_REMAP (0/1, default 0): order the update kernels' workgroups
@@ -182,15 +202,17 @@ int lbm_query_sizes(const lbm_grid *g, int32_t scheme, lbm_sizes *out);
 
 /* Index array of indirect addressing (Sec. 1; fluid nodes and their q-1
  * neighbours).  Two calls:
- *   1. d_idx == NULL: reads d_mask (uint8[n_cells], 1 = solid, x fastest),
+ *   1. d_idx == NULL: reads d_mask (uint8[n_cells], x fastest: 0 = fluid,
+ *      1 = solid wall, 2..5 = boundary cell of class 1..4 (see
+ *      lbm_set_boundary), any other non-zero value = solid wall),
  *      writes d_cellmap (int32[n_cells]): the fluid id of each fluid cell in
  *      the numbering order of desc.brick (lexicographic by default), -1 for a
  *      solid cell, or -2 - k for the solid cell holding esoteric-twist storage
  *      entry k (et_ghosts only, ghosts numbered in the same order).  Stores N_f in *n_fluid_out (host) and keeps
  *      N_f and the ghost count in the grid.  Synchronises `stream` once.
  *   2. d_idx != NULL: reads d_cellmap, writes d_idx (int32[18][idx_pitch]):
- *      IDX[k][n] = fluid id of the cell at x_n + c_{k+1} (periodic wrap) or -1
- *      when that cell is solid.  With et_ghosts, d_et (int32[7][idx_pitch])
+ *      IDX[k][n] = fluid id of the cell at x_n + c_{k+1} (periodic wrap), -1
+ *      when that cell is a solid wall, -m for a boundary cell of mask value m.  With et_ghosts, d_et (int32[7][idx_pitch])
  *      receives the six storage addresses the esoteric twist reads at
  *      x + (1,0,0), (0,1,0), (0,0,1), (1,1,0), (1,0,1), (0,1,1) (fluid id, or
  *      N_f + ghost number for a solid cell) and, in row 6, a bit mask whose

@@ -33,6 +33,8 @@ ADDRESSING = {"direct": DIRECT, "indirect": INDIRECT}
 LAYOUTS = {"soa": SOA, "aos": AOS}
 PRECISIONS = {"f64": F64, "f32": F32, "f16s": F16S, "f32s": F32S}
 COLLIDERS = {"identity": IDENTITY, "bgk": BGK, "trt": TRT}
+BC_WALL, BC_VELOCITY, BC_PRESSURE = 0, 1, 2
+BC_KINDS = {"wall": BC_WALL, "velocity": BC_VELOCITY, "pressure": BC_PRESSURE}
 
 
 class GridDesc(ctypes.Structure):
@@ -51,6 +53,7 @@ class Sizes(ctypes.Structure):
 
 EXPORTS = [
     "lbm_last_error", "lbm_version", "lbm_lattice", "lbm_create_grid", "lbm_destroy_grid", "lbm_set_params",
+    "lbm_set_boundary",
     "lbm_set_option", "lbm_query_sizes", "lbm_build_idx", "lbm_bind", "lbm_set_pdfs", "lbm_get_pdfs",
     "lbm_init_equilibrium", "lbm_step", "lbm_time", "lbm_reduce_moments", "lbm_stream_copy", "lbm_model_bytes",
     "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_destroy", "lbm_batch_add", "lbm_batch_remove",
@@ -83,6 +86,7 @@ def load():
     lib.lbm_create_grid.argtypes = [ctypes.POINTER(GridDesc), ctypes.POINTER(gp)]
     lib.lbm_destroy_grid.argtypes = [gp]
     lib.lbm_set_params.argtypes = [gp, dbl, ctypes.POINTER(dbl)]
+    lib.lbm_set_boundary.argtypes = [gp, ctypes.c_int32, ctypes.c_int32, dbl, ctypes.POINTER(dbl)]
     lib.lbm_set_option.argtypes = [gp, i32, i64]
     lib.lbm_query_sizes.argtypes = [gp, i32, ctypes.POINTER(Sizes)]
     lib.lbm_build_idx.argtypes = [gp, vp, vp, vp, vp, vp, ctypes.POINTER(i64), vp]

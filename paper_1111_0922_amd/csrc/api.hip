@@ -123,6 +123,26 @@ KArgs base_args(const lbm_grid *g)
     a.sigma = (d.precision == LBM_F16S || d.precision == LBM_F32S) ? d.f16_scale : 1.0;
     a.omega_minus = d.omega; // BGK; lbm_step sets the TRT rate
     set_collision(a);
+    // open boundaries: the constant C_c[d] of each class and direction
+    a.bc_on = has_open_boundaries(g) ? 1 : 0;
+    a.bc_neg = 0;
+    for (int c = 0; c < 4; ++c) {
+        const double rho = g->bc_rho[c], *u = g->bc_u[c];
+        const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        const bool neg = g->bc_kind[c] == LBM_BC_PRESSURE;
+        if (neg) a.bc_neg |= 1u << c;
+        for (int i = 0; i < Q; ++i) {
+            const double cu = cx(i) * u[0] + cy(i) * u[1] + cz(i) * u[2];
+            double k = 0.0;
+            if (g->bc_kind[c] == LBM_BC_VELOCITY) k = 6.0 * wd(i) * rho * cu;      // moving wall
+            if (neg) k = 2.0 * wd(i) * rho * (1.0 + 4.5 * cu * cu - 1.5 * uu);      // anti-bounce-back
+            a.bc_can[c][i] = k;
+            // stored form: shifted values v = sigma (f - w) turn f' = s f + k into
+            // v' = s v + sigma (k - (1 - s) w)
+            const bool shifted = d.precision == LBM_F16S || d.precision == LBM_F32S;
+            a.bc_f[c][i] = (float)(shifted ? a.sigma * (k - (neg ? 2.0 * wd(i) : 0.0)) : k);
+        }
+    }
     return a;
 }
 
@@ -208,6 +228,25 @@ int lbm_set_params(lbm_grid *g, double omega, const double g_acc[3])
     if (!(omega > 0.0 && omega < 2.0)) return fail(LBM_E_ARG, "omega must lie in (0, 2)");
     g->d.omega = omega;
     for (int k = 0; k < 3; ++k) g->d.g[k] = g_acc[k];
+    return LBM_OK;
+}
+
+int lbm_set_boundary(lbm_grid *g, int32_t cls, int32_t kind, double rho, const double u[3])
+{
+    if (!g || !u) return fail(LBM_E_ARG, "null argument");
+    if (g->d.addressing != LBM_INDIRECT)
+        return fail(LBM_E_UNSUPPORTED, "open boundaries are classes of the mask of an indirect grid");
+    if (cls < 1 || cls > 4) return fail(LBM_E_ARG, "boundary class %d outside 1..4", cls);
+    if (kind != LBM_BC_WALL && kind != LBM_BC_VELOCITY && kind != LBM_BC_PRESSURE)
+        return fail(LBM_E_ARG, "unknown boundary kind %d", kind);
+    if (!(rho > 0.0) || !std::isfinite(rho)) return fail(LBM_E_ARG, "boundary density must be positive");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(u[k])) return fail(LBM_E_ARG, "boundary velocity must be finite");
+    if (g->scheme == LBM_ET && kind != LBM_BC_WALL)
+        return fail(LBM_E_UNSUPPORTED, "the esoteric twist kernels have no open boundaries");
+    g->bc_kind[cls - 1] = kind;
+    g->bc_rho[cls - 1] = rho;
+    for (int k = 0; k < 3; ++k) g->bc_u[cls - 1][k] = u[k];
     return LBM_OK;
 }
 
@@ -358,6 +397,8 @@ int lbm_bind(lbm_grid *g, int32_t scheme, void *d_pdf0, void *d_pdf1, const int3
     if (two_lattices(scheme) && !d_pdf1) return fail(LBM_E_ARG, "this scheme needs a second lattice");
     if (ind && !d_idx) return fail(LBM_E_ARG, "indirect grid needs the IDX buffer");
     if (ind && scheme == LBM_ET && !d_aux) return fail(LBM_E_ARG, "indirect esoteric twist needs the ET table");
+    if (scheme == LBM_ET && has_open_boundaries(g))
+        return fail(LBM_E_UNSUPPORTED, "the esoteric twist kernels have no open boundaries (velocity or pressure classes)");
     lbm_sizes sz;
     int rc = lbm_query_sizes(g, scheme, &sz);
     if (rc) return rc;

@@ -66,6 +66,8 @@ __device__ __forceinline__ KArgs slot_args(const SlotDesc &sd)
     a.omega_minus = sd.omega_minus;
     a.cpd = sd.cpd;
     a.cpf = sd.cpf;
+    a.bc_on = 0; // batched grids have walls only
+    a.bc_neg = 0;
     return a;
 }
 
@@ -274,6 +276,7 @@ int lbm_batch_add(lbm_batch *b, lbm_grid *g, int32_t *slot_out)
     if (g->d.addressing != LBM_INDIRECT || g->d.layout != LBM_SOA || g->scheme != LBM_AA)
         return fail(LBM_E_UNSUPPORTED, "batched lattices are indirect SoA grids bound to the AA pattern");
     if (g->d.precision != b->precision) return fail(LBM_E_ARG, "grid precision differs from the batch's");
+    if (has_open_boundaries(g)) return fail(LBM_E_UNSUPPORTED, "batched lattices have walls only (no open boundaries)");
     if (g->n_nodes <= 0) return fail(LBM_E_STATE, "grid has no fluid nodes");
     const int64_t need = (g->n_nodes + BLOCK - 1) / BLOCK;
     int64_t used = 0;

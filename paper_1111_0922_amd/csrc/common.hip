@@ -250,8 +250,11 @@ __global__ void __launch_bounds__(BLOCK) k_idx_fill(BuildArgs b)
     uint32_t mask = 0;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-        const int32_t v = b.cellmap[wrap_cell(b, x + cx(i), y + cy(i), z + cz(i))];
-        b.idx[(int64_t)(i - 1) * b.idx_pitch + n] = v >= 0 ? v : -1;
+        const uint32_t cc = wrap_cell(b, x + cx(i), y + cy(i), z + cz(i));
+        const int32_t v = b.cellmap[cc];
+        // a non-fluid neighbour: -1, or -m for a boundary cell of mask value 2 <= m <= 5
+        const int32_t m = b.mask[cc];
+        b.idx[(int64_t)(i - 1) * b.idx_pitch + n] = v >= 0 ? v : ((m >= 2 && m <= 5) ? -m : -1);
         if (v < 0) mask |= 1u << (i - 1);
     }
     if (b.et_on) {

@@ -29,7 +29,19 @@ struct lbm_grid {
     int64_t wg_lds = -1;   // dynamic LDS reserved per update workgroup (-1: per-precision default)
     int row_stage = 1;     // allow the row-staged direct SoA kernels
     int pair = 1;          // allow two nodes per lane (16-bit direct SoA)
+    // open-boundary classes 1..4 (indirect grids): kind, density, velocity
+    int bc_kind[4] = {0, 0, 0, 0};
+    double bc_rho[4] = {1.0, 1.0, 1.0, 1.0};
+    double bc_u[4][3] = {};
 };
+
+// true when some class is not a resting wall
+inline bool has_open_boundaries(const lbm_grid *g)
+{
+    for (int c = 0; c < 4; ++c)
+        if (g->bc_kind[c] != LBM_BC_WALL) return true;
+    return false;
+}
 
 namespace lbm_host {
 

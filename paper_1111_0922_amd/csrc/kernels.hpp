@@ -123,6 +123,16 @@ struct KArgs {
     double omega_minus;    // TRT odd-moment rate (== omega for BGK)
     CollideParams<double> cpd; // collision factors (set_collision) for FP64
     CollideParams<float> cpf;  // and for FP32 compute
+    // Open boundaries of indirect grids (Sec. 6: in-/outlets in both AA
+    // parities).  A neighbour with IDX code -1 - c, c = 1..4, is a boundary
+    // cell of class c: the population that bounces back there arrives as
+    // s_c f + C_c[d] (d its direction), with s_c = -1 (bit c-1 of bc_neg) for
+    // pressure classes and +1 for velocity classes.  Code -1 (c = 0) is a
+    // plain wall.
+    int32_t bc_on;         // some class is not a resting wall
+    uint32_t bc_neg;
+    double bc_can[4][Q];   // C_c[d] on canonical values (also the FP64 compute form)
+    float bc_f[4][Q];      // C_c[d] on the stored form, FP32 compute
     // canonical transfer / reductions
     double *canon;
     const double *canon_in;
@@ -144,6 +154,27 @@ __device__ __forceinline__ const CollideParams<T> &cparams(const KArgs &a)
         return a.cpd;
     else
         return a.cpf;
+}
+
+// The population arriving in direction d from a boundary of class c >= 1,
+// given the bounced value v (compute type, stored form) ...
+template <typename T>
+__device__ __forceinline__ T bc_arrive(const KArgs &a, int c, int d, T v)
+{
+    const T k = sizeof(T) == 8 ? (T)a.bc_can[c - 1][d] : (T)a.bc_f[c - 1][d];
+    return ((a.bc_neg >> (c - 1)) & 1u) ? k - v : v + k;
+}
+// ... the same on canonical FP64 values, and its inverse (the bounced value
+// that makes f arrive).
+__device__ __forceinline__ double bc_arrive_canon(const KArgs &a, int c, int d, double f)
+{
+    const double k = a.bc_can[c - 1][d];
+    return ((a.bc_neg >> (c - 1)) & 1u) ? k - f : f + k;
+}
+__device__ __forceinline__ double bc_depart_canon(const KArgs &a, int c, int d, double f)
+{
+    const double k = a.bc_can[c - 1][d];
+    return ((a.bc_neg >> (c - 1)) & 1u) ? k - f : f - k;
 }
 
 // ------------------------------------------------------------------ block order
@@ -201,6 +232,7 @@ struct Node<A_DIRECT, NEED> {
     // storage cell x + (ox, oy, oz), ox, oy, oz in {0, 1}
     __device__ __forceinline__ int64_t at(int sx, int sy, int sz) const { return shift(sx, sy, sz); }
     __device__ __forceinline__ bool et_solid(int i) const { return solid(i); }
+    __device__ __forceinline__ int bc_class(int) const { return 0; }
     __device__ __forceinline__ void refresh() {}
 };
 
@@ -235,6 +267,14 @@ struct Node<A_INDIRECT, NEED> {
         return c == 0 ? a : (int64_t)e[c - 1];
     }
     __device__ __forceinline__ bool et_solid(int i) const { return (mask >> (i - 1)) & 1u; }
+    // boundary class of the non-fluid neighbour at x + c_i (IDX code -1 - c)
+    __device__ __forceinline__ int bc_class(int i) const
+    {
+        if constexpr ((NEED & NEED_NB) != 0)
+            return -m[i - 1] - 1;
+        else
+            return 0;
+    }
     // Opaque redefinition of the node's index registers (an empty asm, no
     // memory access).  Called between gather and scatter, it keeps the
     // compiler from holding 19 wide gather addresses live across the
@@ -256,8 +296,9 @@ struct Node<A_INDIRECT, NEED> {
 
 // ------------------------------------------------------------------ maps
 template <int R, class N>
-__device__ __forceinline__ void read_slot(const N &nd, int i, int &j, int64_t &c)
+__device__ __forceinline__ void read_slot(const N &nd, int i, int &j, int64_t &c, int &bc)
 {
+    bc = 0;
     if constexpr (R == R_LOCAL) {
         j = i;
         c = nd.a;
@@ -269,6 +310,7 @@ __device__ __forceinline__ void read_slot(const N &nd, int i, int &j, int64_t &c
         } else if (nd.solid(o)) {
             j = o;
             c = nd.a;
+            bc = nd.bc_class(o);
         } else {
             j = i;
             c = nd.nb(o);
@@ -281,6 +323,7 @@ __device__ __forceinline__ void read_slot(const N &nd, int i, int &j, int64_t &c
         } else if (nd.solid(o)) {
             j = i;
             c = nd.a;
+            bc = nd.bc_class(o);
         } else {
             j = o;
             c = nd.nb(o);
@@ -292,9 +335,17 @@ __device__ __forceinline__ void read_slot(const N &nd, int i, int &j, int64_t &c
     }
 }
 
-template <int W, class N>
-__device__ __forceinline__ void write_slot(const N &nd, int i, int &j, int64_t &c)
+template <int R, class N>
+__device__ __forceinline__ void read_slot(const N &nd, int i, int &j, int64_t &c)
 {
+    int bc;
+    read_slot<R>(nd, i, j, c, bc);
+}
+
+template <int W, class N>
+__device__ __forceinline__ void write_slot(const N &nd, int i, int &j, int64_t &c, int &bc)
+{
+    bc = 0;
     if constexpr (W == W_LOCAL) {
         j = i;
         c = nd.a;
@@ -305,6 +356,7 @@ __device__ __forceinline__ void write_slot(const N &nd, int i, int &j, int64_t &
         } else if (nd.solid(i)) {
             j = opp(i);
             c = nd.a;
+            bc = nd.bc_class(i);
         } else {
             j = i;
             c = nd.nb(i);
@@ -319,6 +371,13 @@ __device__ __forceinline__ void write_slot(const N &nd, int i, int &j, int64_t &
         const bool s = (i != 0) && nd.et_solid(i);
         j = s ? (odd ? o : i) : (odd ? i : o);
     }
+}
+
+template <int W, class N>
+__device__ __forceinline__ void write_slot(const N &nd, int i, int &j, int64_t &c)
+{
+    int bc;
+    write_slot<W>(nd, i, j, c, bc);
 }
 
 // ------------------------------------------------------------------ maps as offsets (direct grids)
@@ -600,10 +659,13 @@ __device__ __forceinline__ void update_node(const KArgs &a, uint32_t n)
     ct v[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        int j;
+        int j, bc;
         int64_t c;
-        read_slot<R>(nd, i, j, c);
+        read_slot<R>(nd, i, j, c, bc);
         v[i] = S::load(pdf_load<NT>(src + elem<LAY>(j, c, a.pitch)));
+        if constexpr (ADDR == A_INDIRECT && (R == R_PULL || R == R_AAODD)) {
+            if (bc > 0 && a.bc_on) v[i] = bc_arrive<ct>(a, bc, i, v[i]);
+        }
     }
     if constexpr (COLL == 1 && KIND != K_TS_STREAM) {
         const CollideParams<ct> &p = cparams<ct>(a);
@@ -612,10 +674,14 @@ __device__ __forceinline__ void update_node(const KArgs &a, uint32_t n)
     if constexpr (need_r(R) != 0 && need_w(W) != 0) nd.refresh(); // gather and scatter both use the ids
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        int j;
+        int j, bc;
         int64_t c;
-        write_slot<W>(nd, i, j, c);
-        pdf_store<NT>(dst + elem<LAY>(j, c, a.pitch), S::save(v[i]));
+        write_slot<W>(nd, i, j, c, bc);
+        ct out = v[i];
+        if constexpr (ADDR == A_INDIRECT && W == W_PUSH) {
+            if (bc > 0 && a.bc_on) out = bc_arrive<ct>(a, bc, opp(i), out);
+        }
+        pdf_store<NT>(dst + elem<LAY>(j, c, a.pitch), S::save(out));
     }
 }
 
@@ -659,10 +725,13 @@ __device__ __forceinline__ void update_aos_staged(const KArgs &a)
         if (valid) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                int j;
+                int j, bc;
                 int64_t c;
-                read_slot<R>(nd, i, j, c);
+                read_slot<R>(nd, i, j, c, bc);
                 v[i] = S::load(src[elem<L_AOS>(j, c, a.pitch)]);
+                if constexpr (ADDR == A_INDIRECT && (R == R_PULL || R == R_AAODD)) {
+                    if (bc > 0 && a.bc_on) v[i] = bc_arrive<ct>(a, bc, i, v[i]);
+                }
             }
         }
     }
@@ -685,10 +754,14 @@ __device__ __forceinline__ void update_aos_staged(const KArgs &a)
             if constexpr (need_r(R) != 0 && need_w(W) != 0) nd.refresh();
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                int j;
+                int j, bc;
                 int64_t c;
-                write_slot<W>(nd, i, j, c);
-                dst[elem<L_AOS>(j, c, a.pitch)] = S::save(v[i]);
+                write_slot<W>(nd, i, j, c, bc);
+                ct out = v[i];
+                if constexpr (ADDR == A_INDIRECT && W == W_PUSH) {
+                    if (bc > 0 && a.bc_on) out = bc_arrive<ct>(a, bc, opp(i), out);
+                }
+                dst[elem<L_AOS>(j, c, a.pitch)] = S::save(out);
             }
         }
     }
@@ -741,8 +814,11 @@ __global__ void __launch_bounds__(BLOCK) k_get(KArgs a)
     for (int i = 0; i < Q; ++i) {
         int j;
         int64_t c;
-        read_slot<R>(nd, i, j, c);
-        a.canon[(int64_t)i * a.n_nodes + n] = S::to_canon(src[elem<LAY>(j, c, a.pitch)], i, a.sigma);
+        int bc;
+        read_slot<R>(nd, i, j, c, bc);
+        double f = S::to_canon(src[elem<LAY>(j, c, a.pitch)], i, a.sigma);
+        if (bc > 0 && a.bc_on) f = bc_arrive_canon(a, bc, i, f);
+        a.canon[(int64_t)i * a.n_nodes + n] = f;
     }
 }
 
@@ -760,8 +836,11 @@ __global__ void __launch_bounds__(BLOCK) k_set(KArgs a)
     for (int i = 0; i < Q; ++i) {
         int j;
         int64_t c;
-        read_slot<R>(nd, i, j, c);
-        dst[elem<LAY>(j, c, a.pitch)] = S::from_canon(a.canon_in[(int64_t)i * a.n_nodes + n], i, a.sigma);
+        int bc;
+        read_slot<R>(nd, i, j, c, bc);
+        double f = a.canon_in[(int64_t)i * a.n_nodes + n];
+        if (bc > 0 && a.bc_on) f = bc_depart_canon(a, bc, i, f);
+        dst[elem<LAY>(j, c, a.pitch)] = S::from_canon(f, i, a.sigma);
     }
 }
 
@@ -787,10 +866,11 @@ __global__ void __launch_bounds__(BLOCK) k_init(KArgs a)
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const double cu = cx(i) * ux + cy(i) * uy + cz(i) * uz;
-        const double feq = wd(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-        int j;
+        double feq = wd(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+        int j, bc;
         int64_t c;
-        read_slot<R>(nd, i, j, c);
+        read_slot<R>(nd, i, j, c, bc);
+        if (bc > 0 && a.bc_on) feq = bc_depart_canon(a, bc, i, feq);
         dst[elem<LAY>(j, c, a.pitch)] = S::from_canon(feq, i, a.sigma);
     }
 }
@@ -837,8 +917,10 @@ __device__ __forceinline__ void node_moments(const KArgs &a, uint32_t n, double 
     for (int i = 0; i < Q; ++i) {
         int j;
         int64_t c;
-        read_slot<R>(nd, i, j, c);
-        const double f = S::to_canon(src[elem<LAY>(j, c, a.pitch)], i, a.sigma);
+        int bc;
+        read_slot<R>(nd, i, j, c, bc);
+        double f = S::to_canon(src[elem<LAY>(j, c, a.pitch)], i, a.sigma);
+        if (bc > 0 && a.bc_on) f = bc_arrive_canon(a, bc, i, f);
         m[0] += f;
         if (cx(i) > 0) m[1] += f;
         if (cx(i) < 0) m[1] -= f;

@@ -105,6 +105,11 @@ class Grid:
         arr = (ctypes.c_double * 3)(*[float(v) for v in g])
         L.check(self.lib.lbm_set_params(self._h, float(omega), arr))
 
+    def set_boundary(self, cls: int, kind: str, rho: float = 1.0, u=(0.0, 0.0, 0.0)):
+        """Open boundary class `cls` (mask value cls + 1): 'wall', 'velocity' (moving wall) or 'pressure'."""
+        arr = (ctypes.c_double * 3)(*[float(v) for v in u])
+        L.check(self.lib.lbm_set_boundary(self._h, int(cls), L.BC_KINDS[kind], float(rho), arr))
+
     def set_option(self, option, value):
         L.check(self.lib.lbm_set_option(self._h, int(option), int(value)))
 
