@@ -190,8 +190,23 @@ int lbm_set_boundary(lbm_grid *g, int32_t cls, int32_t kind, double rho, const d
  *     whose nx is a power of two in [2, 512], every lane updates two
  *     x-neighbours and moves them as one 32-bit word per direction; 0 forces
  *     one node per lane.
+ *   LBM_OPT_BAND (blocks in [0, 4096], or -1 = default): on a direct grid
+ *     whose z-plane splits into whole bands of this many workgroups for each
+ *     of the 8 XCDs, order the update workgroups so that every XCD sweeps
+ *     its bands along z; the neighbour rows a node reads or writes then run
+ *     close in time on one L2.  Ignored when the plane does not split.  0
+ *     keeps the natural order.  The default uses bands of 8 (FP64) or 16
+ *     workgroups for AoS kernels that access neighbours, and the natural
+ *     order otherwise.
  * Errors: LBM_E_ARG for an unknown option or a value out of range. */
-enum { LBM_OPT_XCD_REMAP = 1, LBM_OPT_PITCH_PAD = 2, LBM_OPT_WG_LDS = 3, LBM_OPT_ROW_STAGE = 4, LBM_OPT_PAIR = 5 };
+enum {
+    LBM_OPT_XCD_REMAP = 1,
+    LBM_OPT_PITCH_PAD = 2,
+    LBM_OPT_WG_LDS = 3,
+    LBM_OPT_ROW_STAGE = 4,
+    LBM_OPT_PAIR = 5,
+    LBM_OPT_BAND = 6
+};
 int lbm_set_option(lbm_grid *g, int32_t option, int64_t value);
 
 /* Buffer sizes of `scheme` on this grid (host struct out).  For an indirect

@@ -26,6 +26,7 @@ OPT_PITCH_PAD = 2
 OPT_WG_LDS = 3
 OPT_ROW_STAGE = 4
 OPT_PAIR = 5
+OPT_BAND = 6
 
 SCHEMES = {"ts": TS, "os_push": OS_PUSH, "os_pull": OS_PULL, "aa": AA, "et": ET,
            "os_nt": OS_NT, "cg": CG, "swap": SWAP}

@@ -79,6 +79,41 @@ int64_t idx_pitch_of(const lbm_grid *g) { return round_up(g->n_nodes > 0 ? g->n_
 
 uint32_t node_blocks(const lbm_grid *g) { return (uint32_t)((g->n_nodes + BLOCK - 1) / BLOCK); }
 
+// Workgroups of an update launch.
+uint32_t update_blocks(const lbm_grid *g, const KArgs &a)
+{
+    const int64_t npb = a.pair ? 2 * BLOCK : BLOCK;
+    return (uint32_t)((g->n_nodes + npb - 1) / npb);
+}
+
+// Block order of one update kernel: the banded XCD order (logical_block) when
+// it applies.  By default (band < 0) AoS kernels with a neighbour side use it,
+// with bands of 8 workgroups for FP64 and 16 for 4- and 2-byte storage
+// (measured on the 256^3 channel: AA odd AoS 6.7 -> 3.1 ms in FP64, 3.5 ->
+// 1.7 ms in FP32); SoA and node-local kernels keep the natural order, which
+// the bands slow down.
+void set_block_order(const lbm_grid *g, KArgs &a, int kind)
+{
+    a.remap = g->remap;
+    if (g->d.addressing != LBM_DIRECT) return;
+    int64_t band = g->band;
+    if (band < 0) {
+        const int R = rmap_of(kind), W = wmap_of(kind);
+        const bool neighbour_side = !(R == R_LOCAL && (W == W_LOCAL || W == W_AAEVEN));
+        band = (g->d.layout == LBM_AOS && neighbour_side) ? (g->d.precision == LBM_F64 ? 8 : 16) : 0;
+    }
+    if (band <= 0) return;
+    const int64_t npb = a.pair ? 2 * BLOCK : BLOCK;
+    const int64_t plane = (int64_t)g->d.nx * g->d.ny;
+    const int64_t yb = plane / npb;
+    if (plane % npb == 0 && yb % (8 * band) == 0) {
+        a.remap = 2;
+        a.band_yb = (uint32_t)yb;
+        a.band_ty = (uint32_t)band;
+        a.band_z = (uint32_t)(g->n_nodes / plane);
+    }
+}
+
 KArgs base_args(const lbm_grid *g)
 {
     KArgs a;
@@ -263,6 +298,11 @@ int lbm_set_option(lbm_grid *g, int32_t option, int64_t value)
     }
     if (option == LBM_OPT_PAIR) {
         g->pair = value ? 1 : 0;
+        return LBM_OK;
+    }
+    if (option == LBM_OPT_BAND) {
+        if (value < -1 || value > 4096) return fail(LBM_E_ARG, "band height must be -1 or lie in [0, 4096] blocks");
+        g->band = (int)value;
         return LBM_OK;
     }
     if (option == LBM_OPT_WG_LDS) {
@@ -463,7 +503,11 @@ int lbm_step(lbm_grid *g, int32_t scheme, int32_t collider, int64_t n_steps, voi
     const PrecTable &tb = table(g->d.precision);
     const int A = g->d.addressing, L = g->d.layout, C = collider == LBM_IDENTITY ? 0 : 1;
     KArgs a = base_args(g);
-    const uint32_t nb = a.pair ? (uint32_t)((g->n_nodes + 2 * BLOCK - 1) / (2 * BLOCK)) : node_blocks(g);
+    const uint32_t nb = update_blocks(g, a);
+    auto launch = [&](int kind) {
+        set_block_order(g, a, kind);
+        tb.update[A][L][C][kind](a, nb, s);
+    };
     if (collider == LBM_TRT) {
         // Lambda = (1/w+ - 1/2)(1/w- - 1/2)
         a.omega_minus = 1.0 / (g->d.trt_lambda / (1.0 / g->d.omega - 0.5) + 0.5);
@@ -474,25 +518,25 @@ int lbm_step(lbm_grid *g, int32_t scheme, int32_t collider, int64_t n_steps, voi
         case LBM_TS:
             a.src = g->pdf[g->cur];
             a.dst = g->pdf[1 - g->cur];
-            tb.update[A][L][C][K_TS_COLLIDE](a, nb, s);
+            launch(K_TS_COLLIDE);
             a.src = g->pdf[1 - g->cur];
             a.dst = g->pdf[g->cur];
-            tb.update[A][L][C][K_TS_STREAM](a, nb, s);
+            launch(K_TS_STREAM);
             break;
         case LBM_OS_PUSH:
         case LBM_OS_PULL:
             a.src = g->pdf[g->cur];
             a.dst = g->pdf[1 - g->cur];
-            tb.update[A][L][C][g->scheme == LBM_OS_PUSH ? K_OS_PUSH : K_OS_PULL](a, nb, s);
+            launch(g->scheme == LBM_OS_PUSH ? K_OS_PUSH : K_OS_PULL);
             g->cur = 1 - g->cur;
             break;
         case LBM_AA:
             a.src = a.dst = g->pdf[0];
-            tb.update[A][L][C][(g->t & 1) ? K_AA_ODD : K_AA_EVEN](a, nb, s);
+            launch((g->t & 1) ? K_AA_ODD : K_AA_EVEN);
             break;
         case LBM_ET:
             a.src = a.dst = g->pdf[0];
-            tb.update[A][L][C][(g->t & 1) ? K_ET1 : K_ET0](a, nb, s);
+            launch((g->t & 1) ? K_ET1 : K_ET0);
             break;
         }
         ++g->t;

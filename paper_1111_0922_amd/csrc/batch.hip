@@ -66,6 +66,7 @@ __device__ __forceinline__ KArgs slot_args(const SlotDesc &sd)
     a.omega_minus = sd.omega_minus;
     a.cpd = sd.cpd;
     a.cpf = sd.cpf;
+    a.remap = 0;
     a.bc_on = 0; // batched grids have walls only
     a.bc_neg = 0;
     return a;

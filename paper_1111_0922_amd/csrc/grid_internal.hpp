@@ -29,6 +29,7 @@ struct lbm_grid {
     int64_t wg_lds = -1;   // dynamic LDS reserved per update workgroup (-1: per-precision default)
     int row_stage = 1;     // allow the row-staged direct SoA kernels
     int pair = 1;          // allow two nodes per lane (16-bit direct SoA)
+    int band = -1;         // XCD band height (blocks) of the direct-grid block order, 0 = off, -1 = default
     // open-boundary classes 1..4 (indirect grids): kind, density, velocity
     int bc_kind[4] = {0, 0, 0, 0};
     double bc_rho[4] = {1.0, 1.0, 1.0, 1.0};
@@ -48,6 +49,8 @@ namespace lbm_host {
 int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 int hip_check(hipError_t e, const char *where);
 lbm::KArgs base_args(const lbm_grid *g);
+uint32_t update_blocks(const lbm_grid *g, const lbm::KArgs &a);
+void set_block_order(const lbm_grid *g, lbm::KArgs &a, int kind);
 uint32_t node_blocks(const lbm_grid *g);
 int64_t idx_pitch_of(const lbm_grid *g);
 const lbm::PrecTable &table(int precision);

@@ -115,7 +115,8 @@ struct KArgs {
     uint32_t n_nodes;
     int32_t nx, ny, nz, z0, wall;
     FastDiv dvx, dvy;
-    int32_t remap;         // XCD-aware block order
+    int32_t remap;         // block order: 0 natural, 1 XCD chunks, 2 XCD bands (logical_block)
+    uint32_t band_yb, band_ty, band_z;
     uint32_t lds_bytes;    // dynamic LDS reserved per update workgroup (caps residency)
     int32_t row_staged;    // direct SoA, nx divides BLOCK: x-shifted accesses go through LDS
     int32_t pair;          // direct SoA, 16-bit storage, nx divides 2 * BLOCK: two nodes per lane
@@ -179,15 +180,28 @@ __device__ __forceinline__ double bc_depart_canon(const KArgs &a, int c, int d, 
 
 // ------------------------------------------------------------------ block order
 // Workgroups are dispatched round-robin over the 8 XCDs (block b on XCD
-// b mod 8).  With remap set, consecutive logical blocks (neighbouring nodes,
-// which share cache lines of the shifted accesses) run on the same XCD and
-// share its L2.  The map is a bijection on [0, gridDim.x).
-__device__ __forceinline__ uint32_t logical_block(int remap)
+// b mod 8), each XCD with its own L2.  The maps below are bijections on
+// [0, gridDim.x) that change only which node block a workgroup updates:
+//   remap 1: consecutive logical blocks (neighbouring nodes, which share
+//            cache lines of the shifted accesses) run on the same XCD;
+//   remap 2: direct grids seen as z-planes of band_yb blocks; the planes are
+//            cut into bands of band_ty blocks (rows), band k belongs to XCD
+//            k mod 8, and each XCD sweeps its bands along z.  The neighbour
+//            rows a node reads from or writes to (y +- 1, z +- 1) then run
+//            close in time on the same XCD.  Requires band_yb % (8 band_ty)
+//            == 0 and gridDim.x = band_z * band_yb.
+__device__ __forceinline__ uint32_t logical_block(const KArgs &a)
 {
     uint32_t b = blockIdx.x;
-    if (remap) {
+    if (a.remap == 1) {
         const uint32_t G = gridDim.x, x = b & 7u, s = b >> 3, q = G >> 3, r = G & 7u;
         b = (x < r) ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
+    } else if (a.remap == 2) {
+        const uint32_t x = b & 7u, s = b >> 3;
+        const uint32_t per_band = a.band_z * a.band_ty;
+        const uint32_t k = s / per_band, r = s - k * per_band;
+        const uint32_t z = r / a.band_ty, yb = (x + 8u * k) * a.band_ty + (r - z * a.band_ty);
+        b = z * a.band_yb + yb;
     }
     return b;
 }
@@ -468,7 +482,7 @@ __device__ __forceinline__ void update_direct_staged(const KArgs &a)
     constexpr int W = wmap_of(KIND);
     __shared__ st xs[NXSLOT][BLOCK];
     const uint32_t t = threadIdx.x;
-    const uint32_t n = logical_block(a.remap) * BLOCK + t;
+    const uint32_t n = logical_block(a) * BLOCK + t;
     const bool valid = n < a.n_nodes;
     const uint32_t nx = (uint32_t)a.nx; // power of two dividing BLOCK
     const uint32_t xl = t & (nx - 1), row = t - xl;
@@ -558,7 +572,7 @@ __device__ __forceinline__ void update_direct_pair(const KArgs &a)
     __shared__ uint32_t xw[shifts ? NXSLOT : 1][shifts ? BLOCK : 1];
     const uint32_t t = threadIdx.x;
     const uint32_t p = 2 * t;          // the pair's first node within the workgroup
-    const uint32_t n = logical_block(a.remap) * NP + p;
+    const uint32_t n = logical_block(a) * NP + p;
     const bool valid = n < a.n_nodes;  // n_nodes is a multiple of nx, so pairs are whole
     const uint32_t nx = (uint32_t)a.nx;
     const uint32_t xl = p & (nx - 1), row = p - xl;
@@ -704,7 +718,7 @@ __device__ __forceinline__ void update_aos_staged(const KArgs &a)
     constexpr bool local_w = (W == W_LOCAL || W == W_AAEVEN);
     __shared__ st rec[BLOCK * Q];
     const uint32_t t = threadIdx.x;
-    const uint32_t n0 = logical_block(a.remap) * BLOCK;
+    const uint32_t n0 = logical_block(a) * BLOCK;
     const uint32_t cnt = min((uint32_t)BLOCK, a.n_nodes - n0); // the grid covers n_nodes, so n0 < n_nodes
     const bool valid = t < cnt;
     const uint32_t n = n0 + (valid ? t : 0);
@@ -792,7 +806,7 @@ __global__ void __launch_bounds__(BLOCK) k_update(KArgs a)
         update_aos_staged<ADDR, PREC, KIND, COLL>(a);
         return;
     }
-    const uint32_t n = logical_block(a.remap) * BLOCK + threadIdx.x;
+    const uint32_t n = logical_block(a) * BLOCK + threadIdx.x;
     if (n >= a.n_nodes) return;
     update_node<ADDR, LAY, PREC, KIND, COLL>(a, n);
 }

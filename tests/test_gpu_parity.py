@@ -198,3 +198,23 @@ def test_brick_ordered_indirect_matches_oracle(scheme, brick):
     grid.set_pdfs(to_device(oracle.ordered_view(f0, order)))
     grid.step(21)
     assert rel_err(from_device(grid.get_pdfs()), want) <= 1e-12
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("shape,precision", [((256, 32, 6), "f64"), ((64, 64, 5), "f64"), ((512, 16, 4), "f16s")])
+def test_banded_block_order_bit_identical(scheme, layout, shape, precision):
+    """The XCD band order only permutes which workgroup updates which nodes."""
+    import paper_1111_0922_amd as P
+    solid = lbm_inputs.channel_mask(shape[0], shape[1], shape[2])
+    ru = lbm_inputs.rho_u_field(solid.shape, lbm_inputs.velocity_noise(solid.shape, 1e-3, seed=14))
+    f0 = oracle.fluid_view(oracle.init_equilibrium(ru, solid), solid)
+    out = []
+    for band in (0, -1, 1, 2, 4):
+        grid = make_grid(solid, scheme, layout=layout, precision=precision, omega=1.7, g=(1e-5, 0, 0))
+        grid.set_option(P._lib.OPT_BAND, band)
+        grid.set_pdfs(to_device(f0))
+        grid.step(5)
+        out.append(from_device(grid.get_pdfs()))
+    for o in out[1:]:
+        assert np.array_equal(o.view(np.int64), out[0].view(np.int64))
