@@ -729,8 +729,19 @@ __device__ __forceinline__ void update_aos_staged(const KArgs &a)
     st *dst = static_cast<st *>(a.dst);
     ct v[Q];
     if constexpr (local_r) {
+        // coalesced copy of the block's records into LDS; a full block issues
+        // all 19 loads of a lane before its first LDS store (the lines belong
+        // to this workgroup alone, hence the nontemporal hint)
         const st *base = src + a0 * Q;
-        for (uint32_t e = t; e < cnt * Q; e += BLOCK) rec[e] = base[e];
+        if (cnt == (uint32_t)BLOCK) {
+            st tmp[Q];
+#pragma unroll
+            for (int k = 0; k < Q; ++k) tmp[k] = pdf_load<true>(base + t + k * BLOCK);
+#pragma unroll
+            for (int k = 0; k < Q; ++k) rec[t + k * BLOCK] = tmp[k];
+        } else {
+            for (uint32_t e = t; e < cnt * Q; e += BLOCK) rec[e] = base[e];
+        }
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < Q; ++i) v[i] = S::load(rec[t * Q + i]);
@@ -762,7 +773,15 @@ __device__ __forceinline__ void update_aos_staged(const KArgs &a)
         }
         __syncthreads();
         st *base = dst + a0 * Q;
-        for (uint32_t e = t; e < cnt * Q; e += BLOCK) base[e] = rec[e];
+        if (cnt == (uint32_t)BLOCK) {
+            st tmp[Q];
+#pragma unroll
+            for (int k = 0; k < Q; ++k) tmp[k] = rec[t + k * BLOCK];
+#pragma unroll
+            for (int k = 0; k < Q; ++k) pdf_store<true>(base + t + k * BLOCK, tmp[k]);
+        } else {
+            for (uint32_t e = t; e < cnt * Q; e += BLOCK) base[e] = rec[e];
+        }
     } else {
         if (valid) {
             if constexpr (need_r(R) != 0 && need_w(W) != 0) nd.refresh();
