@@ -180,8 +180,8 @@ int lbm_set_boundary(lbm_grid *g, int32_t cls, int32_t kind, double rho, const d
  *     reserved by every update workgroup on top of what the kernel uses.  It
  *     only limits how many workgroups a CU (160 KB of LDS) keeps resident,
  *     which bounds the number of concurrent memory streams.  The default is
- *     45056 for FP64, 40960 for FP32 and 0 for FP16 storage on direct SoA
- *     grids, and 0 for indirect or AoS grids.
+ *     45056 for FP64, 40960 (direct) or 53248 (indirect) for FP32 and 0 for
+ *     FP16 storage on SoA grids, and 0 on AoS grids.
  *   LBM_OPT_ROW_STAGE (0/1, default 1): on a direct SoA grid whose nx is a
  *     power of two no larger than 256, every workgroup holds whole x-rows and
  *     moves the x-shifted PDFs through LDS, so that all global accesses are

@@ -135,16 +135,18 @@ KArgs base_args(const lbm_grid *g)
     a.dvx = make_fastdiv((uint32_t)d.nx);
     a.dvy = make_fastdiv((uint32_t)d.ny);
     a.remap = g->remap;
-    // Measured on MI355X (256^3 channel): FP64 direct SoA workgroups run best with
-    // two resident per CU for the row-staged kernels (20 KB static LDS + 44 KB)
-    // and three for the others (44 KB); FP32 likes 40 KB; FP16 wants no cap.
-    // Indirect and AoS kernels keep full residency: their gathers need the
-    // parallelism to hide latency.
-    const bool streaming = d.addressing == LBM_DIRECT && d.layout == LBM_SOA;
-    a.lds_bytes = (uint32_t)(g->wg_lds >= 0 ? g->wg_lds
-                                           : (!streaming ? 0
-                                                         : (d.precision == LBM_F64 ? 45056
-                                                                                   : ((d.precision == LBM_F32 || d.precision == LBM_F32S) ? 40960 : 0))));
+    // Measured on MI355X: FP64 direct SoA workgroups (256^3 channel) run best
+    // with two resident per CU for the row-staged kernels (20 KB static LDS +
+    // 44 KB) and three for the others (44 KB); FP32 likes 40 KB; FP16 wants no
+    // cap.  Indirect SoA (512^3 pack): 44 KB for FP64 (+1%) and 52 KB for
+    // 4-byte storage (AA even -7%, odd -3% in time).  AoS kernels keep full
+    // residency (their staged records already take 19-38 KB of LDS).
+    int64_t lds = 0;
+    if (d.layout == LBM_SOA) {
+        if (d.precision == LBM_F64) lds = 45056;
+        if (d.precision == LBM_F32 || d.precision == LBM_F32S) lds = d.addressing == LBM_DIRECT ? 40960 : 53248;
+    }
+    a.lds_bytes = (uint32_t)(g->wg_lds >= 0 ? g->wg_lds : lds);
     // whole x-rows per workgroup: nx a power of two dividing the workgroup size
     a.row_staged = (d.addressing == LBM_DIRECT && d.layout == LBM_SOA && g->row_stage && d.nx <= BLOCK &&
                     (d.nx & (d.nx - 1)) == 0) ? 1 : 0;

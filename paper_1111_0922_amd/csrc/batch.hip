@@ -25,6 +25,15 @@
 using namespace lbm;
 using namespace lbm_host;
 
+// Persistent grid of the batched kernel: workgroups per CU, and dynamic LDS
+// reserved per workgroup (which caps how many are resident per CU).
+#ifndef LBM_BATCH_WG_PER_CU
+#define LBM_BATCH_WG_PER_CU 8
+#endif
+#ifndef LBM_BATCH_LDS
+#define LBM_BATCH_LDS 0
+#endif
+
 namespace lbm {
 
 struct SlotDesc {
@@ -178,16 +187,16 @@ void launch_batch_body(lbm_batch *b, int32_t k_steps, double *h_out, hipStream_t
 {
     for (int32_t k = 0; k < k_steps; ++k) {
         if (b->precision == LBM_F64)
-            hipLaunchKernelGGL(k_aa_batched<P_F64>, dim3(b->grid_blocks), dim3(BLOCK), 0, s, b->d_slots, b->d_tiles,
+            hipLaunchKernelGGL(k_aa_batched<P_F64>, dim3(b->grid_blocks), dim3(BLOCK), LBM_BATCH_LDS, s, b->d_slots, b->d_tiles,
                                b->d_hdr, k);
         else if (b->precision == LBM_F32)
-            hipLaunchKernelGGL(k_aa_batched<P_F32>, dim3(b->grid_blocks), dim3(BLOCK), 0, s, b->d_slots, b->d_tiles,
+            hipLaunchKernelGGL(k_aa_batched<P_F32>, dim3(b->grid_blocks), dim3(BLOCK), LBM_BATCH_LDS, s, b->d_slots, b->d_tiles,
                                b->d_hdr, k);
         else if (b->precision == LBM_F16S)
-            hipLaunchKernelGGL(k_aa_batched<P_F16S>, dim3(b->grid_blocks), dim3(BLOCK), 0, s, b->d_slots, b->d_tiles,
+            hipLaunchKernelGGL(k_aa_batched<P_F16S>, dim3(b->grid_blocks), dim3(BLOCK), LBM_BATCH_LDS, s, b->d_slots, b->d_tiles,
                                b->d_hdr, k);
         else
-            hipLaunchKernelGGL(k_aa_batched<P_F32S>, dim3(b->grid_blocks), dim3(BLOCK), 0, s, b->d_slots, b->d_tiles,
+            hipLaunchKernelGGL(k_aa_batched<P_F32S>, dim3(b->grid_blocks), dim3(BLOCK), LBM_BATCH_LDS, s, b->d_slots, b->d_tiles,
                                b->d_hdr, k);
     }
     if (b->precision == LBM_F64)
@@ -252,7 +261,7 @@ int lbm_batch_create(int32_t max_slots, int64_t max_tiles, int32_t precision, vo
     b->d_moments = reinterpret_cast<double *>(ws + w.moments);
     b->slots.assign(max_slots, SlotDesc{});
     b->grids.assign(max_slots, nullptr);
-    b->grid_blocks = (uint32_t)(cus > 0 ? cus : 256) * 8;
+    b->grid_blocks = (uint32_t)(cus > 0 ? cus : 256) * LBM_BATCH_WG_PER_CU;
     rc = hip_check(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "lbm_batch_create (capture stream)");
     if (rc) {
         delete b;
