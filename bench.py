@@ -12,6 +12,8 @@ Besides the headline the JSON line carries:
                 algorithmic bytes per launch and its event-timed average
                 launch duration, against the 8 TB/s HBM3E peak;
   schemes       MFLUP/s and GB/s of every scheme x layout on the same lattice;
+  schemes       also AA with the TRT collision, and AA on an indirect 256^3 duct with a
+                velocity inlet and a pressure outlet (open boundaries);
   porous512     AA and two-step on the 512^3 sphere pack (indirect addressing);
   copy          the STREAM-style copy bandwidth of the device;
   cpu_baseline  the FP64 oracle timed on the host cores on a bounded sample.
@@ -81,6 +83,15 @@ def time_steps(torch, grid, steps, warmup):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     grid.step(steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def time_steps_collider(torch, grid, steps, warmup, collider):
+    grid.step(warmup, collider=collider)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    grid.step(steps, collider=collider)
     torch.cuda.synchronize()
     return time.perf_counter() - t0
 
@@ -325,6 +336,38 @@ def main():
             del g
             torch.cuda.empty_cache()
             log(f"[bench]   aa/soa/{prec}: {mf:.0f} MFLUP/s")
+        # the paper's collision (TRT, Lambda = 3/16) on the same kernels
+        g = channel_grid(P, torch, n, "aa", "soa")
+        dts = time_steps_collider(torch, g, 200, 10, "trt")
+        mf = g.n_nodes * 200 / dts / 1e6
+        bl = P.model_bytes("aa", "direct", "f64")
+        table["aa/soa/trt"] = {"MFLUP/s": round(mf, 1), "GB/s": round(mf * bl / 1e3, 1), "bytes_per_lup": bl,
+                               "frac_hbm": round(mf * bl / 1e3 / HBM_PEAK_GBS, 4)}
+        del g
+        torch.cuda.empty_cache()
+        log(f"[bench]   aa/soa/trt: {mf:.0f} MFLUP/s")
+        # open boundaries: 256^3 duct (indirect), velocity inlet x = 0, pressure outlet x = 255,
+        # walls z = 0 and z = 255, periodic in y
+        duct = np.zeros((n, n, n), np.uint8)
+        duct[:, :, 0] = 2
+        duct[:, :, n - 1] = 3
+        duct[0] = 1
+        duct[n - 1] = 1
+        g = P.Grid(n, n, n, addressing="indirect", omega=1.6)
+        g.build_idx(torch.from_numpy(duct).cuda())
+        g.set_boundary(1, "velocity", 1.0, (0.01, 0.0, 0.0))
+        g.set_boundary(2, "pressure", 1.0, (0.01, 0.0, 0.0))
+        g.bind("aa")
+        g.init_equilibrium()
+        dts = time_steps(torch, g, 200, 10)
+        mf = g.n_nodes * 200 / dts / 1e6
+        bl = P.model_bytes("aa", "indirect", "f64")
+        table["aa/indirect/duct_open_boundaries"] = {"MFLUP/s": round(mf, 1), "GB/s": round(mf * bl / 1e3, 1),
+                                                     "bytes_per_lup": bl,
+                                                     "frac_hbm": round(mf * bl / 1e3 / HBM_PEAK_GBS, 4)}
+        del g, duct
+        torch.cuda.empty_cache()
+        log(f"[bench]   aa/indirect/duct_open_boundaries: {mf:.0f} MFLUP/s")
         result["schemes"] = table
 
         log("[bench] 512^3 sphere pack (r 8, porosity 0.40), indirect, FP64")
