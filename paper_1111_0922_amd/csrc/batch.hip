@@ -34,16 +34,16 @@ using namespace lbm_host;
 #define LBM_BATCH_LDS 0
 #endif
 
+
 namespace lbm {
 
 struct SlotDesc {
-    void *pdf;
-    const int32_t *idx;
+    int64_t pdf_off;     // lattice and IDX: byte offsets from the workspace
+    int64_t idx_off;
     int64_t pitch;
     int64_t idx_pitch;
-    double omega, gx, gy, gz, sigma;
-    double omega_minus;
-    CollideParams<double> cpd;
+    double sigma;        // shifted-storage scale (canonical transfer of the moments)
+    CollideParams<double> cpd; // collision factors of the slot's grid (BGK)
     CollideParams<float> cpf;
     uint32_t n_nodes;
     int32_t t0;          // completed steps of the slot when the run starts
@@ -57,24 +57,31 @@ struct Tile {
     uint32_t slot, node0;
 };
 
-__device__ __forceinline__ KArgs slot_args(const SlotDesc &sd)
+// A pointer read from device memory is a generic (flat) pointer to the
+// compiler, which then emits flat loads and stores (they wait on both the LDS
+// and the vector-memory counters).  The slot table therefore holds byte
+// offsets from the workspace, and the kernels add them to the workspace
+// pointer they receive as an argument: derived from a kernel argument, the
+// addresses are known to be global.
+// Arguments of one slot's nodes.  (Moving the slot's fields to scalar
+// registers with readfirstlane lowered the kernel's VGPRs from 111 to 93 and
+// made it 5% slower on the serving mix; they stay as loaded.)
+template <int PREC>
+__device__ __forceinline__ KArgs slot_args(const SlotDesc &sd, char *base)
 {
     KArgs a;
-    a.src = sd.pdf;
-    a.dst = sd.pdf;
-    a.idx = sd.idx;
+    a.src = base + sd.pdf_off;
+    a.dst = base + sd.pdf_off;
+    a.idx = reinterpret_cast<const int32_t *>(base + sd.idx_off);
     a.et = nullptr;
     a.pitch = sd.pitch;
     a.idx_pitch = sd.idx_pitch;
     a.n_nodes = sd.n_nodes;
-    a.omega = sd.omega;
-    a.gx = sd.gx;
-    a.gy = sd.gy;
-    a.gz = sd.gz;
     a.sigma = sd.sigma;
-    a.omega_minus = sd.omega_minus;
-    a.cpd = sd.cpd;
-    a.cpf = sd.cpf;
+    if constexpr (PREC == P_F64)
+        a.cpd = sd.cpd;
+    else
+        a.cpf = sd.cpf;
     a.remap = 0;
     a.bc_on = 0; // batched grids have walls only
     a.bc_neg = 0;
@@ -84,13 +91,13 @@ __device__ __forceinline__ KArgs slot_args(const SlotDesc &sd)
 // One AA time step (step k of the run) of every active slot.
 template <int PREC>
 __global__ void __launch_bounds__(BLOCK) k_aa_batched(const SlotDesc *slots, const Tile *tiles, const uint32_t *hdr,
-                                                       int32_t k)
+                                                       int32_t k, char *base)
 {
     const uint32_t nt = hdr[0];
     for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
         const Tile tl = tiles[tile];
         const SlotDesc sd = slots[tl.slot];
-        const KArgs a = slot_args(sd);
+        const KArgs a = slot_args<PREC>(sd, base);
         const uint32_t n = tl.node0 + threadIdx.x;
         if (n < sd.n_nodes) {
             if ((sd.t0 + k) & 1)
@@ -104,13 +111,13 @@ __global__ void __launch_bounds__(BLOCK) k_aa_batched(const SlotDesc *slots, con
 // Per-tile FP64 moment partials of the state after `steps` steps.
 template <int PREC>
 __global__ void __launch_bounds__(BLOCK) k_seg_partials(const SlotDesc *slots, const Tile *tiles, const uint32_t *hdr,
-                                                         double *partials, int32_t steps)
+                                                         double *partials, int32_t steps, char *base)
 {
     const uint32_t nt = hdr[0];
     for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
         const Tile tl = tiles[tile];
         const SlotDesc sd = slots[tl.slot];
-        const KArgs a = slot_args(sd);
+        const KArgs a = slot_args<PREC>(sd, base);
         const uint32_t n = tl.node0 + threadIdx.x;
         double m[4] = {0.0, 0.0, 0.0, 0.0};
         if (n < sd.n_nodes) {
@@ -183,34 +190,41 @@ WsLayout layout_of(int32_t max_slots, int64_t max_tiles)
     return w;
 }
 
+char *ws_base(const lbm_batch *b) { return reinterpret_cast<char *>(b->d_hdr); }
+
+int64_t ws_offset(const lbm_batch *b, const void *p)
+{
+    return (int64_t)(reinterpret_cast<uintptr_t>(p) - reinterpret_cast<uintptr_t>(ws_base(b)));
+}
+
 void launch_batch_body(lbm_batch *b, int32_t k_steps, double *h_out, hipStream_t s)
 {
     for (int32_t k = 0; k < k_steps; ++k) {
         if (b->precision == LBM_F64)
             hipLaunchKernelGGL(k_aa_batched<P_F64>, dim3(b->grid_blocks), dim3(BLOCK), LBM_BATCH_LDS, s, b->d_slots, b->d_tiles,
-                               b->d_hdr, k);
+                               b->d_hdr, k, ws_base(b));
         else if (b->precision == LBM_F32)
             hipLaunchKernelGGL(k_aa_batched<P_F32>, dim3(b->grid_blocks), dim3(BLOCK), LBM_BATCH_LDS, s, b->d_slots, b->d_tiles,
-                               b->d_hdr, k);
+                               b->d_hdr, k, ws_base(b));
         else if (b->precision == LBM_F16S)
             hipLaunchKernelGGL(k_aa_batched<P_F16S>, dim3(b->grid_blocks), dim3(BLOCK), LBM_BATCH_LDS, s, b->d_slots, b->d_tiles,
-                               b->d_hdr, k);
+                               b->d_hdr, k, ws_base(b));
         else
             hipLaunchKernelGGL(k_aa_batched<P_F32S>, dim3(b->grid_blocks), dim3(BLOCK), LBM_BATCH_LDS, s, b->d_slots, b->d_tiles,
-                               b->d_hdr, k);
+                               b->d_hdr, k, ws_base(b));
     }
     if (b->precision == LBM_F64)
         hipLaunchKernelGGL(k_seg_partials<P_F64>, dim3(b->grid_blocks), dim3(BLOCK), 0, s, b->d_slots, b->d_tiles,
-                           b->d_hdr, b->d_partials, k_steps);
+                           b->d_hdr, b->d_partials, k_steps, ws_base(b));
     else if (b->precision == LBM_F32)
         hipLaunchKernelGGL(k_seg_partials<P_F32>, dim3(b->grid_blocks), dim3(BLOCK), 0, s, b->d_slots, b->d_tiles,
-                           b->d_hdr, b->d_partials, k_steps);
+                           b->d_hdr, b->d_partials, k_steps, ws_base(b));
     else if (b->precision == LBM_F16S)
         hipLaunchKernelGGL(k_seg_partials<P_F16S>, dim3(b->grid_blocks), dim3(BLOCK), 0, s, b->d_slots, b->d_tiles,
-                           b->d_hdr, b->d_partials, k_steps);
+                           b->d_hdr, b->d_partials, k_steps, ws_base(b));
     else
         hipLaunchKernelGGL(k_seg_partials<P_F32S>, dim3(b->grid_blocks), dim3(BLOCK), 0, s, b->d_slots, b->d_tiles,
-                           b->d_hdr, b->d_partials, k_steps);
+                           b->d_hdr, b->d_partials, k_steps, ws_base(b));
     hipLaunchKernelGGL(k_seg_final, dim3((uint32_t)b->max_slots), dim3(BLOCK), 0, s, b->d_slots, b->d_partials,
                        b->d_moments);
     if (h_out)
@@ -305,16 +319,11 @@ int lbm_batch_add(lbm_batch *b, lbm_grid *g, int32_t *slot_out)
     SlotDesc sd;
     std::memset(&sd, 0, sizeof sd);
     const KArgs a = base_args(g);
-    sd.pdf = g->pdf[0];
-    sd.idx = g->idx;
+    sd.pdf_off = ws_offset(b, g->pdf[0]);
+    sd.idx_off = ws_offset(b, g->idx);
     sd.pitch = a.pitch;
     sd.idx_pitch = a.idx_pitch;
-    sd.omega = a.omega;
-    sd.gx = a.gx;
-    sd.gy = a.gy;
-    sd.gz = a.gz;
     sd.sigma = a.sigma;
-    sd.omega_minus = a.omega_minus;
     sd.cpd = a.cpd;
     sd.cpf = a.cpf;
     sd.n_nodes = (uint32_t)g->n_nodes;
