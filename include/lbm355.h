@@ -158,12 +158,12 @@ int lbm_set_params(lbm_grid *g, double omega, const double g_acc[3]);
  *                    (anti-bounce-back: pressure boundary of density rho, u the
  *                    velocity in its quadratic terms, 0 for a resting reservoir)
  * The rule applies in both AA parities (odd-step gather, odd-step scatter),
- * in TS and OS, in lbm_get_pdfs / lbm_set_pdfs / lbm_init_equilibrium and in
- * the moments.  Host values; takes effect at the next call.  Errors:
- * LBM_E_UNSUPPORTED on a direct grid, or together with the esoteric twist
- * (its kernels keep walls only; lbm_bind refuses ET while a class is open),
- * LBM_E_ARG for cls outside 1..4, an unknown kind, rho <= 0 or a non-finite
- * value.  Grids with open classes cannot join a batch. */
+ * in TS and OS, in the esoteric twist's write side (its class read from
+ * IDX), in lbm_get_pdfs / lbm_set_pdfs / lbm_init_equilibrium and in the
+ * moments.  Host values; takes effect at the next call.  Errors:
+ * LBM_E_UNSUPPORTED on a direct grid, LBM_E_ARG for cls outside 1..4, an
+ * unknown kind, rho <= 0 or a non-finite value.  Grids with open classes
+ * cannot join a batch. */
 enum lbm_bc_kind { LBM_BC_WALL = 0, LBM_BC_VELOCITY = 1, LBM_BC_PRESSURE = 2 };
 int lbm_set_boundary(lbm_grid *g, int32_t cls, int32_t kind, double rho, const double u[3]);
 

@@ -279,8 +279,6 @@ int lbm_set_boundary(lbm_grid *g, int32_t cls, int32_t kind, double rho, const d
     if (!(rho > 0.0) || !std::isfinite(rho)) return fail(LBM_E_ARG, "boundary density must be positive");
     for (int k = 0; k < 3; ++k)
         if (!std::isfinite(u[k])) return fail(LBM_E_ARG, "boundary velocity must be finite");
-    if (g->scheme == LBM_ET && kind != LBM_BC_WALL)
-        return fail(LBM_E_UNSUPPORTED, "the esoteric twist kernels have no open boundaries");
     g->bc_kind[cls - 1] = kind;
     g->bc_rho[cls - 1] = rho;
     for (int k = 0; k < 3; ++k) g->bc_u[cls - 1][k] = u[k];
@@ -439,8 +437,6 @@ int lbm_bind(lbm_grid *g, int32_t scheme, void *d_pdf0, void *d_pdf1, const int3
     if (two_lattices(scheme) && !d_pdf1) return fail(LBM_E_ARG, "this scheme needs a second lattice");
     if (ind && !d_idx) return fail(LBM_E_ARG, "indirect grid needs the IDX buffer");
     if (ind && scheme == LBM_ET && !d_aux) return fail(LBM_E_ARG, "indirect esoteric twist needs the ET table");
-    if (scheme == LBM_ET && has_open_boundaries(g))
-        return fail(LBM_E_UNSUPPORTED, "the esoteric twist kernels have no open boundaries (velocity or pressure classes)");
     lbm_sizes sz;
     int rc = lbm_query_sizes(g, scheme, &sz);
     if (rc) return rc;

@@ -178,6 +178,17 @@ __device__ __forceinline__ double bc_depart_canon(const KArgs &a, int c, int d, 
     return ((a.bc_neg >> (c - 1)) & 1u) ? k - f : f - k;
 }
 
+// The esoteric twist bounces back on its write side only, from its solid
+// bit mask; the class of that neighbour comes from IDX (indirect grids).
+template <int W, class N>
+__device__ __forceinline__ int et_write_class(const KArgs &a, const N &nd, int i)
+{
+    if constexpr (W == W_ET0 || W == W_ET1) {
+        if (i != 0 && a.bc_on && nd.et_solid(i)) return -a.idx[(int64_t)(i - 1) * a.idx_pitch + nd.a] - 1;
+    }
+    return 0;
+}
+
 // ------------------------------------------------------------------ block order
 // Workgroups are dispatched round-robin over the 8 XCDs (block b on XCD
 // b mod 8), each XCD with its own L2.  The maps below are bijections on
@@ -691,8 +702,9 @@ __device__ __forceinline__ void update_node(const KArgs &a, uint32_t n)
         int j, bc;
         int64_t c;
         write_slot<W>(nd, i, j, c, bc);
+        if constexpr (ADDR == A_INDIRECT && (W == W_ET0 || W == W_ET1)) bc = et_write_class<W>(a, nd, i);
         ct out = v[i];
-        if constexpr (ADDR == A_INDIRECT && W == W_PUSH) {
+        if constexpr (ADDR == A_INDIRECT && (W == W_PUSH || W == W_ET0 || W == W_ET1)) {
             if (bc > 0 && a.bc_on) out = bc_arrive<ct>(a, bc, opp(i), out);
         }
         pdf_store<NT>(dst + elem<LAY>(j, c, a.pitch), S::save(out));
@@ -792,8 +804,9 @@ __device__ __forceinline__ void update_aos_staged(const KArgs &a)
                 int j, bc;
                 int64_t c;
                 write_slot<W>(nd, i, j, c, bc);
+                if constexpr (ADDR == A_INDIRECT && (W == W_ET0 || W == W_ET1)) bc = et_write_class<W>(a, nd, i);
                 ct out = v[i];
-                if constexpr (ADDR == A_INDIRECT && W == W_PUSH) {
+                if constexpr (ADDR == A_INDIRECT && (W == W_PUSH || W == W_ET0 || W == W_ET1)) {
                     if (bc > 0 && a.bc_on) out = bc_arrive<ct>(a, bc, opp(i), out);
                 }
                 dst[elem<L_AOS>(j, c, a.pitch)] = S::save(out);

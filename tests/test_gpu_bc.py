@@ -1,11 +1,11 @@
 """Open boundaries (velocity and pressure in-/outlets) on the GPU.
 
 A duct with a velocity inlet, a pressure outlet, a moving lid, a resting
-floor and spheres, run by every scheme that has open boundaries (TS, OS push,
-OS pull, AA: both AA parities), both layouts, against the oracle's link rules;
-the closed forms (uniform duct flow, Couette, pressure-driven Poiseuille) on
-the GPU; canonical readout and upload through the rules; the refusals (ET,
-batch, direct grids).
+floor and spheres, run by every scheme (TS, OS push, OS pull, AA: both AA
+parities, ET: its write side), both layouts, against the oracle's link
+rules; the closed forms (uniform duct flow, Couette, pressure-driven
+Poiseuille) on the GPU; canonical readout and upload through the rules; the
+refusals (batch, direct grids, bad arguments).
 """
 import math
 
@@ -54,7 +54,7 @@ def _state(mask, seed=32):
 
 
 @pytest.mark.parametrize("layout", ["soa", "aos"])
-@pytest.mark.parametrize("scheme", ["ts", "os_push", "os_pull", "aa"])
+@pytest.mark.parametrize("scheme", ["ts", "os_push", "os_pull", "aa", "et"])
 @pytest.mark.parametrize("steps", [12, 13])
 def test_open_boundaries_match_oracle(scheme, layout, steps):
     mask = duct()
@@ -71,7 +71,7 @@ def test_open_boundaries_match_oracle(scheme, layout, steps):
     np.testing.assert_allclose(m[1:], mo[1:], rtol=1e-10, atol=1e-13 * mo[0])
 
 
-@pytest.mark.parametrize("scheme", ["aa", "os_push"])
+@pytest.mark.parametrize("scheme", ["aa", "os_push", "et"])
 def test_open_boundaries_trt_match_oracle(scheme):
     mask = duct(16, 9, 11, seed=33)
     f0 = _state(mask, 34)
@@ -127,7 +127,7 @@ def test_uniform_duct_flow_is_fixed_on_gpu():
     ru[1:] = np.array(U)[:, None, None, None]
     f0 = oracle.fluid_view(oracle.init_equilibrium(ru, m), m)
     bc = {1: ("velocity", 1.0, U), 2: ("pressure", 1.0, U)}
-    for scheme in ("aa", "ts", "os_push", "os_pull"):
+    for scheme in ("aa", "ts", "os_push", "os_pull", "et"):
         grid = _grid(m, scheme, bc=bc)
         grid.set_pdfs(to_device(f0))
         grid.step(40, collider="trt")
@@ -182,11 +182,6 @@ def test_pressure_driven_slit_on_gpu():
 def test_refusals():
     import paper_1111_0922_amd as P
     mask = duct()
-    with pytest.raises(P.LbmError):
-        _grid(mask, "et")                                  # ET keeps walls only
-    grid = _grid(mask, "et", bc={1: ("wall", 1.0, (0, 0, 0))})
-    with pytest.raises(P.LbmError):
-        grid.set_boundary(1, "velocity", 1.0, (0.01, 0, 0))
     aa = _grid(mask, "aa", precision="f32")
     aa.init_equilibrium()
     with pytest.raises(P.LbmError):
