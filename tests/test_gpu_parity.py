@@ -218,3 +218,4 @@ def test_banded_block_order_bit_identical(scheme, layout, shape, precision):
         out.append(from_device(grid.get_pdfs()))
     for o in out[1:]:
         assert np.array_equal(o.view(np.int64), out[0].view(np.int64))
+

@@ -147,3 +147,24 @@ def test_fp16_pair_kernels_bit_identical_to_one_node(scheme, shape, walls):
     assert np.array_equal(out[0].view(np.int64), out[1].view(np.int64))
     want = oracle.fluid_view(oracle.run_ts(q0, solid, 5, 1.7, (1e-5, 2e-5, 0), precision="f16s", sigma=256.0), solid)
     assert float(np.max(np.abs(out[0] - want))) <= 8 * 2.0 ** -23
+
+
+@pytest.mark.parametrize("precision", ["f16s", "f32s", "f32"])
+@pytest.mark.parametrize("scheme", ["aa", "et", "os_pull"])
+@pytest.mark.parametrize("shape,walls", [((6, 5, 7), True), ((11, 3, 4), False), ((3, 1, 1), False)])
+def test_reduced_precision_ragged_boxes(precision, scheme, shape, walls):
+    """Direct boxes whose nx is not a power of two run the one-node kernels (no
+    row staging, no pairs); they follow the oracle with the same storage rounding."""
+    import lbm_inputs
+    nx, ny, nz = shape
+    solid = lbm_inputs.channel_mask(nx, ny, nz) if walls else np.zeros((nz, ny, nx), np.uint8)
+    ru = lbm_inputs.rho_u_field(solid.shape, lbm_inputs.velocity_noise(solid.shape, 1e-3, seed=15))
+    sigma = 256.0 if precision != "f32" else 1.0
+    q0 = oracle.quantize(oracle.init_equilibrium(ru, solid), solid, precision, sigma)
+    want = oracle.fluid_view(oracle.run_ts(q0, solid, 7, 1.3, (1e-5, 0, 2e-6), precision=precision, sigma=sigma),
+                             solid)
+    got, _, _ = _run(solid, scheme, precision, sigma, q0, 7, 1.3, (1e-5, 0, 2e-6))
+    if precision == "f16s":
+        assert float(np.max(np.abs(got - want))) <= 8 * 2.0 ** -23   # as in test_fp16_shifted_storage
+    else:
+        assert float(np.max(np.abs(got - want) / np.abs(want))) <= 5e-6  # 1e-6 per step, 7 steps
