@@ -263,7 +263,8 @@ static long pull_source(int x, int y, int z, int i, const int dims[3], const int
 /* Propagation loop of the two-step algorithm (pull form), B -> A. */
 /* Open boundaries (the in-/outlet routines the AA pattern needs in both
  * parities, Sec. 6).  A non-fluid cell with mask value m >= 2 belongs to
- * boundary class m - 1; bc[5 (m - 2) + 0..4] = {kind, rho, ux, uy, uz}:
+ * boundary class m - 1 (m <= 5; larger values are walls);
+ * bc[5 (m - 2) + 0..4] = {kind, rho, ux, uy, uz}:
  *   kind 0  wall: plain half-way bounce-back;
  *   kind 1  velocity boundary, a wall moving with u (Ladd 1994): the
  *           bounced population gains the momentum the moving wall imparts,
@@ -275,7 +276,7 @@ static long pull_source(int x, int y, int z, int i, const int dims[3], const int
  * walls.  `bounced` is f*_opp(i)(x, t), i the direction that arrives at x. */
 static double boundary_value(double bounced, int i, int m, const double *bc)
 {
-    if (m < 2 || !bc) return bounced;
+    if (m < 2 || m > 5 || !bc) return bounced;
     const double *e = bc + 5 * (m - 2);
     const int kind = (int)e[0];
     const double rho = e[1];
@@ -388,7 +389,7 @@ void ora_init_equilibrium(const double *rho_u, const uint8_t *solid, const int d
  * dimension) is the plain lexicographic order, x fastest.
  * cellmap[c] = fluid id or -1.  idx (optional, 18 rows of idx_pitch):
  * idx[k][n] = id of the cell at x_n + c_{k+1}, -1 if solid or outside a
- * non-periodic axis, -m for a boundary cell of mask value m >= 2.  Returns
+ * non-periodic axis, -m for a boundary cell of mask value 2 <= m <= 5.  Returns
  * the number of fluid nodes. */
 long ora_build_idx_brick(const uint8_t *solid, const int dims[3], const int periodic[3], const int brick[3],
                          int32_t *cellmap, int32_t *idx, long idx_pitch)
@@ -429,7 +430,8 @@ long ora_build_idx_brick(const uint8_t *solid, const int dims[3], const int peri
                     int32_t v = -1;
                     if (!out) {
                         long cc = p[0] + (long)nx * (p[1] + (long)ny * p[2]);
-                        v = solid[cc] ? -(int32_t)solid[cc] : cellmap[cc];
+                        const int mv = solid[cc];
+                        v = (mv >= 2 && mv <= 5) ? -mv : (mv ? -1 : cellmap[cc]);
                     }
                     idx[k * idx_pitch + n] = v;
                 }
