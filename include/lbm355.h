@@ -292,10 +292,9 @@ int lbm_reduce_moments(lbm_grid *g, double *d_out4, void *stream);
 /* ---------------------------------------------------------------- batches
  * Continuous batching of porous-media solves: many lattices of uneven sizes
  * (indirect SoA grids bound to the AA pattern, one storage precision) share
- * one persistent batched AA kernel.  A device workspace holds the slot table,
- * the tile list (tiles of 256 nodes, contiguous per slot), the reduction
- * partials and the per-slot moments; the launch shape is fixed, so one
- * captured graph stays valid while slots are added and removed.  A lattice's
+ * one batched AA kernel, one workgroup per tile.  A device workspace holds
+ * the slot table, the tile list (tiles of 256 nodes, contiguous per slot),
+ * the reduction partials and the per-slot moments.  A lattice's
  * update and moments are bit-identical to running it alone with lbm_step and
  * lbm_reduce_moments.  Slots that share a batch must not be stepped through
  * lbm_step meanwhile.  Callers serialise calls on one batch. */
@@ -326,8 +325,9 @@ int lbm_batch_remove(lbm_batch *b, int32_t slot);
  * slot's FP64 moments (M, Jx, Jy, Jz as lbm_reduce_moments) into the
  * workspace and, when h_moments is not NULL, copies them to h_moments
  * (pinned host memory, max_slots * 4 doubles; rows of empty slots are left
- * stale).  use_graph = 1 replays a captured graph (recaptured when k_steps or
- * h_moments change).  Asynchronous on `stream`: synchronise before reading
+ * stale).  use_graph = 1 replays a captured graph (recaptured when k_steps,
+ * h_moments or the number of tiles change).  Asynchronous on `stream`:
+ * synchronise before reading
  * h_moments. */
 int lbm_batch_run(lbm_batch *b, int32_t k_steps, double *h_moments, int32_t use_graph, void *stream);
 

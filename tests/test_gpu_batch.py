@@ -55,7 +55,7 @@ def test_alone_equals_mixed_bitwise(precision, use_graph):
         assert np.array_equal(m[slot].view(np.int64), m_alone.view(np.int64)), slot
 
 
-def test_slot_churn_reuses_graph_and_stays_exact():
+def test_slot_churn_stays_exact():
     import paper_1111_0922_amd as P
     K = 10
     batch = P.Batch(4, 2048, "f32", use_graph=True)
