@@ -11,7 +11,7 @@ from .grid import _ptr, _stream
 
 
 class Batch:
-    """Up to `max_slots` indirect AA lattices advanced together by one persistent kernel."""
+    """Up to `max_slots` indirect AA lattices advanced together by one batched kernel."""
 
     def __init__(self, max_slots: int, max_tiles: int, precision: str = "f32", use_graph: bool = True,
                  device=None):

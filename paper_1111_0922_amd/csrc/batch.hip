@@ -3,12 +3,13 @@
 // A batch holds up to max_slots lattices ("slots") of uneven sizes, each an
 // lbm_grid bound to the AA pattern on an indirect SoA grid.  Their nodes are
 // cut into tiles of BLOCK nodes; a device-resident tile list (slot, first
-// node) and slot table drive one persistent kernel that advances every active
-// slot by one time step per launch, each slot with its own parity (the AA
-// pattern alternates its even and odd kernels, Sec. 6).  Because the launch
-// shape is fixed and the tables live in device memory, one captured graph
-// (K step launches, the per-slot moment reduction and the copy of the
-// moments to the host) stays valid while slots come and go.
+// node) and slot table drive one kernel, one workgroup per tile, that
+// advances every active slot by one time step per launch, each slot with its
+// own parity (the AA pattern alternates its even and odd kernels, Sec. 6).
+// A run of K steps is one captured graph (K step launches, the per-slot
+// moment reduction and the copy of the moments to the host); since the
+// tables live in device memory it stays valid while slots come and go, and
+// is captured again only when the number of tiles changes.
 //
 // Determinism: a slot's nodes are updated by the same per-node code as the
 // single-lattice kernels, and its moments are reduced tile by tile and then

@@ -18,8 +18,9 @@ from lbm_cases import from_device, make_grid, rel_err, to_device
 pytestmark = pytest.mark.gpu
 
 
-def _sample_update(canon_t, solid, cells, omega, g):
-    """Oracle f(t+1) at `cells` (flat indices) from the canonical state f(t) (fluid nodes only)."""
+def _sample_update(canon_t, solid, cells, omega, g, **kw):
+    """Oracle f(t+1) at `cells` (flat indices) from the canonical state f(t) (fluid nodes only);
+    kw goes to oracle.run_ts (collider, precision, sigma, omega_minus, bc)."""
     nz, ny, nx = solid.shape
     ids = _fluid_ids(solid)
     out = []
@@ -32,7 +33,7 @@ def _sample_update(canon_t, solid, cells, omega, g):
         sub_s = solid.reshape(-1)[sub_cells]
         sub_ids = ids[sub_cells]
         sub_f = np.where(sub_ids >= 0, canon_t[:, np.maximum(sub_ids, 0)], 0.0)
-        nxt = oracle.run_ts(sub_f, sub_s, 1, omega, g, periodic=(0, 0, 0))
+        nxt = oracle.run_ts(sub_f, sub_s, 1, omega, g, periodic=(0, 0, 0), **kw)
         out.append(nxt[:, 1, 1, 1])
     return np.array(out).T
 
@@ -70,6 +71,72 @@ def test_256_channel_sampled(scheme, layout):
         del ft, ft1
     m1 = from_device(grid.moments())
     assert abs(m1[0] - m0[0]) / m0[0] <= 1e-13
+
+
+@pytest.mark.parametrize("case", ["f16s", "f32", "trt"])
+def test_256_channel_sampled_precision_and_trt(case):
+    """The benchmark's FP16 (two nodes per lane), FP32 and TRT runs at full size."""
+    n = 256
+    solid = lbm_inputs.channel_mask(n, n, n)
+    omega, g = 1.6, (1e-6, 0.0, 0.0)
+    prec = case if case != "trt" else "f64"
+    sigma = 1024.0 if prec == "f16s" else 1.0
+    rng = np.random.default_rng(2)
+    grid = make_grid(solid, "aa", precision=prec, omega=omega, g=g, f16_scale=sigma)
+    nf = grid.n_nodes
+    u = torch.from_numpy(lbm_inputs.velocity_noise((n - 2, n, n), 1e-3, seed=1).reshape(3, -1))
+    grid.init_equilibrium(torch.cat([torch.ones(1, nf, dtype=torch.float64), u], 0).cuda())
+    collider = "trt" if case == "trt" else "bgk"
+    kw = {"collider": collider}
+    if case == "trt":
+        kw["omega_minus"] = oracle.trt_omega_minus(omega, 3.0 / 16.0)
+    if prec != "f64":
+        kw.update(precision=prec, sigma=sigma)
+    grid.step(9, collider=collider)
+    for extra in (1, 2):
+        ft = from_device(grid.get_pdfs())
+        grid.step(1, collider=collider)
+        ft1 = from_device(grid.get_pdfs())
+        cells = rng.choice(np.flatnonzero(solid.reshape(-1) == 0), 300, replace=False)
+        ids = _fluid_ids(solid)[cells]
+        want = _sample_update(ft, solid, cells, omega, g, **kw)
+        if prec == "f16s":       # one binary16 code of h = (f - w) sigma may round the other way: 2^-23 in f
+            assert float(np.max(np.abs(ft1[:, ids] - want))) <= 4 * 2.0 ** -23, extra
+        elif prec == "f32":      # FP32 arithmetic of one collision: 16 ulp
+            assert rel_err(ft1[:, ids], want) <= 1e-6, extra
+        else:
+            assert rel_err(ft1[:, ids], want) <= 1e-12, extra
+        del ft, ft1
+
+
+def test_256_duct_open_boundaries_sampled():
+    """The benchmark's 256^3 duct (velocity inlet, pressure outlet, walls) at full size; the
+    samples include nodes next to the inlet and the outlet."""
+    n = 256
+    duct = np.zeros((n, n, n), np.uint8)
+    duct[:, :, 0] = 2
+    duct[:, :, n - 1] = 3
+    duct[0] = 1
+    duct[n - 1] = 1
+    bc = {1: ("velocity", 1.0, (0.01, 0.0, 0.0)), 2: ("pressure", 1.0, (0.01, 0.0, 0.0))}
+    omega, g = 1.6, (0.0, 0.0, 0.0)
+    grid = make_grid(duct, "aa", addressing="indirect", omega=omega, g=g)
+    for cls, (kind, rho, u) in bc.items():
+        grid.set_boundary(cls, kind, rho, u)
+    grid.init_equilibrium()
+    grid.step(9)
+    rng = np.random.default_rng(3)
+    fluid = np.flatnonzero(duct.reshape(-1) == 0)
+    for extra in (1, 2):
+        ft = from_device(grid.get_pdfs())
+        grid.step(1)
+        ft1 = from_device(grid.get_pdfs())
+        edge = fluid[(fluid % n == 1) | (fluid % n == n - 2)]
+        cells = np.concatenate([rng.choice(fluid, 200, replace=False), rng.choice(edge, 100, replace=False)])
+        ids = _fluid_ids(duct)[cells]
+        want = _sample_update(ft, duct, cells, omega, g, bc=bc)
+        assert rel_err(ft1[:, ids], want) <= 1e-12, extra
+        del ft, ft1
 
 
 @pytest.fixture(scope="module")
