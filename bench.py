@@ -305,7 +305,11 @@ def main():
                          "nodes": nf, "lattice": "256x256x256", "layout": "soa", "addressing": "direct",
                          "scheme": "aa"},
               "roofline": roofline,
-              "mass_drift": float(abs(m1[0] - m0[0]) / m0[0])}
+              "mass_drift": float(abs(m1[0] - m0[0]) / m0[0]),
+              # the paper's measured numbers: CPU nodes, FP64 TRT, indirect SoA (Sec. 10); context only
+              "paper_context": {"aa_MLUP_s": ">100", "hardware": "2-socket Westmere (2x Xeon X5650, 12 cores)",
+                                "workload": "FP64 TRT, indirect addressing, SoA, channel and packed bed",
+                                "source": "Sec. 10 (text; the figures' curves are not available)"}}
 
     if not args.only_main:
         log("[bench] copy calibration")
