@@ -326,8 +326,13 @@ int lbm_batch_remove(lbm_batch *b, int32_t slot);
  * workspace and, when h_moments is not NULL, copies them to h_moments
  * (pinned host memory, max_slots * 4 doubles; rows of empty slots are left
  * stale).  use_graph = 1 replays a captured graph (recaptured when k_steps,
- * h_moments or the number of tiles change).  Asynchronous on `stream`:
- * synchronise before reading
+ * h_moments or the number of tiles change); 0 launches the kernels directly;
+ * 2 runs all k_steps in one cooperative launch whose workgroups (as many as
+ * the device keeps resident) stride over the tiles and meet at a grid
+ * barrier between steps, then reduces, and synchronises `stream` before
+ * returning (LBM_E_HIP if a barrier wait exceeded its bound).  Same results
+ * in every mode.  Modes 0 and 1 are asynchronous on `stream`: synchronise
+ * before reading
  * h_moments. */
 int lbm_batch_run(lbm_batch *b, int32_t k_steps, double *h_moments, int32_t use_graph, void *stream);
 

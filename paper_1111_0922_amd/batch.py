@@ -13,8 +13,11 @@ from .grid import _ptr, _stream
 class Batch:
     """Up to `max_slots` indirect AA lattices advanced together by one batched kernel."""
 
+    MODES = {"launches": 0, "graph": 1, "cooperative": 2}
+
     def __init__(self, max_slots: int, max_tiles: int, precision: str = "f32", use_graph: bool = True,
-                 device=None):
+                 device=None, mode: str | None = None):
+        """mode: 'graph' (default with use_graph), 'launches', or 'cooperative' (one launch per run)."""
         self.lib = L.load()
         self.device = torch.device(device) if device is not None else torch.device("cuda")
         nbytes = ctypes.c_int64(0)
@@ -24,7 +27,7 @@ class Batch:
         L.check(self.lib.lbm_batch_create(int(max_slots), int(max_tiles), L.PRECISIONS[precision],
                                           _ptr(self.workspace), ctypes.byref(self._h)))
         self.max_slots = int(max_slots)
-        self.use_graph = bool(use_graph)
+        self.mode = self.MODES[mode if mode is not None else ("graph" if use_graph else "launches")]
         self.moments_host = torch.zeros((self.max_slots, 4), dtype=torch.float64, pin_memory=True)
         self.grids = {}
 
@@ -47,7 +50,7 @@ class Batch:
     def run_async(self, k_steps: int):
         """Enqueue k_steps for every slot plus the per-slot moments (copied to `moments_host`)."""
         L.check(self.lib.lbm_batch_run(self._h, int(k_steps), ctypes.c_void_p(self.moments_host.data_ptr()),
-                                       int(self.use_graph), _stream(self.device)))
+                                       self.mode, _stream(self.device)))
 
     def run(self, k_steps: int) -> np.ndarray:
         """k_steps for every slot; returns float64[max_slots, 4] moments after synchronising."""

@@ -17,6 +17,7 @@
 // the same bits alone or in any mix.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -104,6 +105,71 @@ __global__ void __launch_bounds__(BLOCK) k_aa_batched(const SlotDesc *slots, con
             update_node<A_INDIRECT, L_SOA, PREC, K_AA_ODD, 1>(a, n);
         else
             update_node<A_INDIRECT, L_SOA, PREC, K_AA_EVEN, 1>(a, n);
+    }
+}
+
+// Grid barrier of the cooperative run (every workgroup is resident).  Words
+// of the workspace header: hdr[4] arrivals, hdr[5] generation, hdr[6] set when
+// a wait exceeded its bound.  Thread 0 of each workgroup reads the
+// generation, then arrives; the last arrival resets the count and advances
+// the generation (release), the others wait for that change.  The
+// agent-scope fences write this workgroup's results back to memory before it
+// arrives and drop stale lines after it leaves, as a kernel boundary does
+// (each XCD has its own L2).  Waits are bounded, so every wave ends; a
+// timed-out wait sets hdr[6] and the run reports an error.
+constexpr uint32_t BARRIER_SPIN_LIMIT = 1u << 20;
+
+__device__ __forceinline__ bool grid_barrier(uint32_t *hdr)
+{
+    __shared__ uint32_t ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t *count = hdr + 4, *gen = hdr + 5, *flag = hdr + 6;
+        __threadfence();
+        const uint32_t g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t good = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
+        if (__hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1) {
+            __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            uint32_t spins = 0;
+            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > BARRIER_SPIN_LIMIT) {
+                    __hip_atomic_fetch_or(flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    good = 0;
+                    break;
+                }
+            }
+        }
+        __threadfence();
+        ok = good;
+    }
+    __syncthreads();
+    return ok != 0;
+}
+
+// All k_steps steps in one cooperative launch: the workgroups stride over the
+// tile list and meet at a grid barrier between steps.
+template <int PREC>
+__global__ void __launch_bounds__(BLOCK) k_aa_batched_coop(const SlotDesc *slots, const Tile *tiles, uint32_t *hdr,
+                                                            int32_t k_steps, char *base)
+{
+    const uint32_t nt = hdr[0];
+    for (int32_t k = 0; k < k_steps; ++k) {
+        for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+            const Tile tl = tiles[tile];
+            const SlotDesc sd = slots[tl.slot];
+            const KArgs a = slot_args<PREC>(sd, base);
+            const uint32_t n = tl.node0 + threadIdx.x;
+            if (n < sd.n_nodes) {
+                if ((sd.t0 + k) & 1)
+                    update_node<A_INDIRECT, L_SOA, PREC, K_AA_ODD, 1>(a, n);
+                else
+                    update_node<A_INDIRECT, L_SOA, PREC, K_AA_EVEN, 1>(a, n);
+            }
+        }
+        if (k + 1 < k_steps && !grid_barrier(hdr)) return;
     }
 }
 
@@ -198,6 +264,33 @@ int64_t ws_offset(const lbm_batch *b, const void *p)
 // Workgroups of the batched launches: one per tile.
 uint32_t batch_blocks(const lbm_batch *b) { return b->hdr_host[0] > 0 ? b->hdr_host[0] : 1u; }
 
+// Cooperative run: one launch of all steps, workgroups limited to what the
+// device keeps resident at once.
+template <int PREC>
+int launch_coop(lbm_batch *b, int32_t k_steps, hipStream_t s)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    int rc = hip_check(hipGetDevice(&dev), "lbm_batch_run (device)");
+    if (rc) return rc;
+    rc = hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "lbm_batch_run (CUs)");
+    if (rc) return rc;
+    rc = hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_aa_batched_coop<PREC>, BLOCK, 0),
+                   "lbm_batch_run (occupancy)");
+    if (rc) return rc;
+    const uint32_t resident = (uint32_t)std::max(1, cus * per_cu);
+    const uint32_t grid = std::max(1u, std::min(b->hdr_host[0], resident));
+    const SlotDesc *slots = b->d_slots;
+    const Tile *tiles = b->d_tiles;
+    uint32_t *hdr = b->d_hdr;
+    char *base = ws_base(b);
+    void *args[] = {(void *)&slots, (void *)&tiles, (void *)&hdr, (void *)&k_steps, (void *)&base};
+    return hip_check(hipLaunchCooperativeKernel((const void *)k_aa_batched_coop<PREC>, dim3(grid), dim3(BLOCK), args,
+                                                0, s),
+                     "lbm_batch_run (cooperative launch)");
+}
+
+void launch_reduce_body(lbm_batch *b, int32_t k_steps, double *h_out, hipStream_t s);
+
 void launch_batch_body(lbm_batch *b, int32_t k_steps, double *h_out, hipStream_t s)
 {
     const uint32_t nb = batch_blocks(b);
@@ -215,6 +308,13 @@ void launch_batch_body(lbm_batch *b, int32_t k_steps, double *h_out, hipStream_t
             hipLaunchKernelGGL(k_aa_batched<P_F32S>, dim3(nb), dim3(BLOCK), LBM_BATCH_LDS, s, b->d_slots, b->d_tiles,
                                b->d_hdr, k, ws_base(b));
     }
+    launch_reduce_body(b, k_steps, h_out, s);
+}
+
+// Per-slot FP64 moments of the state after the run, and their copy to the host.
+void launch_reduce_body(lbm_batch *b, int32_t k_steps, double *h_out, hipStream_t s)
+{
+    const uint32_t nb = batch_blocks(b);
     if (b->precision == LBM_F64)
         hipLaunchKernelGGL(k_seg_partials<P_F64>, dim3(nb), dim3(BLOCK), 0, s, b->d_slots, b->d_tiles,
                            b->d_hdr, b->d_partials, k_steps, ws_base(b));
@@ -372,7 +472,31 @@ int lbm_batch_run(lbm_batch *b, int32_t k_steps, double *h_moments, int32_t use_
     int rc = hip_check(hipMemcpyAsync(b->d_slots, b->slots.data(), b->slots.size() * sizeof(SlotDesc),
                                       hipMemcpyHostToDevice, s), "lbm_batch_run (slots)");
     if (rc) return rc;
-    if (use_graph) {
+    if (use_graph == 2) {
+        // cooperative: all steps in one launch, then the moments; synchronous,
+        // so that a timed-out barrier is reported here
+        static const uint32_t zeros[3] = {0, 0, 0};
+        rc = hip_check(hipMemcpyAsync(b->d_hdr + 4, zeros, sizeof zeros, hipMemcpyHostToDevice, s),
+                       "lbm_batch_run (barrier words)");
+        if (rc) return rc;
+        if (b->precision == LBM_F64)
+            rc = launch_coop<P_F64>(b, k_steps, s);
+        else if (b->precision == LBM_F32)
+            rc = launch_coop<P_F32>(b, k_steps, s);
+        else if (b->precision == LBM_F16S)
+            rc = launch_coop<P_F16S>(b, k_steps, s);
+        else
+            rc = launch_coop<P_F32S>(b, k_steps, s);
+        if (rc) return rc;
+        launch_reduce_body(b, k_steps, h_moments, s);
+        rc = hip_check(hipStreamSynchronize(s), "lbm_batch_run (cooperative run)");
+        if (rc) return rc;
+        uint32_t timed_out = 0;
+        rc = hip_check(hipMemcpy(&timed_out, b->d_hdr + 6, sizeof timed_out, hipMemcpyDeviceToHost),
+                       "lbm_batch_run (barrier flag)");
+        if (rc) return rc;
+        if (timed_out) return fail(LBM_E_HIP, "cooperative batch run: a grid barrier wait exceeded its bound");
+    } else if (use_graph) {
         if (!b->exec || b->graph_k != k_steps || b->graph_out != h_moments || b->graph_blocks != batch_blocks(b)) {
             drop_graph(b);
             rc = hip_check(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed), "lbm_batch_run (capture)");

@@ -120,3 +120,29 @@ def test_serving_end_to_end_small():
         assert r.steps > 0 and r.finished is not None
         assert np.isfinite(r.permeability) and r.permeability > 0
     assert sch.peak_used <= 8 << 30
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_cooperative_run_matches_graph_run_bitwise(precision):
+    """All steps in one cooperative launch (grid barrier between steps) give the
+    bits of the graph of one launch per step, states and moments, over two runs."""
+    import paper_1111_0922_amd as P
+    K = 9
+    out = {}
+    for mode in ("graph", "cooperative"):
+        batch = P.Batch(8, 4096, precision, mode=mode)
+        grids = []
+        for i, gm in enumerate(GEOMS):
+            grid, _ = _grid(*gm, precision)
+            if i == 2:
+                grid.step(1)            # a slot at the other parity
+            grids.append((batch.add(grid), grid))
+        for _ in range(2):
+            m = batch.run(K)
+        out[mode] = ([from_device(g.get_pdfs()) for _, g in grids], [m[s].copy() for s, _ in grids],
+                     [g.t for _, g in grids])
+    for a, b in zip(out["graph"][0], out["cooperative"][0]):
+        assert np.array_equal(a.view(np.int64), b.view(np.int64))
+    for a, b in zip(out["graph"][1], out["cooperative"][1]):
+        assert np.array_equal(a.view(np.int64), b.view(np.int64))
+    assert out["graph"][2] == out["cooperative"][2]
