@@ -146,13 +146,17 @@ KArgs base_args(const lbm_grid *g)
         if (d.precision == LBM_F64) lds = 45056;
         if (d.precision == LBM_F32 || d.precision == LBM_F32S) lds = d.addressing == LBM_DIRECT ? 40960 : 53248;
     }
-    a.lds_bytes = (uint32_t)(g->wg_lds >= 0 ? g->wg_lds : lds);
+    a.lds_bytes = (uint32_t)(g->wg_lds >= 0 ? g->wg_lds : lds); // pair kernels: see below
     // whole x-rows per workgroup: nx a power of two dividing the workgroup size
     a.row_staged = (d.addressing == LBM_DIRECT && d.layout == LBM_SOA && g->row_stage && d.nx <= BLOCK &&
                     (d.nx & (d.nx - 1)) == 0) ? 1 : 0;
-    // two nodes per lane for 16-bit storage: nx a power of two dividing 2 * BLOCK
-    a.pair = (d.addressing == LBM_DIRECT && d.layout == LBM_SOA && d.precision == LBM_F16S && g->pair &&
-              d.nx >= 2 && d.nx <= 2 * BLOCK && (d.nx & (d.nx - 1)) == 0) ? 1 : 0;
+    // two nodes per lane: nx a power of two dividing 2 * BLOCK; by default for
+    // 16-bit storage (measured below for the others)
+    const bool pair_on = g->pair > 0 || (g->pair < 0 && d.precision == LBM_F16S);
+    a.pair = (d.addressing == LBM_DIRECT && d.layout == LBM_SOA && pair_on && d.nx >= 2 && d.nx <= 2 * BLOCK &&
+              (d.nx & (d.nx - 1)) == 0) ? 1 : 0;
+    // the pair kernels' registers already hold them to two or three workgroups per CU
+    if (a.pair && g->wg_lds < 0) a.lds_bytes = 0;
     a.omega = d.omega;
     a.gx = d.g[0];
     a.gy = d.g[1];
@@ -297,7 +301,8 @@ int lbm_set_option(lbm_grid *g, int32_t option, int64_t value)
         return LBM_OK;
     }
     if (option == LBM_OPT_PAIR) {
-        g->pair = value ? 1 : 0;
+        if (value < -1 || value > 1) return fail(LBM_E_ARG, "pair must be -1, 0 or 1");
+        g->pair = (int)value;
         return LBM_OK;
     }
     if (option == LBM_OPT_BAND) {
@@ -504,7 +509,7 @@ int lbm_step(lbm_grid *g, int32_t scheme, int32_t collider, int64_t n_steps, voi
     const uint32_t nb = update_blocks(g, a);
     auto launch = [&](int kind) {
         set_block_order(g, a, kind);
-        tb.update[A][L][C][kind](a, nb, s);
+        (a.pair ? tb.pair[C][kind] : tb.update[A][L][C][kind])(a, nb, s);
     };
     if (collider == LBM_TRT) {
         // Lambda = (1/w+ - 1/2)(1/w- - 1/2)

@@ -28,7 +28,7 @@ struct lbm_grid {
     int64_t pitch_pad = 0; // extra SoA elements between direction arrays
     int64_t wg_lds = -1;   // dynamic LDS reserved per update workgroup (-1: per-precision default)
     int row_stage = 1;     // allow the row-staged direct SoA kernels
-    int pair = 1;          // allow two nodes per lane (16-bit direct SoA)
+    int pair = -1;         // two nodes per lane on direct SoA grids: 1 on, 0 off, -1 default
     int band = -1;         // XCD band height (blocks) of the direct-grid block order, 0 = off, -1 = default
     // open-boundary classes 1..4 (indirect grids): kind, density, velocity
     int bc_kind[4] = {0, 0, 0, 0};

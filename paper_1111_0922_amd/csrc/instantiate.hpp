@@ -10,6 +10,11 @@ void launch_update(const KArgs &a, uint32_t blocks, hipStream_t s)
 {
     hipLaunchKernelGGL((k_update<A, L, P, K, C>), dim3(blocks), dim3(BLOCK), a.lds_bytes, s, a);
 }
+template <int P, int K, int C>
+void launch_pair(const KArgs &a, uint32_t blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_update_pair<P, K, C>), dim3(blocks), dim3(BLOCK), a.lds_bytes, s, a);
+}
 template <int A, int L, int P, int R>
 void launch_get(const KArgs &a, uint32_t blocks, hipStream_t s)
 {
@@ -44,6 +49,19 @@ void fill_updates(PrecTable &t)
     t.update[A][L][C][K_ET1] = &launch_update<A, L, P, K_ET1, C>;
 }
 
+template <int P, int C>
+void fill_pairs(PrecTable &t)
+{
+    t.pair[C][K_TS_COLLIDE] = &launch_pair<P, K_TS_COLLIDE, C>;
+    t.pair[C][K_TS_STREAM] = &launch_pair<P, K_TS_STREAM, 0>; // no collision
+    t.pair[C][K_OS_PUSH] = &launch_pair<P, K_OS_PUSH, C>;
+    t.pair[C][K_OS_PULL] = &launch_pair<P, K_OS_PULL, C>;
+    t.pair[C][K_AA_EVEN] = &launch_pair<P, K_AA_EVEN, C>;
+    t.pair[C][K_AA_ODD] = &launch_pair<P, K_AA_ODD, C>;
+    t.pair[C][K_ET0] = &launch_pair<P, K_ET0, C>;
+    t.pair[C][K_ET1] = &launch_pair<P, K_ET1, C>;
+}
+
 template <int A, int L, int P, int R>
 void fill_map(PrecTable &t)
 {
@@ -70,6 +88,8 @@ PrecTable make_table()
 {
     PrecTable t{};
     fill_al<A_DIRECT, L_SOA, P>(t);
+    fill_pairs<P, 0>(t);
+    fill_pairs<P, 1>(t);
     fill_al<A_DIRECT, L_AOS, P>(t);
     fill_al<A_INDIRECT, L_SOA, P>(t);
     fill_al<A_INDIRECT, L_AOS, P>(t);

@@ -559,28 +559,64 @@ __device__ __forceinline__ void update_direct_staged(const KArgs &a)
     }
 }
 
-// Direct SoA update of two x-neighbours (x even, x + 1) per lane, for 16-bit
-// storage: the pair's values of one direction form one aligned 32-bit word,
-// so each load or store of a wavefront covers 256 contiguous bytes instead of
-// 128.  Both nodes share y and z, hence every bounce-back decision.  nx is a
-// power of two dividing 2 * BLOCK, so a workgroup holds whole x-rows and the
-// x-shifts go through LDS as in update_direct_staged (each lane deposits or
-// picks up two 16-bit values).  Per node the arithmetic is that of the
-// one-node kernels, so the results are bit-identical.
+// Direct SoA update of two x-neighbours (x even, x + 1) per lane: the pair's
+// values of one direction form one aligned word (2 x 16, 2 x 32 or 2 x 64
+// bits), so each load or store of a wavefront covers twice the bytes of the
+// one-node kernels with the same number of instructions.  Both nodes share y
+// and z, hence every bounce-back decision.  nx is a power of two dividing
+// 2 * BLOCK, so a workgroup holds whole x-rows and the x-shifts go through
+// LDS as in update_direct_staged (each lane deposits or picks up two
+// values).  Per node the arithmetic is that of the one-node kernels, so the
+// results are bit-identical.
 typedef uint16_t __attribute__((may_alias)) u16_alias;
 typedef uint32_t __attribute__((may_alias)) u32_alias;
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+template <int PREC>
+struct Pair;
+template <>
+struct Pair<P_F16S> {
+    using word = uint32_t; // node x in the low half, x + 1 in the high half
+    using elem = uint16_t;
+    __device__ static elem lo(word w) { return (elem)(w & 0xffffu); }
+    __device__ static elem hi(word w) { return (elem)(w >> 16); }
+    __device__ static word join(elem a, elem b) { return (word)a | ((word)b << 16); }
+    __device__ static float load(elem e) { return (float)__builtin_bit_cast(_Float16, e); }
+    __device__ static elem save(float v) { return __builtin_bit_cast(uint16_t, (_Float16)v); }
+};
+template <typename E, typename V>
+struct PairPlain {
+    using word = V;
+    using elem = E;
+    __device__ static elem lo(word w) { return w.x; }
+    __device__ static elem hi(word w) { return w.y; }
+    __device__ static word join(elem a, elem b) { return word{a, b}; }
+    __device__ static E load(elem e) { return e; }
+    __device__ static elem save(E v) { return v; }
+};
+template <>
+struct Pair<P_F32> : PairPlain<float, v2f> {};
+template <>
+struct Pair<P_F32S> : PairPlain<float, v2f> {};
+template <>
+struct Pair<P_F64> : PairPlain<double, v2d> {};
 
 template <int PREC, int KIND, int COLL>
 __device__ __forceinline__ void update_direct_pair(const KArgs &a)
 {
     using S = Store<PREC>;
     using ct = typename S::ct;
-    static_assert(sizeof(typename S::st) == 2, "two 16-bit values per 32-bit word");
+    using PW = Pair<PREC>;
+    using word = typename PW::word;
+    using el_t = typename PW::elem;
+    typedef el_t __attribute__((may_alias)) elem_alias;
+    typedef word __attribute__((may_alias)) word_alias;
     constexpr int R = rmap_of(KIND);
     constexpr int W = wmap_of(KIND);
     constexpr bool shifts = !(R == R_LOCAL && (W == W_LOCAL || W == W_AAEVEN));
     constexpr uint32_t NP = 2 * BLOCK; // nodes per workgroup
-    __shared__ uint32_t xw[shifts ? NXSLOT : 1][shifts ? BLOCK : 1];
+    __shared__ word xw[shifts ? NXSLOT : 1][shifts ? BLOCK : 1];
     const uint32_t t = threadIdx.x;
     const uint32_t p = 2 * t;          // the pair's first node within the workgroup
     const uint32_t n = logical_block(a) * NP + p;
@@ -589,14 +625,12 @@ __device__ __forceinline__ void update_direct_pair(const KArgs &a)
     const uint32_t xl = p & (nx - 1), row = p - xl;
     Node<A_DIRECT, 0> nd;
     nd.init(a, valid ? n : 0);
-    const uint32_t *src = static_cast<const uint32_t *>(a.src);
-    uint32_t *dst = static_cast<uint32_t *>(a.dst);
-    auto h2f = [](uint32_t h) { return S::load(__builtin_bit_cast(_Float16, (uint16_t)h)); };
-    auto f2h = [](ct v) { return (uint32_t)__builtin_bit_cast(uint16_t, S::save(v)); };
-    auto lds16 = [&](int slot) { return reinterpret_cast<u16_alias *>(&xw[slot][0]); };
+    const word *src = static_cast<const word *>(a.src);
+    word *dst = static_cast<word *>(a.dst);
+    auto lds = [&](int slot) { return reinterpret_cast<elem_alias *>(&xw[slot][0]); };
     // all 19 word loads first, at the pair's own x (unconditional: a lane
     // past n_nodes addresses node 0 and never stores)
-    uint32_t raw[Q];
+    word raw[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         int j, sx, sy, sz;
@@ -609,10 +643,10 @@ __device__ __forceinline__ void update_direct_pair(const KArgs &a)
         int j, sx, sy, sz;
         read_off<R>(nd, i, j, sx, sy, sz);
         if (shifts && xslot(i) >= 0 && sx != 0) {
-            reinterpret_cast<u32_alias *>(&xw[xslot(i) < 0 ? 0 : xslot(i)][0])[t] = raw[i];
+            reinterpret_cast<word_alias *>(&xw[xslot(i) < 0 ? 0 : xslot(i)][0])[t] = raw[i];
         } else {
-            v0[i] = h2f(raw[i] & 0xffffu);
-            v1[i] = h2f(raw[i] >> 16);
+            v0[i] = PW::load(PW::lo(raw[i]));
+            v1[i] = PW::load(PW::hi(raw[i]));
         }
     }
     if constexpr (shifts) {
@@ -623,9 +657,9 @@ __device__ __forceinline__ void update_direct_pair(const KArgs &a)
                 int j, sx, sy, sz;
                 read_off<R>(nd, i, j, sx, sy, sz);
                 if (sx != 0) {
-                    const u16_alias *h = lds16(xslot(i) < 0 ? 0 : xslot(i));
-                    v0[i] = h2f(h[row + ((xl + (uint32_t)sx) & (nx - 1))]);
-                    v1[i] = h2f(h[row + ((xl + 1u + (uint32_t)sx) & (nx - 1))]);
+                    const elem_alias *h = lds(xslot(i) < 0 ? 0 : xslot(i));
+                    v0[i] = PW::load(h[row + ((xl + (uint32_t)sx) & (nx - 1))]);
+                    v1[i] = PW::load(h[row + ((xl + 1u + (uint32_t)sx) & (nx - 1))]);
                 }
             }
         }
@@ -641,12 +675,13 @@ __device__ __forceinline__ void update_direct_pair(const KArgs &a)
         int j, sx, sy, sz;
         write_off<W>(nd, i, j, sx, sy, sz);
         if (shifts && xslot(i) >= 0 && sx != 0) {
-            u16_alias *h = lds16(xslot(i) < 0 ? 0 : xslot(i));
-            h[row + ((xl + (uint32_t)sx) & (nx - 1))] = (uint16_t)f2h(v0[i]);
-            h[row + ((xl + 1u + (uint32_t)sx) & (nx - 1))] = (uint16_t)f2h(v1[i]);
+            elem_alias *h = lds(xslot(i) < 0 ? 0 : xslot(i));
+            h[row + ((xl + (uint32_t)sx) & (nx - 1))] = PW::save(v0[i]);
+            h[row + ((xl + 1u + (uint32_t)sx) & (nx - 1))] = PW::save(v1[i]);
             continue;
         }
-        if (valid) pdf_store<true>(dst + (elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch) >> 1), f2h(v0[i]) | (f2h(v1[i]) << 16));
+        if (valid) pdf_store<true>(dst + (elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch) >> 1),
+                                   PW::join(PW::save(v0[i]), PW::save(v1[i])));
     }
     if constexpr (shifts) {
         __syncthreads();
@@ -657,7 +692,7 @@ __device__ __forceinline__ void update_direct_pair(const KArgs &a)
                 write_off<W>(nd, i, j, sx, sy, sz);
                 if (sx != 0 && valid)
                     pdf_store<true>(dst + (elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch) >> 1),
-                                    (uint32_t)reinterpret_cast<const u32_alias *>(&xw[xslot(i) < 0 ? 0 : xslot(i)][0])[t]);
+                                    (word)reinterpret_cast<const word_alias *>(&xw[xslot(i) < 0 ? 0 : xslot(i)][0])[t]);
             }
         }
     }
@@ -815,6 +850,14 @@ __device__ __forceinline__ void update_aos_staged(const KArgs &a)
     }
 }
 
+// Two nodes per lane on direct SoA grids (a kernel of its own: its registers
+// and LDS would otherwise count against every one-node kernel).
+template <int PREC, int KIND, int COLL>
+__global__ void __launch_bounds__(BLOCK) k_update_pair(KArgs a)
+{
+    update_direct_pair<PREC, KIND, COLL>(a);
+}
+
 template <int ADDR, int LAY, int PREC, int KIND, int COLL>
 __global__ void __launch_bounds__(BLOCK) k_update(KArgs a)
 {
@@ -822,12 +865,6 @@ __global__ void __launch_bounds__(BLOCK) k_update(KArgs a)
     constexpr int W = wmap_of(KIND);
     // kernels whose maps never shift along x need no staging
     constexpr bool shifts = !(R == R_LOCAL && (W == W_LOCAL || W == W_AAEVEN));
-    if constexpr (ADDR == A_DIRECT && LAY == L_SOA && sizeof(typename Store<PREC>::st) == 2) {
-        if (a.pair) {
-            update_direct_pair<PREC, KIND, COLL>(a);
-            return;
-        }
-    }
     if constexpr (ADDR == A_DIRECT && LAY == L_SOA && shifts) {
         if (a.row_staged) {
             update_direct_staged<PREC, KIND, COLL>(a);
@@ -997,6 +1034,7 @@ using Launch = void (*)(const KArgs &, uint32_t, hipStream_t);
 
 struct PrecTable {
     Launch update[2][2][2][K_NUM]; // [addr][layout][collider][kind]
+    Launch pair[2][K_NUM];         // direct SoA, two nodes per lane: [collider][kind]
     Launch get[2][2][R_NUM];
     Launch set[2][2][R_NUM];
     Launch init[2][2][R_NUM];

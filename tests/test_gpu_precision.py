@@ -125,28 +125,38 @@ def test_permeability_chain_to_steady_state():
         assert abs(k - k_oracle) / k_oracle <= bound, (precision, k, k_oracle)
 
 
+@pytest.mark.parametrize("precision", ["f16s", "f32", "f32s", "f64"])
 @pytest.mark.parametrize("scheme", ["ts", "os_push", "os_pull", "aa", "et"])
 @pytest.mark.parametrize("shape,walls", [((32, 32, 32), True), ((2, 3, 5), False), ((4, 4, 2), False),
                                          ((64, 6, 5), True), ((512, 3, 4), True), ((256, 5, 3), False)])
-def test_fp16_pair_kernels_bit_identical_to_one_node(scheme, shape, walls):
-    """FP16 direct SoA grids with nx a power of two update two nodes per lane;
+def test_pair_kernels_bit_identical_to_one_node(precision, scheme, shape, walls):
+    """Direct SoA grids with nx a power of two can update two nodes per lane;
     one node per lane must give the same bits, and both follow the oracle."""
     import lbm_inputs
     import paper_1111_0922_amd as P
     nx, ny, nz = shape
     solid = lbm_inputs.channel_mask(nx, ny, nz) if walls else np.zeros((nz, ny, nx), np.uint8)
     ru = lbm_inputs.rho_u_field(solid.shape, lbm_inputs.velocity_noise(solid.shape, 1e-3, seed=13))
-    q0 = oracle.quantize(oracle.init_equilibrium(ru, solid), solid, "f16s", 256.0)
+    sigma = 256.0 if precision in ("f16s", "f32s") else 1.0
+    q0 = oracle.init_equilibrium(ru, solid)
+    if precision != "f64":
+        q0 = oracle.quantize(q0, solid, precision, sigma)
     out = []
     for pair in (1, 0):
-        grid = make_grid(solid, scheme, precision="f16s", omega=1.7, g=(1e-5, 2e-5, 0), f16_scale=256.0)
+        grid = make_grid(solid, scheme, precision=precision, omega=1.7, g=(1e-5, 2e-5, 0), f16_scale=sigma)
         grid.set_option(P._lib.OPT_PAIR, pair)
         grid.set_pdfs(to_device(oracle.fluid_view(q0, solid)))
         grid.step(5)
         out.append(from_device(grid.get_pdfs()))
     assert np.array_equal(out[0].view(np.int64), out[1].view(np.int64))
-    want = oracle.fluid_view(oracle.run_ts(q0, solid, 5, 1.7, (1e-5, 2e-5, 0), precision="f16s", sigma=256.0), solid)
-    assert float(np.max(np.abs(out[0] - want))) <= 8 * 2.0 ** -23
+    want = oracle.fluid_view(oracle.run_ts(q0, solid, 5, 1.7, (1e-5, 2e-5, 0),
+                                           precision=None if precision == "f64" else precision, sigma=sigma), solid)
+    if precision == "f16s":
+        assert float(np.max(np.abs(out[0] - want))) <= 8 * 2.0 ** -23
+    elif precision == "f64":
+        assert float(np.max(np.abs(out[0] - want) / np.abs(want))) <= 1e-12
+    else:
+        assert float(np.max(np.abs(out[0] - want) / np.abs(want))) <= 5e-6  # 1e-6 per step
 
 
 @pytest.mark.parametrize("precision", ["f16s", "f32s", "f32"])
