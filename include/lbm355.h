@@ -186,10 +186,11 @@ int lbm_set_boundary(lbm_grid *g, int32_t cls, int32_t kind, double rho, const d
  *     power of two no larger than 256, every workgroup holds whole x-rows and
  *     moves the x-shifted PDFs through LDS, so that all global accesses are
  *     aligned; 0 forces the plain kernels.
- *   LBM_OPT_PAIR (0/1, default 1): on a direct SoA grid with FP16 storage
- *     whose nx is a power of two in [2, 512], every lane updates two
- *     x-neighbours and moves them as one 32-bit word per direction; 0 forces
- *     one node per lane.
+ *   LBM_OPT_PAIR (-1 = default, 0 or 1): on a direct SoA grid whose nx is a
+ *     power of two in [2, 512], 1 makes every lane update two x-neighbours
+ *     and move them as one word per direction (32, 64 or 128 bits); 0 keeps
+ *     one node per lane.  The default is two nodes per lane for FP16 storage
+ *     and one otherwise.
  *   LBM_OPT_BAND (blocks in [0, 4096], or -1 = default): on a direct grid
  *     whose z-plane splits into whole bands of this many workgroups for each
  *     of the 8 XCDs, order the update workgroups so that every XCD sweeps
