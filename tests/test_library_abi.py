@@ -69,7 +69,10 @@ def test_validation_errors_without_gpu():
     with pytest.raises(P.LbmError):
         P.Grid(0, 8, 8)
     with pytest.raises(P.LbmError):
-        P.Grid(2048, 2048, 1024)
+        P.Grid(2048, 2048, 1024)       # 2^32 cells
+    with pytest.raises(P.LbmError):
+        P.Grid(2048, 1024, 1024)       # 2^31 cells: one more than the largest box
+    assert P.Grid(2048, 1024, 1023, precision="f16s").n_nodes == 2048 * 1024 * 1023
     with pytest.raises(P.LbmError):
         P.Grid(8, 8, 2, wall_z=True)
     with pytest.raises(P.LbmError):
