@@ -146,3 +146,21 @@ def test_cooperative_run_matches_graph_run_bitwise(precision):
     for a, b in zip(out["graph"][1], out["cooperative"][1]):
         assert np.array_equal(a.view(np.int64), b.view(np.int64))
     assert out["graph"][2] == out["cooperative"][2]
+
+
+def test_empty_batch_runs_and_reports_nothing():
+    """A run with no active slot launches and returns; a slot added afterwards starts cleanly."""
+    import paper_1111_0922_amd as P
+    batch = P.Batch(4, 256, "f32")
+    batch.run(4)                                  # no slot at all
+    grid, _ = _grid(*GEOMS[0], "f32")
+    s = batch.add(grid)
+    batch.remove(s)
+    batch.run(4)                                  # its only slot removed again
+    assert grid.t == 0
+    s = batch.add(grid)
+    m = batch.run(6)
+    ref, _ = _grid(*GEOMS[0], "f32")
+    ref.step(6)
+    assert np.array_equal(from_device(grid.get_pdfs()).view(np.int64), from_device(ref.get_pdfs()).view(np.int64))
+    assert np.array_equal(m[s], from_device(ref.moments()))

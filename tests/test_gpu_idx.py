@@ -101,3 +101,18 @@ def test_no_fluid_grid_refuses_to_bind():
     grid.bind("aa")
     with pytest.raises(P.LbmError):
         grid.step(1)
+
+
+def test_all_solid_mask_has_no_nodes_and_refuses_steps():
+    """An empty fluid set: N_f = 0, the index builds, binding works, and every call
+    that would launch a node kernel is refused with a clear error."""
+    import paper_1111_0922_amd as P
+    grid = P.Grid(6, 5, 4, addressing="indirect")
+    assert grid.build_idx(torch.ones((4, 5, 6), dtype=torch.uint8).cuda()) == 0
+    grid.bind("aa")
+    with pytest.raises(P.LbmError):
+        grid.init_equilibrium()
+    with pytest.raises(P.LbmError):
+        grid.step(1)
+    with pytest.raises(P.LbmError):
+        grid.moments()
