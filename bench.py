@@ -237,6 +237,8 @@ def main():
                     help="only the 384^3 steady-state precision study (FP64 / FP32 / FP16-shifted)")
     ap.add_argument("--profile-aa", choices=["f64", "f32", "f32s", "f16s"], default=None,
                     help="only the AA 256^3 channel run in this storage (for profiling)")
+    ap.add_argument("--profile-porous", action="store_true",
+                    help="only AA FP64 on the 512^3 sphere pack, indirect addressing (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the copy kernel on 1 GiB, 3 times (counter calibration)")
     args = ap.parse_args()
@@ -267,6 +269,18 @@ def main():
         dt = time_steps(torch, grid, args.steps, args.warmup)
         print(json.dumps({"profile": f"AA SoA {args.profile_aa} 256^3 channel", "steps": args.steps,
                           "MFLUP/s": round(grid.n_nodes * args.steps / dt / 1e6, 1)}), flush=True)
+        return
+    if args.profile_porous:
+        import lbm_inputs
+        mask, _ = lbm_inputs.sphere_pack(512, 8, 0.40, seed=3)
+        grid = P.Grid(512, 512, 512, addressing="indirect", omega=1.6, g=(1e-6, 0, 0))
+        nf = grid.build_idx(torch.from_numpy(mask).cuda())
+        del mask
+        grid.bind("aa")
+        grid.init_equilibrium()
+        dt = time_steps(torch, grid, args.steps, args.warmup)
+        print(json.dumps({"profile": "AA SoA f64 indirect 512^3 sphere pack", "nodes": nf, "steps": args.steps,
+                          "MFLUP/s": round(nf * args.steps / dt / 1e6, 1)}), flush=True)
         return
     if args.precision_study:
         print(json.dumps({"precision_study": precision_study(log)}), flush=True)
