@@ -40,10 +40,16 @@ KERNEL_SOURCES = ["kernels.hpp", "collide.hpp", "storage.hpp", "d3q19.hpp"]
 
 
 def kernel_hash() -> str:
+    """Hash of the kernel sources' code: comments and blank space do not count,
+    so a counter summary stays current until the code itself changes."""
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1111_0922_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1111_0922_amd", "csrc", f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)   # block comments
+        text = re.sub(r"//[^\n]*", " ", text)                  # line comments
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -2,9 +2,12 @@
 // scheme, written once over (addressing, layout, precision, scheme kernel,
 // collider) and instantiated per precision in k_<prec>.hip.
 //
-// One lane updates one node.  A kernel reads the node's 19 PDFs through the
-// scheme's read map, collides them in registers and stores them through the
-// scheme's write map.  The maps (Secs. 2, 3, 6, 7):
+// One lane updates one node (two x-neighbours in the pair kernels).  A
+// kernel reads the node's 19 PDFs through the scheme's read map, collides
+// them in registers and stores them through the scheme's write map.  At a
+// non-fluid neighbour the maps bounce back; for the open-boundary classes of
+// indirect grids the bounced value passes the class's link rule (bc_arrive).
+// The maps (Secs. 2, 3, 6, 7):
 //
 //   read maps (slot = (direction array j, cell)):
 //     LOCAL   (i, x)
@@ -262,8 +265,8 @@ struct Node<A_DIRECT, NEED> {
 };
 
 // Indirect addressing (Sec. 1): node ids of fluid nodes; neighbours from
-// IDX (-1 = solid); the esoteric twist reads its storage addresses and the
-// solid-neighbour mask from the ET table.
+// IDX (-1 = wall, -1 - c = open-boundary class c); the esoteric twist reads
+// its storage addresses and the solid-neighbour mask from the ET table.
 template <int NEED>
 struct Node<A_INDIRECT, NEED> {
     int64_t a;
