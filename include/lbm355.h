@@ -183,9 +183,10 @@ int lbm_set_boundary(lbm_grid *g, int32_t cls, int32_t kind, double rho, const d
  *     45056 for FP64, 40960 (direct) or 53248 (indirect) for FP32 and 0 for
  *     FP16 storage on SoA grids, and 0 on AoS grids.
  *   LBM_OPT_ROW_STAGE (0/1, default 1): on a direct SoA grid whose nx is a
- *     power of two no larger than 256, every workgroup holds whole x-rows and
- *     moves the x-shifted PDFs through LDS, so that all global accesses are
- *     aligned; 0 forces the plain kernels.
+ *     power of two no larger than 256, every workgroup holds whole x-rows, and
+ *     where nx is a multiple of 256 one 256-node segment of a row; the
+ *     x-shifted PDFs move through LDS, so that all global accesses of a
+ *     wavefront are aligned; 0 forces the plain kernels.
  *   LBM_OPT_PAIR (-1 = default, 0 or 1): on a direct SoA grid whose nx is a
  *     power of two in [2, 512], 1 makes every lane update two x-neighbours
  *     and move them as one word per direction (32, 64 or 128 bits); 0 keeps

@@ -147,9 +147,13 @@ KArgs base_args(const lbm_grid *g)
         if (d.precision == LBM_F32 || d.precision == LBM_F32S) lds = d.addressing == LBM_DIRECT ? 40960 : 53248;
     }
     a.lds_bytes = (uint32_t)(g->wg_lds >= 0 ? g->wg_lds : lds); // pair kernels: see below
-    // whole x-rows per workgroup: nx a power of two dividing the workgroup size
-    a.row_staged = (d.addressing == LBM_DIRECT && d.layout == LBM_SOA && g->row_stage && d.nx <= BLOCK &&
-                    (d.nx & (d.nx - 1)) == 0) ? 1 : 0;
+    // x-rows staged per workgroup: whole rows (nx a power of two dividing the
+    // workgroup size) or one segment of a row (the workgroup size divides nx)
+    a.row_staged = 0;
+    if (d.addressing == LBM_DIRECT && d.layout == LBM_SOA && g->row_stage) {
+        if (d.nx <= BLOCK && (d.nx & (d.nx - 1)) == 0) a.row_staged = 1;
+        if (d.nx > BLOCK && d.nx % BLOCK == 0) a.row_staged = 2;
+    }
     // two nodes per lane: nx a power of two dividing 2 * BLOCK; by default for
     // 16-bit storage (measured below for the others)
     const bool pair_on = g->pair > 0 || (g->pair < 0 && d.precision == LBM_F16S);
@@ -509,7 +513,7 @@ int lbm_step(lbm_grid *g, int32_t scheme, int32_t collider, int64_t n_steps, voi
     const uint32_t nb = update_blocks(g, a);
     auto launch = [&](int kind) {
         set_block_order(g, a, kind);
-        (a.pair ? tb.pair[C][kind] : tb.update[A][L][C][kind])(a, nb, s);
+        (a.pair ? tb.pair[C][kind] : a.row_staged == 2 ? tb.wide[C][kind] : tb.update[A][L][C][kind])(a, nb, s);
     };
     if (collider == LBM_TRT) {
         // Lambda = (1/w+ - 1/2)(1/w- - 1/2)

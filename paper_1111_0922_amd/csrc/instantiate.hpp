@@ -15,6 +15,11 @@ void launch_pair(const KArgs &a, uint32_t blocks, hipStream_t s)
 {
     hipLaunchKernelGGL((k_update_pair<P, K, C>), dim3(blocks), dim3(BLOCK), a.lds_bytes, s, a);
 }
+template <int P, int K, int C>
+void launch_wide(const KArgs &a, uint32_t blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_update_wide<P, K, C>), dim3(blocks), dim3(BLOCK), a.lds_bytes, s, a);
+}
 template <int A, int L, int P, int R>
 void launch_get(const KArgs &a, uint32_t blocks, hipStream_t s)
 {
@@ -62,6 +67,19 @@ void fill_pairs(PrecTable &t)
     t.pair[C][K_ET1] = &launch_pair<P, K_ET1, C>;
 }
 
+template <int P, int C>
+void fill_wide(PrecTable &t)
+{
+    t.wide[C][K_TS_COLLIDE] = &launch_wide<P, K_TS_COLLIDE, C>;
+    t.wide[C][K_TS_STREAM] = &launch_wide<P, K_TS_STREAM, 0>; // no collision
+    t.wide[C][K_OS_PUSH] = &launch_wide<P, K_OS_PUSH, C>;
+    t.wide[C][K_OS_PULL] = &launch_wide<P, K_OS_PULL, C>;
+    t.wide[C][K_AA_EVEN] = &launch_wide<P, K_AA_EVEN, C>;
+    t.wide[C][K_AA_ODD] = &launch_wide<P, K_AA_ODD, C>;
+    t.wide[C][K_ET0] = &launch_wide<P, K_ET0, C>;
+    t.wide[C][K_ET1] = &launch_wide<P, K_ET1, C>;
+}
+
 template <int A, int L, int P, int R>
 void fill_map(PrecTable &t)
 {
@@ -90,6 +108,8 @@ PrecTable make_table()
     fill_al<A_DIRECT, L_SOA, P>(t);
     fill_pairs<P, 0>(t);
     fill_pairs<P, 1>(t);
+    fill_wide<P, 0>(t);
+    fill_wide<P, 1>(t);
     fill_al<A_DIRECT, L_AOS, P>(t);
     fill_al<A_INDIRECT, L_SOA, P>(t);
     fill_al<A_INDIRECT, L_AOS, P>(t);

@@ -121,7 +121,7 @@ struct KArgs {
     int32_t remap;         // block order: 0 natural, 1 XCD chunks, 2 XCD bands (logical_block)
     uint32_t band_yb, band_ty, band_z;
     uint32_t lds_bytes;    // dynamic LDS reserved per update workgroup (caps residency)
-    int32_t row_staged;    // direct SoA, nx divides BLOCK: x-shifted accesses go through LDS
+    int32_t row_staged;    // direct SoA, x-shifted accesses through LDS: 1 nx divides BLOCK, 2 BLOCK divides nx
     int32_t pair;          // direct SoA, 16-bit storage, nx divides 2 * BLOCK: two nodes per lane
     double omega, gx, gy, gz, sigma;
     double omega_minus;    // TRT odd-moment rate (== omega for BGK)
@@ -477,16 +477,34 @@ __host__ __device__ constexpr int xslot(int i)
 }
 constexpr int NXSLOT = 10;
 
-// Direct SoA update with whole x-rows per workgroup (nx divides BLOCK; rows
-// of a workgroup are consecutive nodes).  Every global access is made at the
-// node's own x, so a wavefront touches whole aligned cache lines; an x-shift
-// of +-1 becomes a cyclic shift inside the row, done through LDS:
+// Direct SoA update with x-rows staged per workgroup.  Every global access
+// of the node's own row segment is made at the node's own x, so a wavefront
+// touches whole aligned cache lines; an x-shift of +-1 becomes a shift inside
+// the segment, done through LDS:
 //   read  slot x + sx:  thread x loads cell (x, y+sy, z+sz), the consumer
 //                       x - sx picks it up from LDS;
 //   write slot x + sx:  thread x deposits its value at LDS position x + sx,
 //                       the owner of that position stores it at its own x.
+// Two shapes (row_staged = 1 or 2):
+//   1: nx divides BLOCK.  A workgroup holds whole rows (consecutive nodes) and
+//      the shift is cyclic inside each row, which is the periodic wrap in x.
+//   2: BLOCK divides nx.  A workgroup holds one segment of BLOCK nodes of a
+//      row.  An end lane whose shifted slot lies beyond the segment loads that
+//      value from global memory itself (read side), or stores its outgoing
+//      value there itself (write side); positions that no lane of this
+//      workgroup deposits into are stored by the neighbouring segment's end
+//      lane.
 // Threads past n_nodes form whole rows; they skip memory but join barriers.
-template <int PREC, int KIND, int COLL>
+// WIDE selects shape 2 at compile time, so that the shape-1 code carries none
+// of the segment-end work; both shapes share one LDS array.
+template <typename st>
+__device__ __forceinline__ st (&staging_rows())[NXSLOT][BLOCK]
+{
+    __shared__ st xs[NXSLOT][BLOCK];
+    return xs;
+}
+
+template <int PREC, int KIND, int COLL, bool WIDE>
 __device__ __forceinline__ void update_direct_staged(const KArgs &a)
 {
     using S = Store<PREC>;
@@ -494,25 +512,33 @@ __device__ __forceinline__ void update_direct_staged(const KArgs &a)
     using ct = typename S::ct;
     constexpr int R = rmap_of(KIND);
     constexpr int W = wmap_of(KIND);
-    __shared__ st xs[NXSLOT][BLOCK];
+    st(&xs)[NXSLOT][BLOCK] = staging_rows<st>();
     const uint32_t t = threadIdx.x;
     const uint32_t n = logical_block(a) * BLOCK + t;
     const bool valid = n < a.n_nodes;
-    const uint32_t nx = (uint32_t)a.nx; // power of two dividing BLOCK
-    const uint32_t xl = t & (nx - 1), row = t - xl;
+    const uint32_t seg = WIDE ? (uint32_t)BLOCK : (uint32_t)a.nx; // a power of two
+    const uint32_t xl = t & (seg - 1), row = t - xl;
+    // LDS position of segment position xl + sx (|sx| <= 1), cyclic in a row
+    auto pos = [&](int sx) -> uint32_t { return row + (((uint32_t)((int)xl + sx)) & (seg - 1)); };
+    // whether segment position xl + sx lies outside this workgroup's segment
+    auto beyond = [&](int sx) -> bool { return WIDE && ((int)xl + sx < 0 || (int)xl + sx >= BLOCK); };
     Node<A_DIRECT, 0> nd;
     nd.init(a, valid ? n : 0);
     const st *src = static_cast<const st *>(a.src);
     st *dst = static_cast<st *>(a.dst);
     // All 19 loads first (each at the node's own x), so they are in flight
     // together.  They are unconditional: a thread past n_nodes addresses node
-    // 0 (in bounds) and never stores what it loaded.
+    // 0 (in bounds) and never stores what it loaded.  In a wide segment the
+    // end lanes also load the values beyond it that they consume.
     typename S::rt raw[Q];
+    typename S::rt halo[WIDE ? NXSLOT : 1];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         int j, sx, sy, sz;
         read_off<R>(nd, i, j, sx, sy, sz);
         raw[i] = pdf_load_raw<true, S>(src + elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch));
+        if (xslot(i) >= 0 && sx != 0 && beyond(sx))
+            halo[WIDE && xslot(i) > 0 ? xslot(i) : 0] = pdf_load_raw<true, S>(src + elem<L_SOA>(j, nd.shift(sx, sy, sz), a.pitch));
     }
     ct v[Q];
 #pragma unroll
@@ -531,7 +557,8 @@ __device__ __forceinline__ void update_direct_staged(const KArgs &a)
         if (xslot(i) >= 0) {
             int j, sx, sy, sz;
             read_off<R>(nd, i, j, sx, sy, sz);
-            if (sx != 0) v[i] = S::load(xs[xslot(i) < 0 ? 0 : xslot(i)][row + ((xl + (uint32_t)sx) & (nx - 1))]);
+            const int k = xslot(i) < 0 ? 0 : xslot(i);
+            if (sx != 0) v[i] = beyond(sx) ? S::load_raw(halo[WIDE ? k : 0]) : S::load(xs[k][pos(sx)]);
         }
     }
     __syncthreads();
@@ -543,11 +570,13 @@ __device__ __forceinline__ void update_direct_staged(const KArgs &a)
     for (int i = 0; i < Q; ++i) {
         int j, sx, sy, sz;
         write_off<W>(nd, i, j, sx, sy, sz);
-        if (xslot(i) >= 0) {
-            if (sx != 0) {
-                xs[xslot(i) < 0 ? 0 : xslot(i)][row + ((xl + (uint32_t)sx) & (nx - 1))] = S::save(v[i]);
-                continue;
+        if (xslot(i) >= 0 && sx != 0) {
+            if (beyond(sx)) {
+                if (valid) pdf_store<true>(dst + elem<L_SOA>(j, nd.shift(sx, sy, sz), a.pitch), S::save(v[i]));
+            } else {
+                xs[xslot(i) < 0 ? 0 : xslot(i)][pos(sx)] = S::save(v[i]);
             }
+            continue;
         }
         if (valid) pdf_store<true>(dst + elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch), S::save(v[i]));
     }
@@ -557,7 +586,9 @@ __device__ __forceinline__ void update_direct_staged(const KArgs &a)
         if (xslot(i) >= 0) {
             int j, sx, sy, sz;
             write_off<W>(nd, i, j, sx, sy, sz);
-            if (sx != 0 && valid) pdf_store<true>(dst + elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch), xs[xslot(i) < 0 ? 0 : xslot(i)][t]);
+            // the depositor of this position is segment position xl - sx
+            if (sx != 0 && valid && !beyond(-sx))
+                pdf_store<true>(dst + elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch), xs[xslot(i) < 0 ? 0 : xslot(i)][t]);
         }
     }
 }
@@ -861,16 +892,35 @@ __global__ void __launch_bounds__(BLOCK) k_update_pair(KArgs a)
     update_direct_pair<PREC, KIND, COLL>(a);
 }
 
+// kernels whose maps never shift along x need no staging
+__host__ __device__ constexpr bool shifts_x(int kind)
+{
+    return !(rmap_of(kind) == R_LOCAL && (wmap_of(kind) == W_LOCAL || wmap_of(kind) == W_AAEVEN));
+}
+
+// Direct SoA grids whose nx is a multiple of BLOCK: one row segment per
+// workgroup (a kernel of its own, so that the segment-end work does not count
+// against the registers of the other kernels).
+template <int PREC, int KIND, int COLL>
+__global__ void __launch_bounds__(BLOCK) k_update_wide(KArgs a)
+{
+    if constexpr (shifts_x(KIND)) {
+        update_direct_staged<PREC, KIND, COLL, true>(a);
+    } else {
+        const uint32_t n = logical_block(a) * BLOCK + threadIdx.x;
+        if (n >= a.n_nodes) return;
+        update_node<A_DIRECT, L_SOA, PREC, KIND, COLL>(a, n);
+    }
+}
+
 template <int ADDR, int LAY, int PREC, int KIND, int COLL>
 __global__ void __launch_bounds__(BLOCK) k_update(KArgs a)
 {
     constexpr int R = rmap_of(KIND);
     constexpr int W = wmap_of(KIND);
-    // kernels whose maps never shift along x need no staging
-    constexpr bool shifts = !(R == R_LOCAL && (W == W_LOCAL || W == W_AAEVEN));
-    if constexpr (ADDR == A_DIRECT && LAY == L_SOA && shifts) {
-        if (a.row_staged) {
-            update_direct_staged<PREC, KIND, COLL>(a);
+    if constexpr (ADDR == A_DIRECT && LAY == L_SOA && shifts_x(KIND)) {
+        if (a.row_staged == 1) {
+            update_direct_staged<PREC, KIND, COLL, false>(a);
             return;
         }
     }
@@ -1038,6 +1088,7 @@ using Launch = void (*)(const KArgs &, uint32_t, hipStream_t);
 struct PrecTable {
     Launch update[2][2][2][K_NUM]; // [addr][layout][collider][kind]
     Launch pair[2][K_NUM];         // direct SoA, two nodes per lane: [collider][kind]
+    Launch wide[2][K_NUM];         // direct SoA, one row segment per workgroup: [collider][kind]
     Launch get[2][2][R_NUM];
     Launch set[2][2][R_NUM];
     Launch init[2][2][R_NUM];

@@ -164,9 +164,10 @@ def test_scheme_mismatch_is_an_error():
 
 
 @pytest.mark.parametrize("scheme", SCHEMES)
-@pytest.mark.parametrize("shape", [(32, 32, 32), (6, 5, 64), (5, 3, 256), (4, 4, 2)])
+@pytest.mark.parametrize("shape", [(32, 32, 32), (6, 5, 64), (5, 3, 256), (4, 4, 2), (5, 3, 512), (4, 2, 768)])
 def test_row_staged_kernels_bit_identical_to_plain(scheme, shape):
-    """Direct SoA grids with nx a power of two run row-staged kernels; the plain kernels must agree bit for bit."""
+    """Direct SoA grids with nx a power of two up to 256, or a multiple of 256 (one row segment per
+    workgroup), run row-staged kernels; the plain kernels must agree bit for bit.  Shapes are (nz, ny, nx)."""
     import paper_1111_0922_amd as P
     solid = lbm_inputs.channel_mask(shape[2], shape[1], shape[0])
     ru = lbm_inputs.rho_u_field(solid.shape, lbm_inputs.velocity_noise(solid.shape, 1e-2, seed=12))

@@ -159,6 +159,40 @@ def test_pair_kernels_bit_identical_to_one_node(precision, scheme, shape, walls)
         assert float(np.max(np.abs(out[0] - want) / np.abs(want))) <= 5e-6  # 1e-6 per step
 
 
+@pytest.mark.parametrize("precision", ["f16s", "f32s", "f32", "f64"])
+@pytest.mark.parametrize("scheme", ["ts", "os_push", "os_pull", "aa", "et"])
+@pytest.mark.parametrize("shape,walls", [((512, 2, 4), True), ((768, 2, 3), False), ((1024, 1, 4), True)])
+def test_wide_row_segments_bit_identical_to_plain(precision, scheme, shape, walls):
+    """nx a multiple of 256: each workgroup stages one row segment and its end lanes
+    reach beyond it in global memory; the plain one-node kernels give the same bits."""
+    import lbm_inputs
+    import paper_1111_0922_amd as P
+    nx, ny, nz = shape
+    solid = lbm_inputs.channel_mask(nx, ny, nz) if walls else np.zeros((nz, ny, nx), np.uint8)
+    ru = lbm_inputs.rho_u_field(solid.shape, lbm_inputs.velocity_noise(solid.shape, 1e-3, seed=17))
+    sigma = 256.0 if precision in ("f16s", "f32s") else 1.0
+    q0 = oracle.init_equilibrium(ru, solid)
+    if precision != "f64":
+        q0 = oracle.quantize(q0, solid, precision, sigma)
+    out = []
+    for staged in (1, 0):
+        grid = make_grid(solid, scheme, precision=precision, omega=1.7, g=(1e-5, 2e-5, 3e-6), f16_scale=sigma)
+        grid.set_option(P._lib.OPT_PAIR, 0)
+        grid.set_option(P._lib.OPT_ROW_STAGE, staged)
+        grid.set_pdfs(to_device(oracle.fluid_view(q0, solid)))
+        grid.step(5)
+        out.append(from_device(grid.get_pdfs()))
+    assert np.array_equal(out[0].view(np.int64), out[1].view(np.int64))
+    want = oracle.fluid_view(oracle.run_ts(q0, solid, 5, 1.7, (1e-5, 2e-5, 3e-6),
+                                           precision=None if precision == "f64" else precision, sigma=sigma), solid)
+    if precision == "f16s":
+        assert float(np.max(np.abs(out[0] - want))) <= 8 * 2.0 ** -23
+    elif precision == "f64":
+        assert float(np.max(np.abs(out[0] - want) / np.abs(want))) <= 1e-12
+    else:
+        assert float(np.max(np.abs(out[0] - want) / np.abs(want))) <= 5e-6  # 1e-6 per step
+
+
 @pytest.mark.parametrize("precision", ["f16s", "f32s", "f32"])
 @pytest.mark.parametrize("scheme", ["aa", "et", "os_pull"])
 @pytest.mark.parametrize("shape,walls", [((6, 5, 7), True), ((11, 3, 4), False), ((3, 1, 1), False)])
