@@ -57,7 +57,8 @@ enum {
     LBM_E_STATE = -2,       /* wrong call order, unbound buffer, scheme mismatch */
     LBM_E_HIP = -3,         /* HIP runtime error (text in lbm_last_error)      */
     LBM_E_UNSUPPORTED = -4, /* combination not provided by this build          */
-    LBM_E_DIVERGED = -5     /* a reduction saw a NaN                           */
+    LBM_E_DIVERGED = -5     /* reserved: the reductions are asynchronous and   */
+                            /* report divergence as a NaN mass M instead       */
 };
 
 /* ---------------------------------------------------------------- enums */
@@ -176,12 +177,15 @@ int lbm_set_boundary(lbm_grid *g, int32_t cls, int32_t kind, double rho, const d
  *     padding added to the SoA pitch so that the 19 direction arrays do not
  *     start at addresses that agree in their low bits.  Changes the buffer
  *     sizes: the grid must be bound again afterwards.
- *   LBM_OPT_WG_LDS (bytes in [0, 65536], or -1 = default): dynamic LDS
- *     reserved by every update workgroup on top of what the kernel uses.  It
- *     only limits how many workgroups a CU (160 KB of LDS) keeps resident,
- *     which bounds the number of concurrent memory streams.  The default is
- *     45056 for FP64, 40960 (direct) or 53248 (indirect) for FP32 and 0 for
- *     FP16 storage on SoA grids, and 0 on AoS grids.
+ *   LBM_OPT_WG_LDS (bytes in [0, 163840], or -1 = default): dynamic LDS
+ *     reserved by every update workgroup on top of what the kernel uses (a
+ *     total the device refuses makes lbm_step fail with LBM_E_HIP).  It only
+ *     limits how many workgroups a CU (160 KB of LDS) keeps resident, which
+ *     bounds the number of concurrent memory streams and the lines in flight
+ *     per L2.  The default is 45056 for FP64, 40960 (direct) or 53248
+ *     (indirect) for FP32 and 0 for FP16 storage on SoA grids; on AoS grids
+ *     it is 0, except FP64 AA: 20480 for the even kernel (two workgroups per
+ *     CU) and 98304 for the odd kernel (one per CU).
  *   LBM_OPT_ROW_STAGE (0/1, default 1): on a direct SoA grid whose nx is a
  *     power of two no larger than 256, every workgroup holds whole x-rows, and
  *     where nx is a multiple of 256 one 256-node segment of a row; the

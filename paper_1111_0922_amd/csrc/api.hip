@@ -114,6 +114,21 @@ void set_block_order(const lbm_grid *g, KArgs &a, int kind)
     }
 }
 
+// Per-kernel residency of AoS FP64 AA (256^3 channel, LDS reserved only to
+// cap the resident workgroups per CU; an explicit LBM_OPT_WG_LDS wins).  The
+// odd kernel scatters 8-byte values into 152-byte records of nine rows; with
+// every workgroup it can hold resident, the rows in flight outgrow the L2
+// and partially written lines leave it several times (3.8x the algorithmic
+// write bytes, counters).  One workgroup per CU: 3.13 -> 2.57 ms.  The even
+// kernel (staged records, 38 KB of LDS) is best at two per CU: 0.88 -> 0.81 ms.
+// Lower residency slows the other AoS kernels, which keep the base default.
+static void set_residency(const lbm_grid *g, KArgs &a, int kind)
+{
+    if (g->wg_lds >= 0 || g->d.layout != LBM_AOS || g->d.precision != LBM_F64) return;
+    if (kind == K_AA_ODD) a.lds_bytes = 98304;
+    if (kind == K_AA_EVEN) a.lds_bytes = 20480;
+}
+
 KArgs base_args(const lbm_grid *g)
 {
     KArgs a;
@@ -315,7 +330,7 @@ int lbm_set_option(lbm_grid *g, int32_t option, int64_t value)
         return LBM_OK;
     }
     if (option == LBM_OPT_WG_LDS) {
-        if (value < -1 || value > 65536) return fail(LBM_E_ARG, "workgroup LDS must be -1 or lie in [0, 65536] bytes");
+        if (value < -1 || value > 163840) return fail(LBM_E_ARG, "workgroup LDS must be -1 or lie in [0, 163840] bytes");
         g->wg_lds = value;
         return LBM_OK;
     }
@@ -513,6 +528,7 @@ int lbm_step(lbm_grid *g, int32_t scheme, int32_t collider, int64_t n_steps, voi
     const uint32_t nb = update_blocks(g, a);
     auto launch = [&](int kind) {
         set_block_order(g, a, kind);
+        set_residency(g, a, kind);
         (a.pair ? tb.pair[C][kind] : a.row_staged == 2 ? tb.wide[C][kind] : tb.update[A][L][C][kind])(a, nb, s);
     };
     if (collider == LBM_TRT) {
