@@ -182,10 +182,12 @@ int lbm_set_boundary(lbm_grid *g, int32_t cls, int32_t kind, double rho, const d
  *     total the device refuses makes lbm_step fail with LBM_E_HIP).  It only
  *     limits how many workgroups a CU (160 KB of LDS) keeps resident, which
  *     bounds the number of concurrent memory streams and the lines in flight
- *     per L2.  The default is 45056 for FP64, 40960 (direct) or 53248
- *     (indirect) for FP32 and 0 for FP16 storage on SoA grids; on AoS grids
- *     it is 0, except FP64 AA: 20480 for the even kernel (two workgroups per
- *     CU) and 98304 for the odd kernel (one per CU).
+ *     per L2.  The default on SoA grids is two workgroups per CU for FP64
+ *     (45056 for the kernels that stage x-rows through 20 KB of their own
+ *     LDS, 65536 for the others), 40960 (direct) or 53248 (indirect) for
+ *     FP32 and 0 for FP16 storage; on AoS grids it is 0, except FP64 AA:
+ *     20480 for the even kernel (two workgroups per CU) and 98304 for the
+ *     odd kernel (one per CU).
  *   LBM_OPT_ROW_STAGE (0/1, default 1): on a direct SoA grid whose nx is a
  *     power of two no larger than 256, every workgroup holds whole x-rows, and
  *     where nx is a multiple of 256 one 256-node segment of a row; the

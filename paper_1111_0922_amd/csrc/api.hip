@@ -114,19 +114,31 @@ void set_block_order(const lbm_grid *g, KArgs &a, int kind)
     }
 }
 
-// Per-kernel residency of AoS FP64 AA (256^3 channel, LDS reserved only to
-// cap the resident workgroups per CU; an explicit LBM_OPT_WG_LDS wins).  The
-// odd kernel scatters 8-byte values into 152-byte records of nine rows; with
-// every workgroup it can hold resident, the rows in flight outgrow the L2
-// and partially written lines leave it several times (3.8x the algorithmic
-// write bytes, counters).  One workgroup per CU: 3.13 -> 2.57 ms.  The even
-// kernel (staged records, 38 KB of LDS) is best at two per CU: 0.88 -> 0.81 ms.
-// Lower residency slows the other AoS kernels, which keep the base default.
+// Per-kernel residency of FP64 kernels (LDS reserved only to cap the
+// resident workgroups per CU; an explicit LBM_OPT_WG_LDS wins).
+//  - SoA: two workgroups per CU for every kernel.  The row-staged kernels
+//    (20 KB of their own) reach it with the base 44 KB; the others need a
+//    64 KB reservation, which took AA even on the 256^3 channel from 0.851
+//    to 0.827 ms and on the 512^3 pack from 2.97 to 2.81 ms (odd 4.59 to
+//    4.48, two-step 6.9 to 6.5 ms per step).  Fewer (one per CU) slows the
+//    staged kernels by 15-25%.
+//  - AoS AA: the odd kernel scatters 8-byte values into 152-byte records of
+//    nine rows; with every workgroup it can hold resident, the rows in
+//    flight outgrow the L2 and partially written lines leave it several
+//    times (3.8x the algorithmic write bytes, counters).  One workgroup per
+//    CU: 3.13 -> 2.57 ms.  The even kernel (staged records, 38 KB of LDS)
+//    is best at two per CU: 0.88 -> 0.81 ms.  Lower residency slows the
+//    other AoS kernels, which keep full residency.
 static void set_residency(const lbm_grid *g, KArgs &a, int kind)
 {
-    if (g->wg_lds >= 0 || g->d.layout != LBM_AOS || g->d.precision != LBM_F64) return;
-    if (kind == K_AA_ODD) a.lds_bytes = 98304;
-    if (kind == K_AA_EVEN) a.lds_bytes = 20480;
+    if (g->wg_lds >= 0 || a.pair || g->d.precision != LBM_F64) return;
+    if (g->d.layout == LBM_SOA) {
+        const bool staged = g->d.addressing == LBM_DIRECT && a.row_staged && shifts_x(kind);
+        a.lds_bytes = staged ? 45056 : 65536;
+    } else {
+        if (kind == K_AA_ODD) a.lds_bytes = 98304;
+        if (kind == K_AA_EVEN) a.lds_bytes = 20480;
+    }
 }
 
 KArgs base_args(const lbm_grid *g)
@@ -150,12 +162,12 @@ KArgs base_args(const lbm_grid *g)
     a.dvx = make_fastdiv((uint32_t)d.nx);
     a.dvy = make_fastdiv((uint32_t)d.ny);
     a.remap = g->remap;
-    // Measured on MI355X: FP64 direct SoA workgroups (256^3 channel) run best
-    // with two resident per CU for the row-staged kernels (20 KB static LDS +
-    // 44 KB) and three for the others (44 KB); FP32 likes 40 KB; FP16 wants no
-    // cap.  Indirect SoA (512^3 pack): 44 KB for FP64 (+1%) and 52 KB for
-    // 4-byte storage (AA even -7%, odd -3% in time).  AoS kernels keep full
-    // residency (their staged records already take 19-38 KB of LDS).
+    // Base reservation, measured on MI355X: FP32 likes 40 KB on direct SoA
+    // grids (256^3 channel) and 52 KB on indirect ones (512^3 pack: AA even
+    // -7%, odd -3% in time); FP16 wants no cap.  FP64 kernels get theirs per
+    // kernel (set_residency; 44 KB is the staged SoA kernels' share).  AoS
+    // kernels otherwise keep full residency (their staged records already
+    // take 19-38 KB of LDS).
     int64_t lds = 0;
     if (d.layout == LBM_SOA) {
         if (d.precision == LBM_F64) lds = 45056;

@@ -165,8 +165,14 @@ __device__ __forceinline__ const CollideParams<T> &cparams(const KArgs &a)
 template <typename T>
 __device__ __forceinline__ T bc_arrive(const KArgs &a, int c, int d, T v)
 {
-    const T k = sizeof(T) == 8 ? (T)a.bc_can[c - 1][d] : (T)a.bc_f[c - 1][d];
-    return ((a.bc_neg >> (c - 1)) & 1u) ? k - v : v + k;
+    // d is a compile-time direction in the unrolled loops, so the four
+    // classes' constants are uniform (scalar loads); the lane's class picks
+    // one (a vector load indexed by the class would wait on memory per link)
+    T k[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) k[q] = sizeof(T) == 8 ? (T)a.bc_can[q][d] : (T)a.bc_f[q][d];
+    const T kc = c == 1 ? k[0] : c == 2 ? k[1] : c == 3 ? k[2] : k[3];
+    return ((a.bc_neg >> (c - 1)) & 1u) ? kc - v : v + kc;
 }
 // ... the same on canonical FP64 values, and its inverse (the bounced value
 // that makes f arrive).
@@ -406,6 +412,25 @@ __device__ __forceinline__ void write_slot(const N &nd, int i, int &j, int64_t &
 {
     int bc;
     write_slot<W>(nd, i, j, c, bc);
+}
+
+// Open-boundary rule on every gathered value that crossed a boundary link
+// (indirect grids, gathering read maps).  Applied after all 19 loads have
+// been issued: a branch between two loads would make a wavefront with such
+// a link wait for each load in turn.
+template <int ADDR, int R, class N, typename T>
+__device__ __forceinline__ void bc_arrive_all(const KArgs &a, const N &nd, T (&v)[Q])
+{
+    if constexpr (ADDR == A_INDIRECT && (R == R_PULL || R == R_AAODD)) {
+        if (!a.bc_on) return;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            int j, bc;
+            int64_t c;
+            read_slot<R>(nd, i, j, c, bc);
+            if (bc > 0) v[i] = bc_arrive<T>(a, bc, i, v[i]);
+        }
+    }
 }
 
 // ------------------------------------------------------------------ maps as offsets (direct grids)
@@ -757,10 +782,8 @@ __device__ __forceinline__ void update_node(const KArgs &a, uint32_t n)
         int64_t c;
         read_slot<R>(nd, i, j, c, bc);
         v[i] = S::load(pdf_load<NT>(src + elem<LAY>(j, c, a.pitch)));
-        if constexpr (ADDR == A_INDIRECT && (R == R_PULL || R == R_AAODD)) {
-            if (bc > 0 && a.bc_on) v[i] = bc_arrive<ct>(a, bc, i, v[i]);
-        }
     }
+    bc_arrive_all<ADDR, R>(a, nd, v);
     if constexpr (COLL == 1 && KIND != K_TS_STREAM) {
         const CollideParams<ct> &p = cparams<ct>(a);
         collide_node<ct, S::shifted>(v, p);
@@ -837,10 +860,8 @@ __device__ __forceinline__ void update_aos_staged(const KArgs &a)
                 int64_t c;
                 read_slot<R>(nd, i, j, c, bc);
                 v[i] = S::load(src[elem<L_AOS>(j, c, a.pitch)]);
-                if constexpr (ADDR == A_INDIRECT && (R == R_PULL || R == R_AAODD)) {
-                    if (bc > 0 && a.bc_on) v[i] = bc_arrive<ct>(a, bc, i, v[i]);
-                }
             }
+            bc_arrive_all<ADDR, R>(a, nd, v);
         }
     }
     if (valid) {
