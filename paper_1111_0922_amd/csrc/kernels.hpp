@@ -162,17 +162,32 @@ __device__ __forceinline__ const CollideParams<T> &cparams(const KArgs &a)
 
 // The population arriving in direction d from a boundary of class c >= 1,
 // given the bounced value v (compute type, stored form) ...
+// The constants C_c[d] in the compute type, copied to LDS once per workgroup
+// (bc_table_fill).  A link reads its constant there by the lane's class: a
+// vector load from the kernel arguments would wait on memory per link, and
+// uniform scalar loads of the whole table (76 values) overflow the scalar
+// registers into spills on every path.
+template <typename T>
+__device__ __forceinline__ T (&bc_table())[4][Q]
+{
+    __shared__ T tab[4][Q];
+    return tab;
+}
+// Every thread of the workgroup calls this (a.bc_on is uniform).
+template <typename T>
+__device__ __forceinline__ void bc_table_fill(const KArgs &a)
+{
+    if (!a.bc_on) return;
+    const uint32_t t = threadIdx.x;
+    if (t < 4 * Q) bc_table<T>()[t / Q][t % Q] = sizeof(T) == 8 ? (T)a.bc_can[t / Q][t % Q] : (T)a.bc_f[t / Q][t % Q];
+    __syncthreads();
+}
+
 template <typename T>
 __device__ __forceinline__ T bc_arrive(const KArgs &a, int c, int d, T v)
 {
-    // d is a compile-time direction in the unrolled loops, so the four
-    // classes' constants are uniform (scalar loads); the lane's class picks
-    // one (a vector load indexed by the class would wait on memory per link)
-    T k[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) k[q] = sizeof(T) == 8 ? (T)a.bc_can[q][d] : (T)a.bc_f[q][d];
-    const T kc = c == 1 ? k[0] : c == 2 ? k[1] : c == 3 ? k[2] : k[3];
-    return ((a.bc_neg >> (c - 1)) & 1u) ? kc - v : v + kc;
+    const T k = bc_table<T>()[c - 1][d];
+    return ((a.bc_neg >> (c - 1)) & 1u) ? k - v : v + k;
 }
 // ... the same on canonical FP64 values, and its inverse (the bounced value
 // that makes f arrive).
@@ -268,6 +283,8 @@ struct Node<A_DIRECT, NEED> {
     __device__ __forceinline__ bool et_solid(int i) const { return solid(i); }
     __device__ __forceinline__ int bc_class(int) const { return 0; }
     __device__ __forceinline__ void refresh() {}
+    __device__ __forceinline__ void pin_nb(int) {}
+    __device__ __forceinline__ void pin_et(int) {}
 };
 
 // Indirect addressing (Sec. 1): node ids of fluid nodes; neighbours from
@@ -314,6 +331,17 @@ struct Node<A_INDIRECT, NEED> {
     // compiler from holding 19 wide gather addresses live across the
     // collision to reuse them for the scatter: the 32-bit ids are enough to
     // rebuild them, which halves the registers of the in-place kernels.
+    // Opaque redefinition of one neighbour id (or ET entry) right before the
+    // gather that uses it: the load's address cannot be computed earlier, so
+    // the wait for that id lands here and not before the first gather load.
+    __device__ __forceinline__ void pin_nb(int q)
+    {
+        if constexpr ((NEED & NEED_NB) != 0) asm volatile("" : "+v"(m[q]));
+    }
+    __device__ __forceinline__ void pin_et(int q)
+    {
+        if constexpr ((NEED & NEED_ET) != 0) asm volatile("" : "+v"(e[q]));
+    }
     __device__ __forceinline__ void refresh()
     {
         if constexpr ((NEED & NEED_NB) != 0) {
@@ -412,6 +440,28 @@ __device__ __forceinline__ void write_slot(const N &nd, int i, int &j, int64_t &
 {
     int bc;
     write_slot<W>(nd, i, j, c, bc);
+}
+
+// Indirect gathers: each load's address comes from one neighbour id, loaded
+// in Node::init.  Pinning that id right before the load (gather_pin) and a
+// scheduling barrier after it (gather_order) issue each load as soon as its
+// id has arrived; otherwise the address computations are grouped first and
+// every id is waited for before the first gather load (512^3 pack, AA odd:
+// 4.48 against 5.47 ms).
+template <int ADDR, int R, class N>
+__device__ __forceinline__ void gather_pin(N &nd, int i)
+{
+    if constexpr (ADDR == A_INDIRECT && (R == R_PULL || R == R_AAODD)) {
+        if (i != 0) nd.pin_nb(opp(i) - 1);
+    } else if constexpr (ADDR == A_INDIRECT && (R == R_ET0 || R == R_ET1)) {
+        const int c = et_cell(ox(i), oy(i), oz(i));
+        if (c != 0) nd.pin_et(c - 1);
+    }
+}
+template <int ADDR, int R>
+__device__ __forceinline__ void gather_order()
+{
+    if constexpr (ADDR == A_INDIRECT && R != R_LOCAL) __builtin_amdgcn_sched_barrier(0);
 }
 
 // Open-boundary rule on every gathered value that crossed a boundary link
@@ -780,8 +830,10 @@ __device__ __forceinline__ void update_node(const KArgs &a, uint32_t n)
     for (int i = 0; i < Q; ++i) {
         int j, bc;
         int64_t c;
+        gather_pin<ADDR, R>(nd, i);
         read_slot<R>(nd, i, j, c, bc);
         v[i] = S::load(pdf_load<NT>(src + elem<LAY>(j, c, a.pitch)));
+        gather_order<ADDR, R>();
     }
     bc_arrive_all<ADDR, R>(a, nd, v);
     if constexpr (COLL == 1 && KIND != K_TS_STREAM) {
@@ -858,8 +910,10 @@ __device__ __forceinline__ void update_aos_staged(const KArgs &a)
             for (int i = 0; i < Q; ++i) {
                 int j, bc;
                 int64_t c;
+                gather_pin<ADDR, R>(nd, i);
                 read_slot<R>(nd, i, j, c, bc);
                 v[i] = S::load(src[elem<L_AOS>(j, c, a.pitch)]);
+                gather_order<ADDR, R>();
             }
             bc_arrive_all<ADDR, R>(a, nd, v);
         }
@@ -939,6 +993,9 @@ __global__ void __launch_bounds__(BLOCK) k_update(KArgs a)
 {
     constexpr int R = rmap_of(KIND);
     constexpr int W = wmap_of(KIND);
+    // open boundaries exist on indirect grids, for the maps that cross links
+    constexpr bool links = R == R_PULL || R == R_AAODD || W == W_PUSH || W == W_ET0 || W == W_ET1;
+    if constexpr (ADDR == A_INDIRECT && links) bc_table_fill<typename Store<PREC>::ct>(a);
     if constexpr (ADDR == A_DIRECT && LAY == L_SOA && shifts_x(KIND)) {
         if (a.row_staged == 1) {
             update_direct_staged<PREC, KIND, COLL, false>(a);
