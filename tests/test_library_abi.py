@@ -87,3 +87,24 @@ def test_validation_errors_without_gpu():
     gi = P.Grid(16, 16, 16, addressing="indirect")
     assert gi.sizes("aa").pdf_bytes == 0  # unknown until the index is built
     assert gi.lib.lbm_bind(gi._h, P._lib.AA, None, None, None, None, None) == P._lib.LBM_E_STATE
+
+
+def test_option_ranges_without_gpu():
+    """lbm_set_option validates every option on the host; the pitch pad rounds up to 128 elements."""
+    import paper_1111_0922_amd as P
+    L = P._lib
+    g = P.Grid(64, 8, 8, wall_z=True)
+    ok = [(L.OPT_WG_LDS, -1), (L.OPT_WG_LDS, 0), (L.OPT_WG_LDS, 163840), (L.OPT_PAIR, -1), (L.OPT_PAIR, 1),
+          (L.OPT_BAND, -1), (L.OPT_BAND, 4096), (L.OPT_ROW_STAGE, 0), (L.OPT_ROW_STAGE, 1)]
+    for opt, val in ok:
+        g.set_option(opt, val)
+    bad = [(L.OPT_WG_LDS, -2), (L.OPT_WG_LDS, 163841), (L.OPT_PAIR, 2), (L.OPT_PAIR, -2), (L.OPT_BAND, -2),
+           (L.OPT_BAND, 4097), (L.OPT_PITCH_PAD, -1), (L.OPT_PITCH_PAD, (1 << 20) + 1), (99, 0)]
+    for opt, val in bad:
+        with pytest.raises(P.LbmError):
+            g.set_option(opt, val)
+    p0 = g.sizes("aa").pitch
+    g.set_option(L.OPT_PITCH_PAD, 100)
+    assert g.sizes("aa").pitch == p0 + 128
+    g.set_option(L.OPT_PITCH_PAD, 0)
+    assert g.sizes("aa").pitch == p0
