@@ -160,8 +160,6 @@ __device__ __forceinline__ const CollideParams<T> &cparams(const KArgs &a)
         return a.cpf;
 }
 
-// The population arriving in direction d from a boundary of class c >= 1,
-// given the bounced value v (compute type, stored form) ...
 // The constants C_c[d] in the compute type, copied to LDS once per workgroup
 // (bc_table_fill).  A link reads its constant there by the lane's class: a
 // vector load from the kernel arguments would wait on memory per link, and
@@ -183,6 +181,8 @@ __device__ __forceinline__ void bc_table_fill(const KArgs &a)
     __syncthreads();
 }
 
+// The population arriving in direction d from a boundary of class c >= 1,
+// given the bounced value v (compute type, stored form) ...
 template <typename T>
 __device__ __forceinline__ T bc_arrive(const KArgs &a, int c, int d, T v)
 {
@@ -326,11 +326,6 @@ struct Node<A_INDIRECT, NEED> {
         else
             return 0;
     }
-    // Opaque redefinition of the node's index registers (an empty asm, no
-    // memory access).  Called between gather and scatter, it keeps the
-    // compiler from holding 19 wide gather addresses live across the
-    // collision to reuse them for the scatter: the 32-bit ids are enough to
-    // rebuild them, which halves the registers of the in-place kernels.
     // Opaque redefinition of one neighbour id (or ET entry) right before the
     // gather that uses it: the load's address cannot be computed earlier, so
     // the wait for that id lands here and not before the first gather load.
@@ -342,6 +337,11 @@ struct Node<A_INDIRECT, NEED> {
     {
         if constexpr ((NEED & NEED_ET) != 0) asm volatile("" : "+v"(e[q]));
     }
+    // Opaque redefinition of the node's index registers (an empty asm, no
+    // memory access).  Called between gather and scatter, it keeps the
+    // compiler from holding 19 wide gather addresses live across the
+    // collision to reuse them for the scatter: the 32-bit ids are enough to
+    // rebuild them, which halves the registers of the in-place kernels.
     __device__ __forceinline__ void refresh()
     {
         if constexpr ((NEED & NEED_NB) != 0) {
