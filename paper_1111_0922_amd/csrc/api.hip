@@ -127,8 +127,9 @@ void set_block_order(const lbm_grid *g, KArgs &a, int kind)
 //    flight outgrow the L2 and partially written lines leave it several
 //    times (3.8x the algorithmic write bytes, counters).  One workgroup per
 //    CU: 3.13 -> 2.57 ms.  The even kernel (staged records, 38 KB of LDS)
-//    is best at two per CU: 0.88 -> 0.81 ms.  Lower residency slows the
-//    other AoS kernels, which keep full residency.
+//    is best at two per CU: 0.88 -> 0.81 ms.  Indirect AoS grids gain the
+//    same way (256^3 pack: even 0.354 -> 0.322, odd 2.39 -> 2.02 ms).  Lower
+//    residency slows the other AoS kernels, which keep full residency.
 static void set_residency(const lbm_grid *g, KArgs &a, int kind)
 {
     if (g->wg_lds >= 0 || a.pair || g->d.precision != LBM_F64) return;
