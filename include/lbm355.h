@@ -321,9 +321,10 @@ int lbm_batch_destroy(lbm_batch *b);
 /* Adds a grid (indirect, SoA, bound to LBM_AA, the batch's precision, state
  * initialised) in the first free slot, written to *slot_out.  The grid keeps
  * its step counter; its parity decides which AA kernel each of its nodes
- * runs; its nodes collide with BGK at the grid's omega and force.  Errors:
- * LBM_E_STATE when no slot or tile space is left, LBM_E_UNSUPPORTED for
- * other grid kinds. */
+ * runs; its nodes collide with BGK at the grid's omega and force, and its
+ * open-boundary classes (lbm_set_boundary) apply as they are set at this
+ * call.  Errors: LBM_E_STATE when no slot or tile space is left,
+ * LBM_E_UNSUPPORTED for other grid kinds. */
 int lbm_batch_add(lbm_batch *b, lbm_grid *g, int32_t *slot_out);
 
 /* Empties a slot; the grid's state stays where it is. */

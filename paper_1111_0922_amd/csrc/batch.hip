@@ -48,7 +48,11 @@ struct SlotDesc {
     uint32_t tile_begin; // its tiles (and reduction partials) are contiguous
     uint32_t n_tiles;
     int32_t active;
+    int32_t bc_on;       // open-boundary classes, as set when the grid was added
+    uint32_t bc_neg;
     int32_t pad_;
+    double bc_can[4][Q];
+    float bc_f[4][Q];
 };
 
 struct Tile {
@@ -81,9 +85,19 @@ __device__ __forceinline__ KArgs slot_args(const SlotDesc &sd, char *base)
     else
         a.cpf = sd.cpf;
     a.remap = 0;
-    a.bc_on = 0; // batched grids have walls only
-    a.bc_neg = 0;
+    // the open-boundary constants stay in the slot table: the update kernels
+    // copy them to LDS (bc_table_load), the reduction reads them there
+    a.bc_on = sd.bc_on;
+    a.bc_neg = sd.bc_neg;
     return a;
+}
+
+// Open-boundary table of one slot for a workgroup's tile (all threads; the
+// slot, hence bc_on, is uniform over the workgroup).
+template <int PREC>
+__device__ __forceinline__ void slot_bc_table(const SlotDesc *sdp)
+{
+    if (sdp->bc_on) bc_table_load<typename Store<PREC>::ct>(sdp->bc_can, sdp->bc_f);
 }
 
 // One AA time step (step k of the run) of every active slot: one workgroup
@@ -99,6 +113,7 @@ __global__ void __launch_bounds__(BLOCK) k_aa_batched(const SlotDesc *slots, con
     const Tile tl = tiles[tile];
     const SlotDesc sd = slots[tl.slot];
     const KArgs a = slot_args<PREC>(sd, base);
+    slot_bc_table<PREC>(slots + tl.slot);
     const uint32_t n = tl.node0 + threadIdx.x;
     if (n < sd.n_nodes) {
         if ((sd.t0 + k) & 1)
@@ -161,6 +176,10 @@ __global__ void __launch_bounds__(BLOCK) k_aa_batched_coop(const SlotDesc *slots
             const Tile tl = tiles[tile];
             const SlotDesc sd = slots[tl.slot];
             const KArgs a = slot_args<PREC>(sd, base);
+            if (sd.bc_on) {
+                __syncthreads(); // the previous tile's links have read the table
+                slot_bc_table<PREC>(slots + tl.slot);
+            }
             const uint32_t n = tl.node0 + threadIdx.x;
             if (n < sd.n_nodes) {
                 if ((sd.t0 + k) & 1)
@@ -187,9 +206,9 @@ __global__ void __launch_bounds__(BLOCK) k_seg_partials(const SlotDesc *slots, c
     double m[4] = {0.0, 0.0, 0.0, 0.0};
     if (n < sd.n_nodes) {
         if ((sd.t0 + steps) & 1)
-            node_moments<A_INDIRECT, L_SOA, PREC, R_AAODD>(a, n, m);
+            node_moments<A_INDIRECT, L_SOA, PREC, R_AAODD>(a, n, m, slots[tl.slot].bc_can);
         else
-            node_moments<A_INDIRECT, L_SOA, PREC, R_LOCAL>(a, n, m);
+            node_moments<A_INDIRECT, L_SOA, PREC, R_LOCAL>(a, n, m, slots[tl.slot].bc_can);
     }
     block_sum4(m, partials + 4 * (int64_t)tile);
 }
@@ -396,7 +415,6 @@ int lbm_batch_add(lbm_batch *b, lbm_grid *g, int32_t *slot_out)
     if (g->d.addressing != LBM_INDIRECT || g->d.layout != LBM_SOA || g->scheme != LBM_AA)
         return fail(LBM_E_UNSUPPORTED, "batched lattices are indirect SoA grids bound to the AA pattern");
     if (g->d.precision != b->precision) return fail(LBM_E_ARG, "grid precision differs from the batch's");
-    if (has_open_boundaries(g)) return fail(LBM_E_UNSUPPORTED, "batched lattices have walls only (no open boundaries)");
     if (g->n_nodes <= 0) return fail(LBM_E_STATE, "grid has no fluid nodes");
     const int64_t need = (g->n_nodes + BLOCK - 1) / BLOCK;
     int64_t used = 0;
@@ -425,6 +443,10 @@ int lbm_batch_add(lbm_batch *b, lbm_grid *g, int32_t *slot_out)
     sd.n_nodes = (uint32_t)g->n_nodes;
     sd.n_tiles = (uint32_t)need;
     sd.active = 1;
+    sd.bc_on = a.bc_on;
+    sd.bc_neg = a.bc_neg;
+    std::memcpy(sd.bc_can, a.bc_can, sizeof sd.bc_can);
+    std::memcpy(sd.bc_f, a.bc_f, sizeof sd.bc_f);
     b->slots[free_slot] = sd;
     b->grids[free_slot] = g;
     b->tiles_dirty = true;

@@ -171,14 +171,19 @@ __device__ __forceinline__ T (&bc_table())[4][Q]
     __shared__ T tab[4][Q];
     return tab;
 }
-// Every thread of the workgroup calls this (a.bc_on is uniform).
+// Every thread of the workgroup calls these (a.bc_on is uniform): the table
+// from the canonical constants (FP64 compute) or the stored-form ones.
+template <typename T>
+__device__ __forceinline__ void bc_table_load(const double (*can)[Q], const float (*f)[Q])
+{
+    const uint32_t t = threadIdx.x;
+    if (t < 4 * Q) bc_table<T>()[t / Q][t % Q] = sizeof(T) == 8 ? (T)can[t / Q][t % Q] : (T)f[t / Q][t % Q];
+    __syncthreads();
+}
 template <typename T>
 __device__ __forceinline__ void bc_table_fill(const KArgs &a)
 {
-    if (!a.bc_on) return;
-    const uint32_t t = threadIdx.x;
-    if (t < 4 * Q) bc_table<T>()[t / Q][t % Q] = sizeof(T) == 8 ? (T)a.bc_can[t / Q][t % Q] : (T)a.bc_f[t / Q][t % Q];
-    __syncthreads();
+    if (a.bc_on) bc_table_load<T>(a.bc_can, a.bc_f);
 }
 
 // The population arriving in direction d from a boundary of class c >= 1,
@@ -191,10 +196,14 @@ __device__ __forceinline__ T bc_arrive(const KArgs &a, int c, int d, T v)
 }
 // ... the same on canonical FP64 values, and its inverse (the bounced value
 // that makes f arrive).
+__device__ __forceinline__ double bc_arrive_canon(const double (*can)[Q], uint32_t neg, int c, int d, double f)
+{
+    const double k = can[c - 1][d];
+    return ((neg >> (c - 1)) & 1u) ? k - f : f + k;
+}
 __device__ __forceinline__ double bc_arrive_canon(const KArgs &a, int c, int d, double f)
 {
-    const double k = a.bc_can[c - 1][d];
-    return ((a.bc_neg >> (c - 1)) & 1u) ? k - f : f + k;
+    return bc_arrive_canon(a.bc_can, a.bc_neg, c, d, f);
 }
 __device__ __forceinline__ double bc_depart_canon(const KArgs &a, int c, int d, double f)
 {
@@ -1120,9 +1129,11 @@ __device__ __forceinline__ void block_sum4(double (&m)[4], double *out)
     __syncthreads(); // part[] may be reused by a following call in the same workgroup
 }
 
-// FP64 moments (M, Jx, Jy, Jz) of one node's canonical PDFs, read through map R.
+// FP64 moments (M, Jx, Jy, Jz) of one node's canonical PDFs, read through map
+// R; `can` holds the open-boundary constants (the kernel arguments' own, or a
+// batched slot's in device memory).
 template <int ADDR, int LAY, int PREC, int R>
-__device__ __forceinline__ void node_moments(const KArgs &a, uint32_t n, double (&m)[4])
+__device__ __forceinline__ void node_moments(const KArgs &a, uint32_t n, double (&m)[4], const double (*can)[Q])
 {
     using S = Store<PREC>;
     using st = typename S::st;
@@ -1136,7 +1147,7 @@ __device__ __forceinline__ void node_moments(const KArgs &a, uint32_t n, double 
         int bc;
         read_slot<R>(nd, i, j, c, bc);
         double f = S::to_canon(src[elem<LAY>(j, c, a.pitch)], i, a.sigma);
-        if (bc > 0 && a.bc_on) f = bc_arrive_canon(a, bc, i, f);
+        if (bc > 0 && a.bc_on) f = bc_arrive_canon(can, a.bc_neg, bc, i, f);
         m[0] += f;
         if (cx(i) > 0) m[1] += f;
         if (cx(i) < 0) m[1] -= f;
@@ -1152,7 +1163,7 @@ __global__ void __launch_bounds__(BLOCK) k_reduce(KArgs a)
 {
     const uint32_t n = blockIdx.x * BLOCK + threadIdx.x;
     double m[4] = {0.0, 0.0, 0.0, 0.0};
-    if (n < a.n_nodes) node_moments<ADDR, LAY, PREC, R>(a, n, m);
+    if (n < a.n_nodes) node_moments<ADDR, LAY, PREC, R>(a, n, m, a.bc_can);
     block_sum4(m, a.partials + 4 * (int64_t)blockIdx.x);
 }
 

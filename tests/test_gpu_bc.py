@@ -5,7 +5,8 @@ floor and spheres, run by every scheme (TS, OS push, OS pull, AA: both AA
 parities, ET: its write side), both layouts, against the oracle's link
 rules; the closed forms (uniform duct flow, Couette, pressure-driven
 Poiseuille) on the GPU; canonical readout and upload through the rules; the
-refusals (batch, direct grids, bad arguments).
+refusals (direct grids, bad arguments); open boundaries in batched
+lattices (alone, mixed with walls-only lattices, graph and cooperative runs).
 """
 import math
 
@@ -184,8 +185,6 @@ def test_refusals():
     mask = duct()
     aa = _grid(mask, "aa", precision="f32")
     aa.init_equilibrium()
-    with pytest.raises(P.LbmError):
-        P.Batch(2, 64, "f32").add(aa)
     direct = P.Grid(8, 8, 8, wall_z=True)
     with pytest.raises(P.LbmError):
         direct.set_boundary(1, "velocity", 1.0, (0.01, 0, 0))
@@ -193,3 +192,57 @@ def test_refusals():
         aa.set_boundary(5, "velocity", 1.0, (0.01, 0, 0))
     with pytest.raises(P.LbmError):
         aa.set_boundary(1, "pressure", -1.0, (0, 0, 0))
+
+
+def _batch_lattices(precision):
+    """Two open-boundary ducts (one started at odd parity, other classes and sizes) and a
+    walls-only porous lattice: (grid, steps before the batch) pairs, built the same way each call."""
+    import paper_1111_0922_amd as P
+    out = []
+    for k, (shape, seed, bc, pre) in enumerate([((20, 12, 10), 31, BC, 0), ((16, 9, 11), 33, {1: ("pressure", 1.004, (0, 0, 0)),
+                                                2: ("pressure", 0.996, (0, 0, 0)), 3: ("velocity", 1.0, (0, 0.01, 0))}, 1),
+                                               ((18, 14, 12), 35, {}, 0)]):
+        mask = duct(*shape, seed=seed) if bc else lbm_inputs.sphere_pack(shape, 3, 0.6, seed)[0]
+        grid = _grid(mask, "aa", precision=precision, f16_scale=64.0, bc=bc)
+        grid.set_pdfs(to_device(oracle.fluid_view(_state(mask, seed + 1), mask)))
+        if pre:
+            grid.step(pre)
+        out.append(grid)
+    return out
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "f32s"])
+@pytest.mark.parametrize("mode", ["graph", "cooperative"])
+def test_batched_open_boundaries_equal_alone(precision, mode):
+    """Open-boundary lattices in a batch (mixed with a walls-only one) evolve to the bits of
+    the same lattices stepped alone, states and moments, over two runs."""
+    import paper_1111_0922_amd as P
+    K = 7
+    alone = []
+    for grid in _batch_lattices(precision):
+        grid.step(2 * K)
+        alone.append((from_device(grid.get_pdfs()), from_device(grid.moments())))
+    batch = P.Batch(4, 1024, precision, mode=mode)
+    grids = [(batch.add(g), g) for g in _batch_lattices(precision)]
+    for _ in range(2):
+        m = batch.run(K)
+    for (slot, grid), (f_alone, m_alone) in zip(grids, alone):
+        assert np.array_equal(from_device(grid.get_pdfs()).view(np.int64), f_alone.view(np.int64)), slot
+        assert np.array_equal(m[slot].view(np.int64), m_alone.view(np.int64)), slot
+
+
+def test_batched_open_boundaries_match_oracle():
+    """FP64 duct in a batch against the oracle's link rules."""
+    import paper_1111_0922_amd as P
+    mask = duct()
+    f0 = _state(mask)
+    grid = _grid(mask, "aa")
+    grid.set_pdfs(to_device(oracle.fluid_view(f0, mask)))
+    batch = P.Batch(2, 256, "f64")
+    s = batch.add(grid)
+    m = batch.run(13)
+    want = oracle.run_ts(f0, mask, 13, 1.3, (0.0, 0.0, 0.0), bc=BC)
+    assert rel_err(from_device(grid.get_pdfs()), oracle.fluid_view(want, mask)) <= 1e-12
+    mo = oracle.moments(want, mask)
+    assert abs(m[s][0] - mo[0]) / mo[0] <= 1e-13
+    np.testing.assert_allclose(m[s][1:], mo[1:], rtol=1e-10, atol=1e-13 * mo[0])
