@@ -220,3 +220,32 @@ def test_banded_block_order_bit_identical(scheme, layout, shape, precision):
     for o in out[1:]:
         assert np.array_equal(o.view(np.int64), out[0].view(np.int64))
 
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("addressing,layout", [("direct", "soa"), ("direct", "aos"), ("indirect", "soa"),
+                                               ("indirect", "aos")])
+def test_layout_and_launch_options_bit_identical(scheme, addressing, layout):
+    """Pitch padding, the LDS reservation (residency) and the XCD-aware block order change
+    addresses and launch shapes only: every setting gives the same bits."""
+    import paper_1111_0922_amd as P
+    L = P._lib
+    if addressing == "direct":
+        solid = lbm_inputs.channel_mask(32, 10, 9)
+    else:
+        solid = lbm_inputs.sphere_pack((20, 14, 12), 3, 0.6, 41)[0]
+    ru = lbm_inputs.rho_u_field(solid.shape, lbm_inputs.velocity_noise(solid.shape, 1e-2, seed=42))
+    f0 = oracle.fluid_view(oracle.init_equilibrium(ru, solid), solid)
+    settings = [{}, {L.OPT_PITCH_PAD: 33920}, {L.OPT_WG_LDS: 0}, {L.OPT_WG_LDS: 98304}, {L.OPT_XCD_REMAP: 1}]
+    out = []
+    for opts in settings:
+        grid = make_grid(solid, scheme, addressing=addressing, layout=layout, omega=1.7, g=(1e-5, 2e-5, 0))
+        for k, v in opts.items():
+            grid.set_option(k, v)
+        grid.bind(scheme)  # the pitch pad changes the buffer sizes
+        grid.set_pdfs(to_device(f0))
+        grid.step(5)
+        out.append((from_device(grid.get_pdfs()), from_device(grid.moments())))
+    for f, m in out[1:]:
+        assert np.array_equal(f.view(np.int64), out[0][0].view(np.int64))
+        assert np.array_equal(m.view(np.int64), out[0][1].view(np.int64))
