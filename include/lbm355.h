@@ -177,9 +177,9 @@ int lbm_set_boundary(lbm_grid *g, int32_t cls, int32_t kind, double rho, const d
  *     padding added to the SoA pitch so that the 19 direction arrays do not
  *     start at addresses that agree in their low bits.  Changes the buffer
  *     sizes: the grid must be bound again afterwards.
- *   LBM_OPT_WG_LDS (bytes in [0, 163840], or -1 = default): dynamic LDS
- *     reserved by every update workgroup on top of what the kernel uses (a
- *     total the device refuses makes lbm_step fail with LBM_E_HIP).  It only
+ *   LBM_OPT_WG_LDS (bytes in [0, 122880], or -1 = default): dynamic LDS
+ *     reserved by every update workgroup on top of what the kernel uses (up
+ *     to 40 KB, so that a workgroup always fits a CU's 160 KB).  It only
  *     limits how many workgroups a CU (160 KB of LDS) keeps resident, which
  *     bounds the number of concurrent memory streams and the lines in flight
  *     per L2.  The default on SoA grids is two workgroups per CU for FP64
@@ -284,7 +284,8 @@ int lbm_init_equilibrium(lbm_grid *g, const double *d_rho_u, void *stream);
  * even in c with w+ = omega and the odd parts with w- = 1/(Lambda/(1/omega -
  * 1/2) + 1/2), Lambda = desc.trt_lambda (LBM_E_ARG unless > 0); the force
  * term is split the same way.  LBM_IDENTITY replaces the collision by the
- * identity (pure propagation).  Asynchronous. */
+ * identity (pure propagation).  Asynchronous.  A launch the device refuses
+ * returns LBM_E_HIP with the step counter at the last step launched. */
 int lbm_step(lbm_grid *g, int32_t scheme, int32_t collider, int64_t n_steps, void *stream);
 
 /* Number of completed time steps since bind/set/init. */

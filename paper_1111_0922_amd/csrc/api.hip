@@ -343,7 +343,9 @@ int lbm_set_option(lbm_grid *g, int32_t option, int64_t value)
         return LBM_OK;
     }
     if (option == LBM_OPT_WG_LDS) {
-        if (value < -1 || value > 163840) return fail(LBM_E_ARG, "workgroup LDS must be -1 or lie in [0, 163840] bytes");
+        // at most 120 KB: with a kernel's own LDS (up to 40 KB) every
+        // workgroup still fits the 160 KB of a CU
+        if (value < -1 || value > 122880) return fail(LBM_E_ARG, "workgroup LDS must be -1 or lie in [0, 122880] bytes");
         g->wg_lds = value;
         return LBM_OK;
     }
@@ -564,7 +566,6 @@ int lbm_step(lbm_grid *g, int32_t scheme, int32_t collider, int64_t n_steps, voi
             a.src = g->pdf[g->cur];
             a.dst = g->pdf[1 - g->cur];
             launch(g->scheme == LBM_OS_PUSH ? K_OS_PUSH : K_OS_PULL);
-            g->cur = 1 - g->cur;
             break;
         case LBM_AA:
             a.src = a.dst = g->pdf[0];
@@ -575,9 +576,14 @@ int lbm_step(lbm_grid *g, int32_t scheme, int32_t collider, int64_t n_steps, voi
             launch((g->t & 1) ? K_ET1 : K_ET0);
             break;
         }
+        // a refused launch (e.g. more LDS than a workgroup may hold) leaves the
+        // step counter at the last step that was launched
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_check(e, "lbm_step");
+        if (g->scheme == LBM_OS_PUSH || g->scheme == LBM_OS_PULL) g->cur = 1 - g->cur; // lattice swap
         ++g->t;
     }
-    return hip_check(hipGetLastError(), "lbm_step");
+    return LBM_OK;
 }
 
 int64_t lbm_time(const lbm_grid *g) { return g ? g->t : -1; }
