@@ -194,7 +194,8 @@ int lbm_set_boundary(lbm_grid *g, int32_t cls, int32_t kind, double rho, const d
  *     x-shifted PDFs move through LDS, so that all global accesses of a
  *     wavefront are aligned; 0 forces the plain kernels.
  *   LBM_OPT_PAIR (-1 = default, 0 or 1): on a direct SoA grid whose nx is a
- *     power of two in [2, 512], 1 makes every lane update two x-neighbours
+ *     power of two in [2, 512] or a multiple of 512 (a workgroup then holds
+ *     one 512-node segment of a row), 1 makes every lane update two x-neighbours
  *     and move them as one word per direction (32, 64 or 128 bits); 0 keeps
  *     one node per lane.  The default is two nodes per lane for FP16 storage
  *     and one otherwise.

@@ -182,11 +182,15 @@ KArgs base_args(const lbm_grid *g)
         if (d.nx <= BLOCK && (d.nx & (d.nx - 1)) == 0) a.row_staged = 1;
         if (d.nx > BLOCK && d.nx % BLOCK == 0) a.row_staged = 2;
     }
-    // two nodes per lane: nx a power of two dividing 2 * BLOCK; by default for
-    // 16-bit storage (measured below for the others)
+    // two nodes per lane: nx a power of two dividing 2 * BLOCK (whole rows) or
+    // a multiple of 2 * BLOCK (512-node row segments); by default for 16-bit
+    // storage (measured below for the others)
     const bool pair_on = g->pair > 0 || (g->pair < 0 && d.precision == LBM_F16S);
-    a.pair = (d.addressing == LBM_DIRECT && d.layout == LBM_SOA && pair_on && d.nx >= 2 && d.nx <= 2 * BLOCK &&
-              (d.nx & (d.nx - 1)) == 0) ? 1 : 0;
+    a.pair = 0;
+    if (d.addressing == LBM_DIRECT && d.layout == LBM_SOA && pair_on) {
+        if (d.nx >= 2 && d.nx <= 2 * BLOCK && (d.nx & (d.nx - 1)) == 0) a.pair = 1;
+        if (d.nx > 2 * BLOCK && d.nx % (2 * BLOCK) == 0) a.pair = 2; // 512-node row segments
+    }
     // the pair kernels' registers already hold them to two or three workgroups per CU
     if (a.pair && g->wg_lds < 0) a.lds_bytes = 0;
     a.omega = d.omega;
@@ -544,7 +548,8 @@ int lbm_step(lbm_grid *g, int32_t scheme, int32_t collider, int64_t n_steps, voi
     auto launch = [&](int kind) {
         set_block_order(g, a, kind);
         set_residency(g, a, kind);
-        (a.pair ? tb.pair[C][kind] : a.row_staged == 2 ? tb.wide[C][kind] : tb.update[A][L][C][kind])(a, nb, s);
+        (a.pair == 2 ? tb.pair_wide[C][kind] : a.pair ? tb.pair[C][kind]
+         : a.row_staged == 2 ? tb.wide[C][kind] : tb.update[A][L][C][kind])(a, nb, s);
     };
     if (collider == LBM_TRT) {
         // Lambda = (1/w+ - 1/2)(1/w- - 1/2)

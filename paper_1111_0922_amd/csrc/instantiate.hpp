@@ -16,6 +16,11 @@ void launch_pair(const KArgs &a, uint32_t blocks, hipStream_t s)
     hipLaunchKernelGGL((k_update_pair<P, K, C>), dim3(blocks), dim3(BLOCK), a.lds_bytes, s, a);
 }
 template <int P, int K, int C>
+void launch_pair_wide(const KArgs &a, uint32_t blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_update_pair_wide<P, K, C>), dim3(blocks), dim3(BLOCK), a.lds_bytes, s, a);
+}
+template <int P, int K, int C>
 void launch_wide(const KArgs &a, uint32_t blocks, hipStream_t s)
 {
     hipLaunchKernelGGL((k_update_wide<P, K, C>), dim3(blocks), dim3(BLOCK), a.lds_bytes, s, a);
@@ -68,6 +73,19 @@ void fill_pairs(PrecTable &t)
 }
 
 template <int P, int C>
+void fill_pairs_wide(PrecTable &t)
+{
+    t.pair_wide[C][K_TS_COLLIDE] = &launch_pair_wide<P, K_TS_COLLIDE, C>;
+    t.pair_wide[C][K_TS_STREAM] = &launch_pair_wide<P, K_TS_STREAM, 0>; // no collision
+    t.pair_wide[C][K_OS_PUSH] = &launch_pair_wide<P, K_OS_PUSH, C>;
+    t.pair_wide[C][K_OS_PULL] = &launch_pair_wide<P, K_OS_PULL, C>;
+    t.pair_wide[C][K_AA_EVEN] = &launch_pair_wide<P, K_AA_EVEN, C>;
+    t.pair_wide[C][K_AA_ODD] = &launch_pair_wide<P, K_AA_ODD, C>;
+    t.pair_wide[C][K_ET0] = &launch_pair_wide<P, K_ET0, C>;
+    t.pair_wide[C][K_ET1] = &launch_pair_wide<P, K_ET1, C>;
+}
+
+template <int P, int C>
 void fill_wide(PrecTable &t)
 {
     t.wide[C][K_TS_COLLIDE] = &launch_wide<P, K_TS_COLLIDE, C>;
@@ -110,6 +128,8 @@ PrecTable make_table()
     fill_pairs<P, 1>(t);
     fill_wide<P, 0>(t);
     fill_wide<P, 1>(t);
+    fill_pairs_wide<P, 0>(t);
+    fill_pairs_wide<P, 1>(t);
     fill_al<A_DIRECT, L_AOS, P>(t);
     fill_al<A_INDIRECT, L_SOA, P>(t);
     fill_al<A_INDIRECT, L_AOS, P>(t);

@@ -720,7 +720,12 @@ struct Pair<P_F32S> : PairPlain<float, v2f> {};
 template <>
 struct Pair<P_F64> : PairPlain<double, v2d> {};
 
-template <int PREC, int KIND, int COLL>
+// WIDE: nx a multiple of 2 * BLOCK, one 512-node segment of a row per
+// workgroup (as the one-node row segments): lane 0's first node and lane
+// BLOCK-1's second node reach one element beyond the segment in global
+// memory, and an owner whose word is half written by the neighbouring
+// segment stores only its own half.
+template <int PREC, int KIND, int COLL, bool WIDE>
 __device__ __forceinline__ void update_direct_pair(const KArgs &a)
 {
     using S = Store<PREC>;
@@ -740,20 +745,47 @@ __device__ __forceinline__ void update_direct_pair(const KArgs &a)
     const uint32_t n = logical_block(a) * NP + p;
     const bool valid = n < a.n_nodes;  // n_nodes is a multiple of nx, so pairs are whole
     const uint32_t nx = (uint32_t)a.nx;
-    const uint32_t xl = p & (nx - 1), row = p - xl;
+    const uint32_t seg = WIDE ? NP : nx; // a power of two
+    const uint32_t xl = p & (seg - 1), row = p - xl;
     Node<A_DIRECT, 0> nd;
     nd.init(a, valid ? n : 0);
     const word *src = static_cast<const word *>(a.src);
     word *dst = static_cast<word *>(a.dst);
+    const elem_alias *src_e = static_cast<const elem_alias *>(a.src);
+    elem_alias *dst_e = static_cast<elem_alias *>(a.dst);
     auto lds = [&](int slot) { return reinterpret_cast<elem_alias *>(&xw[slot][0]); };
+    // wide segments: whether segment position q lies beyond this workgroup,
+    // and the cell of x + 2 (the second node's right neighbour, periodic)
+    auto beyond = [&](int q) -> bool { return WIDE && (q < 0 || q >= (int)NP); };
+    int64_t dx2 = 2;
+    if constexpr (WIDE) {
+        const uint32_t m = valid ? n : 0;
+        const uint32_t x = m - fdiv(m, a.dvx) * nx;
+        if (x + 2 >= nx) dx2 = 2 - (int64_t)nx;
+    }
     // all 19 word loads first, at the pair's own x (unconditional: a lane
-    // past n_nodes addresses node 0 and never stores)
+    // past n_nodes addresses node 0 and never stores); the segment-end lanes
+    // also load the element beyond the segment that they consume
     word raw[Q];
+    el_t halo[WIDE ? NXSLOT : 1];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         int j, sx, sy, sz;
         read_off<R>(nd, i, j, sx, sy, sz);
         raw[i] = pdf_load<true>(src + (elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch) >> 1));
+        if constexpr (WIDE && shifts) {
+            if (xslot(i) >= 0 && sx != 0 && beyond(sx < 0 ? (int)xl - 1 : (int)xl + 2)) {
+                const int64_t c = sx < 0 ? nd.shift(-1, sy, sz) : nd.shift(0, sy, sz) + dx2;
+                halo[xslot(i) > 0 ? xslot(i) : 0] = pdf_load<true>(src_e + elem<L_SOA>(j, c, a.pitch));
+            }
+        }
+    }
+    if constexpr (WIDE && shifts) {
+        // opaque redefinition of the raw halo values (an empty asm, no memory
+        // access): their conversion cannot move into the load branches, where
+        // it would wait for each load in turn
+#pragma unroll
+        for (int k = 0; k < NXSLOT; ++k) asm volatile("" : "+v"(halo[k]));
     }
     ct v0[Q], v1[Q];
 #pragma unroll
@@ -775,9 +807,14 @@ __device__ __forceinline__ void update_direct_pair(const KArgs &a)
                 int j, sx, sy, sz;
                 read_off<R>(nd, i, j, sx, sy, sz);
                 if (sx != 0) {
-                    const elem_alias *h = lds(xslot(i) < 0 ? 0 : xslot(i));
-                    v0[i] = PW::load(h[row + ((xl + (uint32_t)sx) & (nx - 1))]);
-                    v1[i] = PW::load(h[row + ((xl + 1u + (uint32_t)sx) & (nx - 1))]);
+                    const int k = xslot(i) < 0 ? 0 : xslot(i);
+                    const elem_alias *h = lds(k);
+                    v0[i] = PW::load(h[row + ((xl + (uint32_t)sx) & (seg - 1))]);
+                    v1[i] = PW::load(h[row + ((xl + 1u + (uint32_t)sx) & (seg - 1))]);
+                    if constexpr (WIDE) {
+                        if (sx < 0 && beyond((int)xl - 1)) v0[i] = PW::load(halo[k]);
+                        if (sx > 0 && beyond((int)xl + 2)) v1[i] = PW::load(halo[k]);
+                    }
                 }
             }
         }
@@ -794,8 +831,17 @@ __device__ __forceinline__ void update_direct_pair(const KArgs &a)
         write_off<W>(nd, i, j, sx, sy, sz);
         if (shifts && xslot(i) >= 0 && sx != 0) {
             elem_alias *h = lds(xslot(i) < 0 ? 0 : xslot(i));
-            h[row + ((xl + (uint32_t)sx) & (nx - 1))] = PW::save(v0[i]);
-            h[row + ((xl + 1u + (uint32_t)sx) & (nx - 1))] = PW::save(v1[i]);
+            // a value whose slot lies beyond the segment goes to global memory
+            if (beyond((int)xl + sx)) {
+                if (valid) pdf_store<true>(dst_e + elem<L_SOA>(j, nd.shift(-1, sy, sz), a.pitch), PW::save(v0[i]));
+            } else {
+                h[row + ((xl + (uint32_t)sx) & (seg - 1))] = PW::save(v0[i]);
+            }
+            if (beyond((int)xl + 1 + sx)) {
+                if (valid) pdf_store<true>(dst_e + elem<L_SOA>(j, nd.shift(0, sy, sz) + dx2, a.pitch), PW::save(v1[i]));
+            } else {
+                h[row + ((xl + 1u + (uint32_t)sx) & (seg - 1))] = PW::save(v1[i]);
+            }
             continue;
         }
         if (valid) pdf_store<true>(dst + (elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch) >> 1),
@@ -808,9 +854,17 @@ __device__ __forceinline__ void update_direct_pair(const KArgs &a)
             if (xslot(i) >= 0) {
                 int j, sx, sy, sz;
                 write_off<W>(nd, i, j, sx, sy, sz);
-                if (sx != 0 && valid)
-                    pdf_store<true>(dst + (elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch) >> 1),
-                                    (word)reinterpret_cast<const word_alias *>(&xw[xslot(i) < 0 ? 0 : xslot(i)][0])[t]);
+                if (sx != 0 && valid) {
+                    const word w = reinterpret_cast<const word_alias *>(&xw[xslot(i) < 0 ? 0 : xslot(i)][0])[t];
+                    const int64_t e = elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch);
+                    // the depositors of positions xl and xl + 1 are xl - sx and xl + 1 - sx
+                    if (beyond((int)xl - sx))
+                        pdf_store<true>(dst_e + e + 1, PW::hi(w));
+                    else if (beyond((int)xl + 1 - sx))
+                        pdf_store<true>(dst_e + e, PW::lo(w));
+                    else
+                        pdf_store<true>(dst + (e >> 1), w);
+                }
             }
         }
     }
@@ -973,7 +1027,13 @@ __device__ __forceinline__ void update_aos_staged(const KArgs &a)
 template <int PREC, int KIND, int COLL>
 __global__ void __launch_bounds__(BLOCK) k_update_pair(KArgs a)
 {
-    update_direct_pair<PREC, KIND, COLL>(a);
+    update_direct_pair<PREC, KIND, COLL, false>(a);
+}
+// ... with one 512-node row segment per workgroup (nx a multiple of 512)
+template <int PREC, int KIND, int COLL>
+__global__ void __launch_bounds__(BLOCK) k_update_pair_wide(KArgs a)
+{
+    update_direct_pair<PREC, KIND, COLL, true>(a);
 }
 
 // kernels whose maps never shift along x need no staging
@@ -1178,6 +1238,7 @@ struct PrecTable {
     Launch update[2][2][2][K_NUM]; // [addr][layout][collider][kind]
     Launch pair[2][K_NUM];         // direct SoA, two nodes per lane: [collider][kind]
     Launch wide[2][K_NUM];         // direct SoA, one row segment per workgroup: [collider][kind]
+    Launch pair_wide[2][K_NUM];    // direct SoA, two nodes per lane, 512-node row segments
     Launch get[2][2][R_NUM];
     Launch set[2][2][R_NUM];
     Launch init[2][2][R_NUM];

@@ -128,10 +128,12 @@ def test_permeability_chain_to_steady_state():
 @pytest.mark.parametrize("precision", ["f16s", "f32", "f32s", "f64"])
 @pytest.mark.parametrize("scheme", ["ts", "os_push", "os_pull", "aa", "et"])
 @pytest.mark.parametrize("shape,walls", [((32, 32, 32), True), ((2, 3, 5), False), ((4, 4, 2), False),
-                                         ((64, 6, 5), True), ((512, 3, 4), True), ((256, 5, 3), False)])
+                                         ((64, 6, 5), True), ((512, 3, 4), True), ((256, 5, 3), False),
+                                         ((1024, 2, 4), True), ((1536, 1, 3), False)])
 def test_pair_kernels_bit_identical_to_one_node(precision, scheme, shape, walls):
-    """Direct SoA grids with nx a power of two can update two nodes per lane;
-    one node per lane must give the same bits, and both follow the oracle."""
+    """Direct SoA grids with nx a power of two up to 512, or a multiple of 512 (row segments),
+    can update two nodes per lane; one node per lane must give the same bits, and both follow
+    the oracle."""
     import lbm_inputs
     import paper_1111_0922_amd as P
     nx, ny, nz = shape
