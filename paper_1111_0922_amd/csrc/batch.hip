@@ -27,11 +27,17 @@
 using namespace lbm;
 using namespace lbm_host;
 
-// Dynamic LDS reserved per workgroup of the batched update kernel (caps how
-// many are resident per CU; none by default).
-#ifndef LBM_BATCH_LDS
-#define LBM_BATCH_LDS 0
-#endif
+// Dynamic LDS reserved per workgroup of the batched update kernel, only to
+// cap how many are resident per CU.  Measured on the 32 serving lattices
+// (graph runs): FP64 13.95 -> 14.61 GLUP/s with 64 KB (two per CU), FP32
+// 26.2 -> 27.05 with 40-52 KB; FP16 loses with any cap (34.1 -> 25.6 at
+// 40 KB).
+static uint32_t batch_lds(int32_t precision)
+{
+    if (precision == LBM_F64) return 65536;
+    if (precision == LBM_F32 || precision == LBM_F32S) return 53248;
+    return 0;
+}
 
 namespace lbm {
 
@@ -313,18 +319,19 @@ void launch_reduce_body(lbm_batch *b, int32_t k_steps, double *h_out, hipStream_
 void launch_batch_body(lbm_batch *b, int32_t k_steps, double *h_out, hipStream_t s)
 {
     const uint32_t nb = batch_blocks(b);
+    const uint32_t lds = batch_lds(b->precision);
     for (int32_t k = 0; k < k_steps; ++k) {
         if (b->precision == LBM_F64)
-            hipLaunchKernelGGL(k_aa_batched<P_F64>, dim3(nb), dim3(BLOCK), LBM_BATCH_LDS, s, b->d_slots, b->d_tiles,
+            hipLaunchKernelGGL(k_aa_batched<P_F64>, dim3(nb), dim3(BLOCK), lds, s, b->d_slots, b->d_tiles,
                                b->d_hdr, k, ws_base(b));
         else if (b->precision == LBM_F32)
-            hipLaunchKernelGGL(k_aa_batched<P_F32>, dim3(nb), dim3(BLOCK), LBM_BATCH_LDS, s, b->d_slots, b->d_tiles,
+            hipLaunchKernelGGL(k_aa_batched<P_F32>, dim3(nb), dim3(BLOCK), lds, s, b->d_slots, b->d_tiles,
                                b->d_hdr, k, ws_base(b));
         else if (b->precision == LBM_F16S)
-            hipLaunchKernelGGL(k_aa_batched<P_F16S>, dim3(nb), dim3(BLOCK), LBM_BATCH_LDS, s, b->d_slots, b->d_tiles,
+            hipLaunchKernelGGL(k_aa_batched<P_F16S>, dim3(nb), dim3(BLOCK), lds, s, b->d_slots, b->d_tiles,
                                b->d_hdr, k, ws_base(b));
         else
-            hipLaunchKernelGGL(k_aa_batched<P_F32S>, dim3(nb), dim3(BLOCK), LBM_BATCH_LDS, s, b->d_slots, b->d_tiles,
+            hipLaunchKernelGGL(k_aa_batched<P_F32S>, dim3(nb), dim3(BLOCK), lds, s, b->d_slots, b->d_tiles,
                                b->d_hdr, k, ws_base(b));
     }
     launch_reduce_body(b, k_steps, h_out, s);
