@@ -188,11 +188,12 @@ int lbm_set_boundary(lbm_grid *g, int32_t cls, int32_t kind, double rho, const d
  *     FP32 and 0 for FP16 storage; on AoS grids it is 0, except FP64 AA:
  *     20480 for the even kernel (two workgroups per CU) and 98304 for the
  *     odd kernel (one per CU).
- *   LBM_OPT_ROW_STAGE (0/1, default 1): on a direct SoA grid whose nx is a
- *     power of two no larger than 256, every workgroup holds whole x-rows, and
- *     where nx is a multiple of 256 one 256-node segment of a row; the
- *     x-shifted PDFs move through LDS, so that all global accesses of a
- *     wavefront are aligned; 0 forces the plain kernels.
+ *   LBM_OPT_ROW_STAGE (0/1, default 1): on a direct SoA grid the x-shifted
+ *     PDFs move through LDS, so that all global accesses of a wavefront are
+ *     aligned: a workgroup holds whole x-rows where nx is a power of two no
+ *     larger than 256, one 256-node segment of a row where nx is a multiple of
+ *     256, and otherwise 256 consecutive nodes across rows (neighbours outside
+ *     the workgroup in global memory); 0 forces the plain kernels.
  *   LBM_OPT_PAIR (-1 = default, 0 or 1): on a direct SoA grid whose nx is a
  *     power of two in [2, 512] or a multiple of 512 (a workgroup then holds
  *     one 512-node segment of a row), 1 makes every lane update two x-neighbours

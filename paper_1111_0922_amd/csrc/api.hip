@@ -181,6 +181,7 @@ KArgs base_args(const lbm_grid *g)
     if (d.addressing == LBM_DIRECT && d.layout == LBM_SOA && g->row_stage) {
         if (d.nx <= BLOCK && (d.nx & (d.nx - 1)) == 0) a.row_staged = 1;
         if (d.nx > BLOCK && d.nx % BLOCK == 0) a.row_staged = 2;
+        if (a.row_staged == 0) a.row_staged = 3; // any other nx: shifts through LDS across rows
     }
     // two nodes per lane: nx a power of two dividing 2 * BLOCK (whole rows) or
     // a multiple of 2 * BLOCK (512-node row segments); by default for 16-bit
@@ -549,7 +550,8 @@ int lbm_step(lbm_grid *g, int32_t scheme, int32_t collider, int64_t n_steps, voi
         set_block_order(g, a, kind);
         set_residency(g, a, kind);
         (a.pair == 2 ? tb.pair_wide[C][kind] : a.pair ? tb.pair[C][kind]
-         : a.row_staged == 2 ? tb.wide[C][kind] : tb.update[A][L][C][kind])(a, nb, s);
+         : a.row_staged == 2 ? tb.wide[C][kind] : a.row_staged == 3 ? tb.gen[C][kind]
+         : tb.update[A][L][C][kind])(a, nb, s);
     };
     if (collider == LBM_TRT) {
         // Lambda = (1/w+ - 1/2)(1/w- - 1/2)

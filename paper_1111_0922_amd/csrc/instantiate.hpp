@@ -16,6 +16,11 @@ void launch_pair(const KArgs &a, uint32_t blocks, hipStream_t s)
     hipLaunchKernelGGL((k_update_pair<P, K, C>), dim3(blocks), dim3(BLOCK), a.lds_bytes, s, a);
 }
 template <int P, int K, int C>
+void launch_gen(const KArgs &a, uint32_t blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_update_gen<P, K, C>), dim3(blocks), dim3(BLOCK), a.lds_bytes, s, a);
+}
+template <int P, int K, int C>
 void launch_pair_wide(const KArgs &a, uint32_t blocks, hipStream_t s)
 {
     hipLaunchKernelGGL((k_update_pair_wide<P, K, C>), dim3(blocks), dim3(BLOCK), a.lds_bytes, s, a);
@@ -70,6 +75,19 @@ void fill_pairs(PrecTable &t)
     t.pair[C][K_AA_ODD] = &launch_pair<P, K_AA_ODD, C>;
     t.pair[C][K_ET0] = &launch_pair<P, K_ET0, C>;
     t.pair[C][K_ET1] = &launch_pair<P, K_ET1, C>;
+}
+
+template <int P, int C>
+void fill_gen(PrecTable &t)
+{
+    t.gen[C][K_TS_COLLIDE] = &launch_gen<P, K_TS_COLLIDE, C>;
+    t.gen[C][K_TS_STREAM] = &launch_gen<P, K_TS_STREAM, 0>; // no collision
+    t.gen[C][K_OS_PUSH] = &launch_gen<P, K_OS_PUSH, C>;
+    t.gen[C][K_OS_PULL] = &launch_gen<P, K_OS_PULL, C>;
+    t.gen[C][K_AA_EVEN] = &launch_gen<P, K_AA_EVEN, C>;
+    t.gen[C][K_AA_ODD] = &launch_gen<P, K_AA_ODD, C>;
+    t.gen[C][K_ET0] = &launch_gen<P, K_ET0, C>;
+    t.gen[C][K_ET1] = &launch_gen<P, K_ET1, C>;
 }
 
 template <int P, int C>
@@ -130,6 +148,8 @@ PrecTable make_table()
     fill_wide<P, 1>(t);
     fill_pairs_wide<P, 0>(t);
     fill_pairs_wide<P, 1>(t);
+    fill_gen<P, 0>(t);
+    fill_gen<P, 1>(t);
     fill_al<A_DIRECT, L_AOS, P>(t);
     fill_al<A_INDIRECT, L_SOA, P>(t);
     fill_al<A_INDIRECT, L_AOS, P>(t);

@@ -121,7 +121,7 @@ struct KArgs {
     int32_t remap;         // block order: 0 natural, 1 XCD chunks, 2 XCD bands (logical_block)
     uint32_t band_yb, band_ty, band_z;
     uint32_t lds_bytes;    // dynamic LDS reserved per update workgroup (caps residency)
-    int32_t row_staged;    // direct SoA, x-shifted accesses through LDS: 1 nx divides BLOCK, 2 BLOCK divides nx
+    int32_t row_staged;    // direct SoA, x-shifted accesses through LDS: 1 nx divides BLOCK, 2 BLOCK divides nx, 3 other nx
     int32_t pair;          // direct SoA, 16-bit storage, nx divides 2 * BLOCK: two nodes per lane
     double omega, gx, gy, gz, sigma;
     double omega_minus;    // TRT odd-moment rate (== omega for BGK)
@@ -677,6 +677,115 @@ __device__ __forceinline__ void update_direct_staged(const KArgs &a)
     }
 }
 
+// Direct SoA update with x-shifts through LDS for any nx (the shapes above
+// need nx to divide BLOCK or BLOCK to divide nx).  A workgroup holds BLOCK
+// consecutive nodes, which may span row boundaries.  For an x-shift s the
+// neighbour of node n is n + s inside the same row (periodic in x: n + s -/+ nx
+// across the row's end).  A neighbour inside the workgroup is reached through
+// LDS at its own lane; one outside it is loaded from, or stored to, global
+// memory by the lane itself, and an owner stores an LDS position only if its
+// depositor lies inside the workgroup.  Every global access of a lane's own
+// node is made at the node's own x.
+template <int PREC, int KIND, int COLL>
+__device__ __forceinline__ void update_direct_general(const KArgs &a)
+{
+    using S = Store<PREC>;
+    using st = typename S::st;
+    using ct = typename S::ct;
+    constexpr int R = rmap_of(KIND);
+    constexpr int W = wmap_of(KIND);
+    st(&xs)[NXSLOT][BLOCK] = staging_rows<st>();
+    const uint32_t t = threadIdx.x;
+    const uint32_t n0 = logical_block(a) * BLOCK;
+    const uint32_t n = n0 + t;
+    const bool valid = n < a.n_nodes;
+    const uint32_t m = valid ? n : 0;
+    const uint32_t nx = (uint32_t)a.nx;
+    const uint32_t x = m - fdiv(m, a.dvx) * nx;
+    // node of the same-row neighbour at x + s (s = +-1), and whether it is one
+    // of this workgroup's nodes
+    auto along = [&](int s) -> int64_t {
+        int64_t q = (int64_t)m + s;
+        if (s > 0 && x == nx - 1) q -= nx;
+        if (s < 0 && x == 0) q += nx;
+        return q;
+    };
+    auto inside = [&](int64_t q) -> bool { return q >= (int64_t)n0 && q < (int64_t)n0 + BLOCK; };
+    Node<A_DIRECT, 0> nd;
+    nd.init(a, m);
+    const st *src = static_cast<const st *>(a.src);
+    st *dst = static_cast<st *>(a.dst);
+    // all loads first: the own-x value of every direction, and for a shifted
+    // direction whose neighbour lies outside the workgroup, that value too
+    typename S::rt raw[Q];
+    typename S::rt halo[NXSLOT];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        int j, sx, sy, sz;
+        read_off<R>(nd, i, j, sx, sy, sz);
+        raw[i] = pdf_load_raw<true, S>(src + elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch));
+        if (xslot(i) >= 0 && sx != 0 && valid && !inside(along(sx)))
+            halo[xslot(i) > 0 ? xslot(i) : 0] = pdf_load_raw<true, S>(src + elem<L_SOA>(j, nd.shift(sx, sy, sz), a.pitch));
+    }
+    ct v[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        int j, sx, sy, sz;
+        read_off<R>(nd, i, j, sx, sy, sz);
+        if (xslot(i) >= 0 && sx != 0) {
+            xs[xslot(i) < 0 ? 0 : xslot(i)][t] = S::unraw(raw[i]);
+        } else {
+            v[i] = S::load_raw(raw[i]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        if (xslot(i) >= 0) {
+            int j, sx, sy, sz;
+            read_off<R>(nd, i, j, sx, sy, sz);
+            const int k = xslot(i) < 0 ? 0 : xslot(i);
+            if (sx != 0) {
+                const int64_t q = along(sx);
+                v[i] = inside(q) ? S::load(xs[k][(uint32_t)(q - n0)]) : S::load_raw(halo[k]);
+            }
+        }
+    }
+    __syncthreads();
+    if constexpr (COLL == 1 && KIND != K_TS_STREAM) {
+        const CollideParams<ct> &p = cparams<ct>(a);
+        collide_node<ct, S::shifted>(v, p);
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        int j, sx, sy, sz;
+        write_off<W>(nd, i, j, sx, sy, sz);
+        if (xslot(i) >= 0 && sx != 0) {
+            // a lane past n_nodes stands at node 0 and deposits nothing: its
+            // neighbour could be a position whose depositor is a real node
+            const int64_t q = along(sx);
+            if (!valid) continue;
+            if (inside(q))
+                xs[xslot(i) < 0 ? 0 : xslot(i)][(uint32_t)(q - n0)] = S::save(v[i]);
+            else
+                pdf_store<true>(dst + elem<L_SOA>(j, nd.shift(sx, sy, sz), a.pitch), S::save(v[i]));
+            continue;
+        }
+        if (valid) pdf_store<true>(dst + elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch), S::save(v[i]));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        if (xslot(i) >= 0) {
+            int j, sx, sy, sz;
+            write_off<W>(nd, i, j, sx, sy, sz);
+            // the depositor of this position is the neighbour at x - sx
+            if (sx != 0 && valid && inside(along(-sx)))
+                pdf_store<true>(dst + elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch), xs[xslot(i) < 0 ? 0 : xslot(i)][t]);
+        }
+    }
+}
+
 // Direct SoA update of two x-neighbours (x even, x + 1) per lane: the pair's
 // values of one direction form one aligned word (2 x 16, 2 x 32 or 2 x 64
 // bits), so each load or store of a wavefront covers twice the bytes of the
@@ -1042,6 +1151,20 @@ __host__ __device__ constexpr bool shifts_x(int kind)
     return !(rmap_of(kind) == R_LOCAL && (wmap_of(kind) == W_LOCAL || wmap_of(kind) == W_AAEVEN));
 }
 
+// Direct SoA grids of any other nx: BLOCK consecutive nodes, shifts through
+// LDS inside the workgroup (a kernel of its own, as above).
+template <int PREC, int KIND, int COLL>
+__global__ void __launch_bounds__(BLOCK) k_update_gen(KArgs a)
+{
+    if constexpr (shifts_x(KIND)) {
+        update_direct_general<PREC, KIND, COLL>(a);
+    } else {
+        const uint32_t n = logical_block(a) * BLOCK + threadIdx.x;
+        if (n >= a.n_nodes) return;
+        update_node<A_DIRECT, L_SOA, PREC, KIND, COLL>(a, n);
+    }
+}
+
 // Direct SoA grids whose nx is a multiple of BLOCK: one row segment per
 // workgroup (a kernel of its own, so that the segment-end work does not count
 // against the registers of the other kernels).
@@ -1239,6 +1362,7 @@ struct PrecTable {
     Launch pair[2][K_NUM];         // direct SoA, two nodes per lane: [collider][kind]
     Launch wide[2][K_NUM];         // direct SoA, one row segment per workgroup: [collider][kind]
     Launch pair_wide[2][K_NUM];    // direct SoA, two nodes per lane, 512-node row segments
+    Launch gen[2][K_NUM];          // direct SoA, any other nx: shifts through LDS across rows
     Launch get[2][2][R_NUM];
     Launch set[2][2][R_NUM];
     Launch init[2][2][R_NUM];

@@ -164,10 +164,11 @@ def test_scheme_mismatch_is_an_error():
 
 
 @pytest.mark.parametrize("scheme", SCHEMES)
-@pytest.mark.parametrize("shape", [(32, 32, 32), (6, 5, 64), (5, 3, 256), (4, 4, 2), (5, 3, 512), (4, 2, 768)])
+@pytest.mark.parametrize("shape", [(32, 32, 32), (6, 5, 64), (5, 3, 256), (4, 4, 2), (5, 3, 512), (4, 2, 768),
+                                   (4, 3, 384), (3, 3, 257), (5, 4, 100), (7, 5, 6)])
 def test_row_staged_kernels_bit_identical_to_plain(scheme, shape):
-    """Direct SoA grids with nx a power of two up to 256, or a multiple of 256 (one row segment per
-    workgroup), run row-staged kernels; the plain kernels must agree bit for bit.  Shapes are (nz, ny, nx)."""
+    """Direct SoA grids run row-staged kernels (whole rows, row segments, or rows spanning
+    workgroups for any other nx); the plain kernels must agree bit for bit.  Shapes are (nz, ny, nx)."""
     import paper_1111_0922_amd as P
     solid = lbm_inputs.channel_mask(shape[2], shape[1], shape[0])
     ru = lbm_inputs.rho_u_field(solid.shape, lbm_inputs.velocity_noise(solid.shape, 1e-2, seed=12))

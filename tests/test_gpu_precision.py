@@ -163,10 +163,14 @@ def test_pair_kernels_bit_identical_to_one_node(precision, scheme, shape, walls)
 
 @pytest.mark.parametrize("precision", ["f16s", "f32s", "f32", "f64"])
 @pytest.mark.parametrize("scheme", ["ts", "os_push", "os_pull", "aa", "et"])
-@pytest.mark.parametrize("shape,walls", [((512, 2, 4), True), ((768, 2, 3), False), ((1024, 1, 4), True)])
+@pytest.mark.parametrize("shape,walls", [((512, 2, 4), True), ((768, 2, 3), False), ((1024, 1, 4), True),
+                                         ((384, 2, 4), True), ((300, 3, 3), False), ((257, 2, 3), True),
+                                         ((100, 3, 4), True), ((6, 5, 7), True), ((3, 1, 1), False)])
 def test_wide_row_segments_bit_identical_to_plain(precision, scheme, shape, walls):
-    """nx a multiple of 256: each workgroup stages one row segment and its end lanes
-    reach beyond it in global memory; the plain one-node kernels give the same bits."""
+    """nx a multiple of 256: each workgroup stages one row segment and its end lanes reach
+    beyond it in global memory; any other nx (not a power of two up to 256): the workgroup's
+    256 nodes span rows and reach neighbours outside it in global memory.  The plain one-node
+    kernels give the same bits."""
     import lbm_inputs
     import paper_1111_0922_amd as P
     nx, ny, nz = shape
