@@ -250,7 +250,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this library has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+              "(sharding over GPUs is a design, not built)", file=sys.stderr)
         sys.exit(2)
     if args.steps % 2:
         args.steps += 1  # whole even/odd pairs
