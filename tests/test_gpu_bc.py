@@ -211,7 +211,7 @@ def _batch_lattices(precision):
     return out
 
 
-@pytest.mark.parametrize("precision", ["f64", "f32", "f32s"])
+@pytest.mark.parametrize("precision", ["f64", "f32", "f32s", "f16s"])
 @pytest.mark.parametrize("mode", ["graph", "cooperative"])
 def test_batched_open_boundaries_equal_alone(precision, mode):
     """Open-boundary lattices in a batch (mixed with a walls-only one) evolve to the bits of
