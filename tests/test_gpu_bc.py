@@ -99,6 +99,25 @@ def test_open_boundaries_reduced_precision(precision, bars):
         assert float(np.max(np.abs(got - want) / np.abs(want))) <= bar, steps
 
 
+def test_open_boundaries_fp16_shifted():
+    """FP16 shifted storage (sigma = 64) against the oracle with the same storage rounding.  The
+    GPU collides in FP32 and the oracle in FP64, so a stored half can round the other way: one
+    FP16 ulp of |v| < 1, divided by sigma, is 2^-10 / 64 in f; the bound allows one such flip
+    per step."""
+    mask = duct(16, 10, 9, seed=37)
+    f0 = _state(mask, 38)
+    sigma = 64.0
+    q0 = oracle.quantize(f0, (mask != 0).astype(np.uint8), "f16s", sigma)
+    for steps in (1, 5):
+        want = oracle.fluid_view(oracle.run_ts(q0, mask, steps, 1.3, (0, 0, 0), precision="f16s", sigma=sigma,
+                                               bc=BC), mask)
+        grid = _grid(mask, "aa", precision="f16s", f16_scale=sigma)
+        grid.set_pdfs(to_device(oracle.fluid_view(q0, mask)))
+        grid.step(steps)
+        got = from_device(grid.get_pdfs())
+        assert float(np.max(np.abs(got - want))) <= steps * 2.0 ** -10 / sigma, steps
+
+
 @pytest.mark.parametrize("scheme", ["aa", "os_pull"])
 def test_readout_and_upload_through_the_rules(scheme):
     """At odd t (AA) and always (OS pull) the canonical state passes the rules:
