@@ -58,6 +58,29 @@ def test_trt_porous_matches_oracle(scheme, layout):
     assert rel_err(got, oracle.fluid_view(want, solid)) <= 1e-12
 
 
+@pytest.mark.parametrize("precision", ["f32", "f32s", "f16s"])
+@pytest.mark.parametrize("scheme", ["aa", "os_pull", "et"])
+def test_trt_reduced_precision_matches_oracle(scheme, precision):
+    """TRT with 4- and 2-byte storage against the oracle's TRT with the same storage rounding
+    (FP32 collision on the GPU, FP64 in the oracle): the bars of the BGK storage tests."""
+    import paper_1111_0922_amd as P
+    solid = lbm_inputs.channel_mask(32, 12, 10)
+    sigma = 256.0 if precision in ("f16s", "f32s") else 1.0
+    omega, lam, g = 1.7, 0.5, (1e-5, 2e-5, 0)
+    q0 = oracle.quantize(_state(solid, 27), solid, precision, sigma)
+    want = oracle.fluid_view(oracle.run_ts(q0, solid, 5, omega, g, collider="trt",
+                                           omega_minus=oracle.trt_omega_minus(omega, lam),
+                                           precision=precision, sigma=sigma), solid)
+    grid = make_grid(solid, scheme, precision=precision, omega=omega, g=g, f16_scale=sigma, trt_lambda=lam)
+    grid.set_pdfs(to_device(oracle.fluid_view(q0, solid)))
+    grid.step(5, collider="trt")
+    got = from_device(grid.get_pdfs())
+    if precision == "f16s":
+        assert float(np.max(np.abs(got - want))) <= 8 * 2.0 ** -23
+    else:
+        assert float(np.max(np.abs(got - want) / np.abs(want))) <= 5e-6  # 1e-6 per step
+
+
 @pytest.mark.parametrize("precision", PRECISIONS)
 @pytest.mark.parametrize("scheme", ["aa", "ts"])
 def test_trt_with_equal_rates_is_bgk_bitwise(scheme, precision):
