@@ -250,3 +250,29 @@ def test_layout_and_launch_options_bit_identical(scheme, addressing, layout):
     for f, m in out[1:]:
         assert np.array_equal(f.view(np.int64), out[0][0].view(np.int64))
         assert np.array_equal(m.view(np.int64), out[0][1].view(np.int64))
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("nx,precision", [(300, "f64"), (512, "f64"), (384, "f16s"), (1024, "f16s")])
+def test_launch_options_bit_identical_on_wide_rows(scheme, nx, precision):
+    """The kernels across rows (nx = 300, 384), on row segments (512) and with two nodes per lane
+    on row segments (FP16, 1024) under the XCD-aware block order, the LDS reservation and pitch
+    padding: the same bits."""
+    import paper_1111_0922_amd as P
+    L = P._lib
+    solid = lbm_inputs.channel_mask(nx, 3, 5)
+    sigma = 64.0 if precision == "f16s" else 1.0
+    ru = lbm_inputs.rho_u_field(solid.shape, lbm_inputs.velocity_noise(solid.shape, 1e-2, seed=43))
+    f0 = oracle.fluid_view(oracle.init_equilibrium(ru, solid), solid)
+    settings = [{}, {L.OPT_XCD_REMAP: 1}, {L.OPT_WG_LDS: 0}, {L.OPT_WG_LDS: 65536}, {L.OPT_PITCH_PAD: 4224}]
+    out = []
+    for opts in settings:
+        grid = make_grid(solid, scheme, precision=precision, omega=1.7, g=(1e-5, 2e-5, 0), f16_scale=sigma)
+        for k, v in opts.items():
+            grid.set_option(k, v)
+        grid.bind(scheme)
+        grid.set_pdfs(to_device(f0))
+        grid.step(5)
+        out.append(from_device(grid.get_pdfs()))
+    for f in out[1:]:
+        assert np.array_equal(f.view(np.int64), out[0].view(np.int64))
