@@ -300,6 +300,23 @@ int64_t lbm_time(const lbm_grid *g);
  * M NaN.  Uses the bound scratch.  Asynchronous. */
 int lbm_reduce_moments(lbm_grid *g, double *d_out4, void *stream);
 
+/* For callers that cannot allocate device memory or bring a workspace (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * allocation): lbm_reduce_moments with its per-block partials in a
+ * library-owned static device array instead of the bound scratch buffer.
+ * Same kernels, same block shape, hence the same bits as lbm_reduce_moments.
+ * The call allocates nothing.  The array holds LBM_NOALLOC_MAX_NODES / 256
+ * partials of 4 doubles (8 MiB); each GPU the library runs on keeps its own
+ * copy until the process ends.  The first call on a device looks the array's
+ * address up (hipGetSymbolAddress, with that device current): make that first
+ * call outside stream capture.  Every call on one GPU shares that GPU's
+ * array, so calls that overlap on one GPU (different streams, or threads)
+ * race; serialise them.  Errors: LBM_E_ARG for a grid of more than
+ * LBM_NOALLOC_MAX_NODES nodes (refused before any device work) or a null
+ * pointer, LBM_E_STATE as lbm_reduce_moments.  Asynchronous. */
+#define LBM_NOALLOC_MAX_NODES (1 << 26)
+int lbm_reduce_moments_noalloc(lbm_grid *g, double *d_out4, void *stream);
+
 /* ---------------------------------------------------------------- batches
  * Continuous batching of porous-media solves: many lattices of uneven sizes
  * (indirect SoA grids bound to the AA pattern, one storage precision) share

@@ -27,6 +27,7 @@ OPT_WG_LDS = 3
 OPT_ROW_STAGE = 4
 OPT_PAIR = 5
 OPT_BAND = 6
+NOALLOC_MAX_NODES = 1 << 26   # LBM_NOALLOC_MAX_NODES
 
 SCHEMES = {"ts": TS, "os_push": OS_PUSH, "os_pull": OS_PULL, "aa": AA, "et": ET,
            "os_nt": OS_NT, "cg": CG, "swap": SWAP}
@@ -56,7 +57,7 @@ EXPORTS = [
     "lbm_last_error", "lbm_version", "lbm_lattice", "lbm_create_grid", "lbm_destroy_grid", "lbm_set_params",
     "lbm_set_boundary",
     "lbm_set_option", "lbm_query_sizes", "lbm_build_idx", "lbm_bind", "lbm_set_pdfs", "lbm_get_pdfs",
-    "lbm_init_equilibrium", "lbm_step", "lbm_time", "lbm_reduce_moments", "lbm_stream_copy", "lbm_model_bytes",
+    "lbm_init_equilibrium", "lbm_step", "lbm_time", "lbm_reduce_moments", "lbm_reduce_moments_noalloc", "lbm_stream_copy", "lbm_model_bytes",
     "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_destroy", "lbm_batch_add", "lbm_batch_remove",
     "lbm_batch_run", "lbm_batch_moments",
 ]
@@ -99,6 +100,7 @@ def load():
     lib.lbm_time.argtypes = [gp]
     lib.lbm_time.restype = i64
     lib.lbm_reduce_moments.argtypes = [gp, vp, vp]
+    lib.lbm_reduce_moments_noalloc.argtypes = [gp, vp, vp]
     lib.lbm_stream_copy.argtypes = [vp, vp, i64, vp]
     lib.lbm_model_bytes.argtypes = [i32, i32, i32, i32]
     lib.lbm_model_bytes.restype = dbl

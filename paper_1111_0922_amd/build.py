@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblbm355.so")
-SOURCES = ["api.hip", "batch.hip", "common.hip", "k_f64.hip", "k_f32.hip", "k_f16s.hip", "k_f32s.hip"]
+SOURCES = ["api.hip", "batch.hip", "common.hip", "noalloc.hip", "k_f64.hip", "k_f32.hip", "k_f16s.hip", "k_f32s.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -173,3 +173,10 @@ class Grid:
             out = torch.empty(4, dtype=torch.float64, device=self.device)
         L.check(self.lib.lbm_reduce_moments(self._h, _ptr(out), _stream(self.device)))
         return out
+
+    def moments_noalloc(self, out: torch.Tensor) -> torch.Tensor:
+        """As moments(), into a caller-given float64[4] device tensor, through the entry point that
+        allocates nothing (its partials live in a static device array of the library)."""
+        assert out.dtype == torch.float64 and out.numel() >= 4 and out.is_contiguous()
+        L.check(self.lib.lbm_reduce_moments_noalloc(self._h, _ptr(out), _stream(self.device)))
+        return out
