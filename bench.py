@@ -16,7 +16,11 @@ Besides the headline the JSON line carries:
                 velocity inlet and a pressure outlet (open boundaries);
   porous512     AA and two-step on the 512^3 sphere pack (indirect addressing);
   copy          the STREAM-style copy bandwidth of the device;
-  cpu_baseline  the FP64 oracle timed on the host cores on a bounded sample.
+  precision     the 384^3 sphere pack run to steady state in every storage form,
+                with each form's permeability error against FP64;
+  serving       continuous batching of porous solves: solves/s, p50/p99 latency,
+                aggregate MFLUP/s and share of the HBM roofline;
+  cpu_baseline  the FP64 oracle timed on the host cores on bounded samples.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--only-main] [--no-cpu]
 """
@@ -136,30 +140,89 @@ def bench_copy(P, torch, nbytes=4 << 30, reps=10):
     return 2 * nbytes / dt / 1e9
 
 
-def cpu_baseline(budget_s=12.0):
-    """Oracle (two-step, FP64) on the host cores: 256^3 channel steps until the budget is used."""
+def cpu_info():
+    """Host CPU model, sockets and cores from lscpu (empty values if it is missing)."""
+    import subprocess
+    info = {}
+    try:
+        text = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+    except (OSError, subprocess.SubprocessError):
+        text = ""
+    for line in text.splitlines():
+        if ":" in line:
+            k, v = line.split(":", 1)
+            info[k.strip()] = v.strip()
+    return {"model": info.get("Model name", ""), "sockets": info.get("Socket(s)", ""),
+            "cores_per_socket": info.get("Core(s) per socket", ""), "threads_per_core": info.get("Thread(s) per core", ""),
+            "cpus": info.get("CPU(s)", str(os.cpu_count()))}
+
+
+def cpu_baseline():
+    """The FP64 oracle (two-step two-grid, dense lattice) timed on the host, one thread and all threads.
+
+    Samples (bounded, ~20 s of CPU work):
+      config1  32^3 channel, omega 1, 100 steps in full;
+      config2  256^3 channel, omega 1.6: 2 steps on all threads; one thread: 1 step of a
+               256 x 256 x 34 channel (32 fluid planes, the same per-node work);
+      config3  the first 32 z-planes of the 512^3 sphere pack (r 8, porosity 0.40, seed 3), periodic:
+               2 steps on all threads, 1 step on one;
+      config4  the first 32 z-planes of the 384^3 sphere pack (r 8, porosity 0.6, seed 4): 2 / 1 steps.
+    A step's time is that of a call with the steps less that of a call with none (the oracle copies
+    its lattice in and allocates the second one on every call).  `value` is config2 on all threads.
+    """
     import lbm_inputs
     import oracle
     oracle.build(force=False)
-    n = 256
-    solid = lbm_inputs.channel_mask(n, n, n)
+    all_threads = oracle.num_threads(0)
+    g = (1e-6, 0.0, 0.0)
+
+    def rate(f, solid, omega, steps, threads):
+        t0 = time.perf_counter()
+        oracle.run_ts(f, solid, 0, omega, g, threads=threads)
+        t_over = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.run_ts(f, solid, steps, omega, g, threads=threads)
+        dt = max(time.perf_counter() - t0 - t_over, 1e-9)
+        nf = int((solid == 0).sum())
+        return {"MFLUP/s": round(nf * steps / dt / 1e6, 2), "steps": steps, "threads": threads, "seconds": round(dt, 2)}
+
+    out = {}
+    solid = lbm_inputs.channel_mask(32, 32, 32)
+    f = oracle.init_equilibrium(lbm_inputs.rho_u_field(solid.shape,
+                                                       lbm_inputs.velocity_noise(solid.shape, 1e-3, seed=1)), solid)
+    out["config1_32cube_channel"] = {"all": rate(f, solid, 1.0, 100, all_threads), "one": rate(f, solid, 1.0, 100, 1)}
+    solid = lbm_inputs.channel_mask(256, 256, 256)
     f = oracle.init_equilibrium(lbm_inputs.rho_u_field(solid.shape), solid)
-    threads = oracle.num_threads(0)
-    nf = int((solid == 0).sum())
-    steps, t0 = 0, time.perf_counter()
-    while True:
-        f = oracle.run_ts(f, solid, 1, 1.6, (1e-6, 0.0, 0.0), threads=threads)
-        steps += 1
-        if time.perf_counter() - t0 > budget_s or steps >= 40:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": round(nf * steps / dt / 1e6, 2), "unit": "MFLUP/s", "cores": threads, "kind": "oracle",
-            "sample": f"256^3 channel, FP64 two-step (pull), {steps} steps, {threads} threads, {dt:.1f} s"}
+    c2 = {"all": rate(f, solid, 1.6, 2, all_threads)}
+    solid = lbm_inputs.channel_mask(256, 256, 34)
+    f = oracle.init_equilibrium(lbm_inputs.rho_u_field(solid.shape), solid)
+    c2["one"] = rate(f, solid, 1.6, 1, 1)
+    c2["one"]["sample"] = "256 x 256 x 34 channel"
+    out["config2_256cube_channel"] = c2
+    del f
+    for key, (n, phi, seed, omega) in (("config3_512pack_32planes", (512, 0.40, 3, 1.6)),
+                                        ("config4_384pack_32planes", (384, 0.6, 4, 1.0))):
+        solid = np.ascontiguousarray(lbm_inputs.sphere_pack(n, 8, phi, seed)[0][:32])
+        f = oracle.init_equilibrium(lbm_inputs.rho_u_field(solid.shape), solid)
+        out[key] = {"all": rate(f, solid, omega, 2, all_threads), "one": rate(f, solid, omega, 1, 1)}
+        del f
+    head = out["config2_256cube_channel"]["all"]
+    return {"value": head["MFLUP/s"], "unit": "MFLUP/s", "cores": all_threads, "kind": "oracle",
+            "sample": f"256^3 channel, FP64 two-step (pull), {head['steps']} steps on {all_threads} threads "
+                      "(config1 in full; configs 2-4 sampled, one thread and all threads)",
+            "configs": out, "cpu": cpu_info()}
 
 
-def serving_bench(log, n_requests, seed_base=100000):
-    """Config 5: porous permeability solves of uneven sizes, FP32 AA indirect, continuous batching."""
+def serving_bench(log, n_requests, n_light=100, seed_base=100000):
+    """Porous permeability solves of uneven sizes (FP32 AA indirect), continuous batching.
+
+    Three runs: all `n_requests` at t = 0 (saturated), then Poisson arrivals at 0.9x and 0.5x of the
+    saturated rate (`n_requests` and `n_light` requests).  The first tenth of each run's requests,
+    by arrival, is warm-up and left out of the figures.
+    """
+    import paper_1111_0922_amd as P
     from paper_1111_0922_amd.serve import GpuExecutor, Request, Scheduler, poisson_arrivals
+    bl = P.model_bytes("aa", "indirect", "f32")
 
     def run(rate, seed0, n):
         ex = GpuExecutor(max_slots=64, max_tiles=1 << 20, precision="f32", omega=1.0, g=1e-6)
@@ -168,66 +231,93 @@ def serving_bench(log, n_requests, seed_base=100000):
         arr = poisson_arrivals(n, rate, seed=seed0)
         reqs = [Request(rid=i, seed=seed0 + i, arrival=float(a)) for i, a in enumerate(arr)]
         out = sch.serve(reqs)
-        rep = sch.report(out, warmup=min(4, n // 8))
+        rep = sch.report(out, warmup=n // 10, bytes_per_lup=bl, hbm_peak_gbs=HBM_PEAK_GBS)
         rep["rate_per_s"] = rate
+        rep["arrived"] = n
+        rep["warmup_discarded"] = n // 10
         rep["steps_mean"] = float(np.mean([r.steps for r in out]))
+        rep["makespan_s"] = sch.makespan
+        log(f"[bench]   {rep['requests']} measured requests, {rep['solves_per_s']:.2f} solves/s, "
+            f"p50 {rep['p50_latency_s']:.2f} s, p99 {rep['p99_latency_s']:.2f} s, "
+            f"{rep['mflups']:.0f} MFLUP/s, busy {rep['gpu_busy_frac']:.3f}")
         return rep
 
     log(f"[bench] serving: saturated ({n_requests} requests at t=0)")
     sat = run(float("inf"), seed_base, n_requests)
     out = {"saturated": sat}
-    for frac in (0.5, 0.9):
+    for frac, n in ((0.9, n_requests), (0.5, n_light)):
         lam = frac * sat["solves_per_s"]
-        log(f"[bench] serving: Poisson rate {lam:.2f}/s ({frac} x saturated)")
-        out[f"poisson_{frac}"] = run(lam, seed_base + 1000 * int(frac * 10), n_requests)
-    out["requests_per_run"] = n_requests
+        log(f"[bench] serving: Poisson rate {lam:.2f}/s ({frac} x saturated), {n} requests")
+        out[f"poisson_{frac}"] = run(lam, seed_base + 1000 * int(frac * 10), n)
     out["budget_bytes"] = 64 << 30
     out["max_slots"] = 64
+    out["storage"] = "f32"
+    out["bytes_per_lup"] = bl
     return out
 
 
-def precision_study(log, n=384, radius=8, porosity=0.6, seed=4, tol=1e-7, max_steps=60000, k=100):
-    """Config 4: AA indirect to steady state in FP64, FP32 and FP16-shifted storage; permeability errors."""
+PERMEABILITY_BOUNDS = {"f32": 1e-2, "f32s": 1e-5, "f16s_sigma1": 5e-3, "f16s_sigma1024": 1e-4}
+
+
+def precision_study(log, n=384, radius=8, porosity=0.6, seed=4, tol=1e-7, max_steps=20000, k=100):
+    """384^3 sphere pack (r 8, porosity 0.6), AA indirect to steady state in every storage form.
+
+    Steady state: the mean velocity U, sampled every k steps, changes by less than tol of itself over
+    three consecutive windows (converged), or has no trend above tol per window while its window
+    changes keep flipping sign (noise floor: steady to the storage's rounding noise), or the cap.
+    Reported per form: steps, status, permeability and its relative error against FP64 with the
+    stated bound, mass drift, MFLUP/s and the fraction of the HBM roofline (model bytes per LUP).
+    """
     import torch
     import lbm_inputs
     import paper_1111_0922_amd as P
+    from paper_1111_0922_amd.steady import SteadyMonitor
     mask, spheres = lbm_inputs.sphere_pack(n, radius, porosity, seed)
     mt = torch.from_numpy(mask).cuda()
     phi = float(1 - mask.mean())
-    g = 1e-6
-    res = {"lattice": f"{n}^3", "radius": radius, "porosity": phi, "spheres": spheres, "tol": tol}
+    del mask
+    g, omega = 1e-6, 1.0
+    nu = (1.0 / omega - 0.5) / 3.0
+    res = {"lattice": f"{n}^3", "radius": radius, "porosity": phi, "spheres": spheres, "omega": omega, "g": g,
+           "tol": tol, "window_steps": k, "max_steps": max_steps,
+           "rule": "converged: 3 consecutive windows with |dU|/U < tol; noise_floor: least-squares trend "
+                   "< tol per window over 10 windows with >= 3 sign flips of dU; else cap"}
     for prec, sigma in (("f64", 1.0), ("f32", 1.0), ("f32s", 1.0), ("f16s", 1.0), ("f16s", 1024.0)):
-        grid = P.Grid(n, n, n, addressing="indirect", precision=prec, omega=1.0, g=(g, 0, 0), f16_scale=sigma)
+        key = prec if prec != "f16s" else f"f16s_sigma{int(sigma)}"
+        grid = P.Grid(n, n, n, addressing="indirect", precision=prec, omega=omega, g=(g, 0, 0), f16_scale=sigma)
         nf = grid.build_idx(mt)
         grid.bind("aa")
         grid.init_equilibrium()
         m0 = grid.moments().cpu().numpy()
-        prev, steps = None, 0
+        mon, steps = SteadyMonitor(tol), 0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        while steps < max_steps:
+        while steps < max_steps and mon.status == "running":
             grid.step(k)
             steps += k
             m = grid.moments().cpu().numpy()
-            U = (m[1] + 0.5 * m[0] * g) / m[0]
-            if prev is not None and U != 0 and abs(U - prev) / abs(U) < tol:
-                break
-            if steps % 5000 == 0:
-                log(f"[precision] {prec} sigma {sigma}: step {steps}, U {U:.9e}, "
-                    f"change {abs(U - prev) / abs(U) if prev else float('nan'):.2e}")
-            prev = U
+            mon.push((m[1] + 0.5 * m[0] * g) / m[0])
         dt = time.perf_counter() - t0
-        nu = (1.0 / 1.0 - 0.5) / 3.0
-        key = prec if prec not in ("f16s",) else f"f16s_sigma{int(sigma)}"
-        res[key] = {"steps": steps, "U": U, "permeability": nu * phi * U / g, "MFLUP/s": nf * steps / dt / 1e6,
-                    "mass_drift": float(abs(m[0] - m0[0]) / m0[0]), "converged": steps < max_steps}
-        log(f"[precision] {key}: {steps} steps, k = {res[key]['permeability']:.6g}, {res[key]['MFLUP/s']:.0f} MFLUP/s")
+        U = mon.history[-1]
+        mf = nf * steps / dt / 1e6
+        bl = P.model_bytes("aa", "indirect", prec)
+        res[key] = {"steps": steps, "status": mon.status if mon.status != "running" else "cap",
+                    "U": U, "permeability": nu * phi * U / g, "MFLUP/s": round(mf, 1),
+                    "frac_hbm": round(mf * bl / 1e3 / HBM_PEAK_GBS, 4), "bytes_per_lup": bl,
+                    "mass_drift": float(abs(m[0] - m0[0]) / m0[0]),
+                    "last_window_change": mon.last_change, "trend_per_window": mon.trend,
+                    "noise_per_window": mon.noise}
+        log(f"[precision] {key}: {steps} steps, {res[key]['status']}, k = {res[key]['permeability']:.8g}, "
+            f"{mf:.0f} MFLUP/s")
         del grid
         torch.cuda.empty_cache()
     k64 = res["f64"]["permeability"]
-    for key in list(res):
-        if isinstance(res[key], dict) and "permeability" in res[key]:
-            res[key]["rel_err_vs_f64"] = abs(res[key]["permeability"] - k64) / abs(k64)
+    for key, bound in PERMEABILITY_BOUNDS.items():
+        e = abs(res[key]["permeability"] - k64) / abs(k64)
+        res[key]["rel_err_vs_f64"] = e
+        res[key]["bound"] = bound
+        res[key]["within_bound"] = bool(e <= bound)
+    res["nodes"] = nf
     return res
 
 
@@ -238,9 +328,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--only-main", action="store_true", help="headline AA run only (for profiling)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--serving-requests", type=int, default=48, help="requests per serving run (0 = skip)")
+    ap.add_argument("--serving-requests", type=int, default=500,
+                    help="requests of the saturated and 0.9x Poisson serving runs (0 = skip serving)")
+    ap.add_argument("--serving-light", type=int, default=100, help="requests of the 0.5x Poisson serving run")
     ap.add_argument("--precision-study", action="store_true",
                     help="only the 384^3 steady-state precision study (FP64 / FP32 / FP16-shifted)")
+    ap.add_argument("--no-precision", action="store_true", help="skip the precision study")
     ap.add_argument("--profile-aa", choices=["f64", "f32", "f32s", "f16s"], default=None,
                     help="only the AA 256^3 channel run in this storage (for profiling)")
     ap.add_argument("--profile-porous", action="store_true",
@@ -418,8 +511,11 @@ def main():
         result["porous512"] = porous
         del mask_t
         torch.cuda.empty_cache()
+        if not args.no_precision:
+            log("[bench] precision study: 384^3 sphere pack to steady state, every storage form")
+            result["precision"] = precision_study(log)
         if args.serving_requests > 0:
-            result["serving"] = serving_bench(log, args.serving_requests)
+            result["serving"] = serving_bench(log, args.serving_requests, args.serving_light)
 
     if not args.no_cpu and not args.only_main:
         log("[bench] CPU oracle baseline")

@@ -57,8 +57,10 @@ enum {
     LBM_E_STATE = -2,       /* wrong call order, unbound buffer, scheme mismatch */
     LBM_E_HIP = -3,         /* HIP runtime error (text in lbm_last_error)      */
     LBM_E_UNSUPPORTED = -4, /* combination not provided by this build          */
-    LBM_E_DIVERGED = -5     /* reserved: the reductions are asynchronous and   */
-                            /* report divergence as a NaN mass M instead       */
+    LBM_E_DIVERGED = -5     /* a lattice diverged (non-finite moments); returned
+                               by lbm_batch_sync, which names the slots.  The
+                               asynchronous lbm_reduce_moments reports the same
+                               as a NaN mass M instead.                        */
 };
 
 /* ---------------------------------------------------------------- enums */
@@ -125,14 +127,18 @@ typedef struct {
     int64_t build_scratch_bytes; /* scratch of lbm_build_idx                        */
 } lbm_sizes;
 
-/* Text of the last error on this thread ("" if none).  Never NULL. */
+/* Text of the last error on this thread ("" if none).  Never NULL.  No paper
+ * passage: error reporting of this library. */
 const char *lbm_last_error(void);
 
-/* Library version as an integer (major * 10000 + minor * 100 + patch). */
+/* Library version as an integer (major * 10000 + minor * 100 + patch).  No
+ * paper passage. */
 int lbm_version(void);
 
 /* The library's canonical lattice: c[19*3] (cx, cy, cz per direction),
- * w[19], opp[19].  Host pointers; any may be NULL.  Touches no GPU. */
+ * w[19], opp[19].  Host pointers; any may be NULL.  Touches no GPU.  The
+ * paper names the D3Q19 model (Sec. 1, Sec. 9) but prints neither velocities
+ * nor weights: these are the standard D3Q19 set in this library's order. */
 int lbm_lattice(int32_t *c, double *w, int32_t *opp);
 
 /* Creates a grid from `desc` (host struct, copied).  Sec. 1: direct
@@ -142,10 +148,13 @@ int lbm_lattice(int32_t *c, double *w, int32_t *opp);
  * (0, 2), an unknown enum, or f16_scale <= 0 with LBM_F16S. */
 int lbm_create_grid(const lbm_grid_desc *desc, lbm_grid **out);
 
-/* Releases the host-side descriptor.  Device buffers stay the caller's. */
+/* Releases the host-side descriptor.  Device buffers stay the caller's.  No
+ * paper passage. */
 int lbm_destroy_grid(lbm_grid *g);
 
-/* Replaces omega and g (host values) for subsequent steps. */
+/* Replaces omega and g (host values) for subsequent steps.  No paper passage:
+ * the paper's solver collides with TRT (Sec. 10) and prints no operator; omega
+ * and the body force g are the parameters of this library's collisions. */
 int lbm_set_params(lbm_grid *g, double omega, const double g_acc[3]);
 
 /* Open boundaries: in- and outlets (Sec. 6 counts the in-/outlet routines
@@ -169,7 +178,9 @@ enum lbm_bc_kind { LBM_BC_WALL = 0, LBM_BC_VELOCITY = 1, LBM_BC_PRESSURE = 2 };
 int lbm_set_boundary(lbm_grid *g, int32_t cls, int32_t kind, double rho, const double u[3]);
 
 /* Launch and layout options (host values; results are bit-identical for any
- * setting):
+ * setting).  No paper passage: launch choices of this library for MI355X
+ * (the paper's own tuning is CPU cache blocking and non-temporal stores,
+ * Sec. 3, which these replace):
  *   LBM_OPT_XCD_REMAP (0/1, default 0): order the update kernels' workgroups
  *     so that consecutive node blocks run on the same XCD (MI355X dispatches
  *     workgroups round-robin over its 8 XCDs, each with its own L2).
@@ -219,10 +230,29 @@ enum {
 };
 int lbm_set_option(lbm_grid *g, int32_t option, int64_t value);
 
+/* Block order of the update kernels of an indirect grid: workgroup b updates
+ * node block d_order[b] (blocks of 256 consecutive fluid ids).  d_order is a
+ * caller-owned device array of n_blocks = ceil(N_f / 256) entries that must
+ * stay alive while the grid steps; it must be a permutation of 0..n_blocks-1
+ * (the library does not check: an entry out of range updates nothing, a
+ * repeated one updates its block twice).  MI355X dispatches workgroup b to
+ * XCD b mod 8, each XCD with its own L2, so the table decides which node
+ * blocks share an L2 and when.  NULL restores the natural order; rebuilding
+ * the index (lbm_build_idx call 1) also does.  Results are bit-identical for
+ * every permutation.  Errors: LBM_E_UNSUPPORTED on a direct grid, LBM_E_STATE
+ * before lbm_build_idx, LBM_E_ARG for a wrong n_blocks.  No paper passage:
+ * a launch choice of this library (the paper orders the fluid nodes
+ * themselves, Sec. 10; desc.brick does that here). */
+int lbm_set_block_order(lbm_grid *g, const uint32_t *d_order, int64_t n_blocks);
+
 /* Buffer sizes of `scheme` on this grid (host struct out).  For an indirect
  * grid, n_nodes, pdf/idx/aux sizes are known only after the first
  * lbm_build_idx call; before it they are 0 and cellmap_bytes /
- * build_scratch_bytes are already valid. */
+ * build_scratch_bytes are already valid.  The sizes follow the data
+ * structures of Sec. 1 (full array of all cells for direct addressing; fluid
+ * nodes plus the (q-1)-entry IDX for indirect addressing) and the number of
+ * lattices each scheme keeps: two for the two-step and one-step schemes
+ * (Secs. 2, 3), one for the AA pattern and the esoteric twist (Secs. 6, 7). */
 int lbm_query_sizes(const lbm_grid *g, int32_t scheme, lbm_sizes *out);
 
 /* Index array of indirect addressing (Sec. 1; fluid nodes and their q-1
@@ -248,7 +278,9 @@ int lbm_build_idx(lbm_grid *g, const uint8_t *d_mask, int32_t *d_cellmap, int32_
                   int32_t *d_et, void *d_scratch, int64_t *n_fluid_out, void *stream);
 
 /* Binds the caller's device buffers for `scheme` (sizes from
- * lbm_query_sizes) and resets the step counter t to 0.  pdf1 is required for
+ * lbm_query_sizes) and resets the step counter t to 0.  Secs. 2 and 3: the
+ * two-step and one-step schemes alternate between two lattices; Secs. 6 and
+ * 7: the AA pattern and the esoteric twist update one lattice in place.  pdf1 is required for
  * TS and OS, ignored otherwise; idx is required for indirect grids; aux is
  * the ET table (indirect ET only); scratch holds reduction partials.
  * The PDF contents are undefined until lbm_set_pdfs or lbm_init_equilibrium.
@@ -261,19 +293,28 @@ int lbm_bind(lbm_grid *g, int32_t scheme, void *d_pdf0, void *d_pdf1, const int3
 /* Uploads a canonical FP64 state d_canon[19][n_nodes] into the bound scheme's
  * layout (the inverse of the scheme's next read, so that the next step sees
  * exactly these f_i), rounding to the storage precision (FP16S stores
- * (f_i - w_i) * sigma rounded to nearest).  Asynchronous. */
+ * (f_i - w_i) * sigma rounded to nearest).  Asynchronous.  The layouts it
+ * inverts are the paper's: the one-step pull lattice holds post-collision
+ * values (Sec. 3, Fig. 1(c, d)), the AA lattice after an odd step holds them
+ * in the opposite slots (Sec. 6, Fig. 5), the esoteric twist's direction
+ * table flips with the parity (Sec. 7).  The canonical transfer itself has no
+ * paper passage (state exchange and checkpoints of this library). */
 int lbm_set_pdfs(lbm_grid *g, const double *d_canon, void *stream);
 
 /* Reads the canonical FP64 state f(t) into d_canon[19][n_nodes]: the values
  * the next step of the bound scheme will read (for the one-step pull scheme
- * this applies the pending propagation, for the AA pattern after an odd
- * number of steps the odd-step gather, for the esoteric twist the parity's
- * direction table).  Asynchronous. */
+ * this applies the pending propagation, Sec. 3 / Fig. 1(c); for the AA
+ * pattern after an odd number of steps the odd-step gather, Sec. 6 / Fig. 5;
+ * for the esoteric twist the parity's direction table, Sec. 7).  The readout
+ * itself has no paper passage (state exchange and checkpoints of this
+ * library).  Asynchronous. */
 int lbm_get_pdfs(const lbm_grid *g, double *d_canon, void *stream);
 
 /* f = f^eq(rho, u) per node from d_rho_u[4][n_nodes] (rho, ux, uy, uz), or the
  * rest state rho = 1, u = 0 when d_rho_u is NULL; resets t to 0.
- * Asynchronous. */
+ * Asynchronous.  No paper passage (the paper prints no initial condition):
+ * the equilibrium of this library's BGK collision, stored in the bound
+ * scheme's layout. */
 int lbm_init_equilibrium(lbm_grid *g, const double *d_rho_u, void *stream);
 
 /* Advances the bound state by n_steps time steps of `scheme` (must be the
@@ -290,14 +331,16 @@ int lbm_init_equilibrium(lbm_grid *g, const double *d_rho_u, void *stream);
  * returns LBM_E_HIP with the step counter at the last step launched. */
 int lbm_step(lbm_grid *g, int32_t scheme, int32_t collider, int64_t n_steps, void *stream);
 
-/* Number of completed time steps since bind/set/init. */
+/* Number of completed time steps since bind/set/init (its parity selects the
+ * AA kernel, Sec. 6, and the esoteric twist's direction table, Sec. 7). */
 int64_t lbm_time(const lbm_grid *g);
 
 /* FP64 moments of the canonical state: d_out4 = {M, Jx, Jy, Jz} with
  * M = sum_n sum_i f_i and J = sum_n sum_i c_i f_i (raw; the mean velocity
  * adds M g / 2).  Deterministic: per-node FP64 sums, a fixed-shape tree per
  * block of 256 nodes, then one fixed-order final pass.  A NaN anywhere makes
- * M NaN.  Uses the bound scratch.  Asynchronous. */
+ * M NaN.  Uses the bound scratch.  Asynchronous.  No paper passage: mass and
+ * mean velocity decide convergence and permeability in this library. */
 int lbm_reduce_moments(lbm_grid *g, double *d_out4, void *stream);
 
 /* For callers that cannot allocate device memory or bring a workspace (code
@@ -328,14 +371,21 @@ int lbm_reduce_moments_noalloc(lbm_grid *g, double *d_out4, void *stream);
  * lbm_step meanwhile.  Callers serialise calls on one batch. */
 typedef struct lbm_batch lbm_batch;
 
-/* Device workspace bytes for max_slots slots and max_tiles tiles in total. */
+/* Device workspace bytes for max_slots slots and max_tiles tiles in total.
+ * The batch calls have no paper passage: the serving executor is an addition
+ * of this library, built on the AA pattern because it needs one lattice per
+ * solve and independent node updates (Sec. 6 notes that this suits GPUs,
+ * whose memory is small). */
 int lbm_batch_workspace_bytes(int32_t max_slots, int64_t max_tiles, int64_t *bytes);
 
 /* Creates a batch over the caller's workspace (device memory, at least
  * lbm_batch_workspace_bytes, alive until lbm_batch_destroy).  Creates one
- * internal HIP stream used only to capture the run graph. */
+ * internal HIP stream used only to capture the run graph.  No paper passage
+ * (see lbm_batch_workspace_bytes). */
 int lbm_batch_create(int32_t max_slots, int64_t max_tiles, int32_t precision, void *d_workspace, lbm_batch **out);
 
+/* Destroys the batch and its capture stream; the workspace and the grids stay
+ * the caller's.  No paper passage. */
 int lbm_batch_destroy(lbm_batch *b);
 
 /* Adds a grid (indirect, SoA, bound to LBM_AA, the batch's precision, state
@@ -344,10 +394,11 @@ int lbm_batch_destroy(lbm_batch *b);
  * runs; its nodes collide with BGK at the grid's omega and force, and its
  * open-boundary classes (lbm_set_boundary) apply as they are set at this
  * call.  Errors: LBM_E_STATE when no slot or tile space is left,
- * LBM_E_UNSUPPORTED for other grid kinds. */
+ * LBM_E_UNSUPPORTED for other grid kinds.  No paper passage; each slot runs
+ * the even and odd kernels of the AA pattern (Sec. 6). */
 int lbm_batch_add(lbm_batch *b, lbm_grid *g, int32_t *slot_out);
 
-/* Empties a slot; the grid's state stays where it is. */
+/* Empties a slot; the grid's state stays where it is.  No paper passage. */
 int lbm_batch_remove(lbm_batch *b, int32_t slot);
 
 /* Advances every active slot by k_steps AA time steps, then reduces each
@@ -361,12 +412,23 @@ int lbm_batch_remove(lbm_batch *b, int32_t slot);
  * barrier between steps, then reduces, and synchronises `stream` before
  * returning (LBM_E_HIP if a barrier wait exceeded its bound).  Same results
  * in every mode.  Modes 0 and 1 are asynchronous on `stream`: synchronise
- * before reading
- * h_moments. */
+ * (lbm_batch_sync) before reading h_moments.  No paper passage; the steps are
+ * the AA pattern's (Sec. 6). */
 int lbm_batch_run(lbm_batch *b, int32_t k_steps, double *h_moments, int32_t use_graph, void *stream);
 
+/* Waits for the batch's work on `stream` (synchronises it), then checks the
+ * moments of every slot that took part in the last lbm_batch_run: a slot whose
+ * M, Jx, Jy or Jz is not finite has diverged (a NaN or an overflow somewhere
+ * in its lattice).  h_status (host, max_slots entries, may be NULL) receives 1
+ * for such a slot and 0 for every other.  Returns LBM_E_DIVERGED when some
+ * slot diverged (lbm_last_error lists them; the other slots' results are
+ * valid and unaffected, since every slot is updated and reduced on its own),
+ * LBM_OK otherwise.  Slots added since the last run report 0.  No paper
+ * passage: failure handling of the serving executor. */
+int lbm_batch_sync(lbm_batch *b, int32_t *h_status, void *stream);
+
 /* Copies the last run's per-slot moments (max_slots * 4 doubles) to device
- * memory d_out.  Asynchronous. */
+ * memory d_out.  Asynchronous.  No paper passage. */
 int lbm_batch_moments(lbm_batch *b, double *d_out, void *stream);
 
 /* Plain device copy of `bytes` (multiple of 16, 16-byte aligned pointers):

@@ -56,10 +56,10 @@ class Sizes(ctypes.Structure):
 EXPORTS = [
     "lbm_last_error", "lbm_version", "lbm_lattice", "lbm_create_grid", "lbm_destroy_grid", "lbm_set_params",
     "lbm_set_boundary",
-    "lbm_set_option", "lbm_query_sizes", "lbm_build_idx", "lbm_bind", "lbm_set_pdfs", "lbm_get_pdfs",
+    "lbm_set_option", "lbm_set_block_order", "lbm_query_sizes", "lbm_build_idx", "lbm_bind", "lbm_set_pdfs", "lbm_get_pdfs",
     "lbm_init_equilibrium", "lbm_step", "lbm_time", "lbm_reduce_moments", "lbm_reduce_moments_noalloc", "lbm_stream_copy", "lbm_model_bytes",
     "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_destroy", "lbm_batch_add", "lbm_batch_remove",
-    "lbm_batch_run", "lbm_batch_moments",
+    "lbm_batch_run", "lbm_batch_sync", "lbm_batch_moments",
 ]
 
 _lib = None
@@ -90,6 +90,7 @@ def load():
     lib.lbm_set_params.argtypes = [gp, dbl, ctypes.POINTER(dbl)]
     lib.lbm_set_boundary.argtypes = [gp, ctypes.c_int32, ctypes.c_int32, dbl, ctypes.POINTER(dbl)]
     lib.lbm_set_option.argtypes = [gp, i32, i64]
+    lib.lbm_set_block_order.argtypes = [gp, vp, i64]
     lib.lbm_query_sizes.argtypes = [gp, i32, ctypes.POINTER(Sizes)]
     lib.lbm_build_idx.argtypes = [gp, vp, vp, vp, vp, vp, ctypes.POINTER(i64), vp]
     lib.lbm_bind.argtypes = [gp, i32, vp, vp, vp, vp, vp]
@@ -110,6 +111,7 @@ def load():
     lib.lbm_batch_add.argtypes = [gp, gp, ctypes.POINTER(i32)]
     lib.lbm_batch_remove.argtypes = [gp, i32]
     lib.lbm_batch_run.argtypes = [gp, i32, vp, i32, vp]
+    lib.lbm_batch_sync.argtypes = [gp, vp, vp]
     lib.lbm_batch_moments.argtypes = [gp, vp, vp]
     _lib = lib
     return lib

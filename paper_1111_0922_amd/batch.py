@@ -52,8 +52,18 @@ class Batch:
         L.check(self.lib.lbm_batch_run(self._h, int(k_steps), ctypes.c_void_p(self.moments_host.data_ptr()),
                                        self.mode, _stream(self.device)))
 
+    def sync(self) -> np.ndarray:
+        """Waits for the batch's work on the current stream; returns int32[max_slots], 1 for each slot
+        of the last run whose moments are not finite (a diverged lattice), else 0."""
+        status = np.zeros(self.max_slots, dtype=np.int32)
+        rc = self.lib.lbm_batch_sync(self._h, ctypes.c_void_p(status.ctypes.data), _stream(self.device))
+        if rc not in (L.LBM_OK, L.LBM_E_DIVERGED):
+            L.check(rc)
+        return status
+
     def run(self, k_steps: int) -> np.ndarray:
-        """k_steps for every slot; returns float64[max_slots, 4] moments after synchronising."""
+        """k_steps for every slot; returns float64[max_slots, 4] moments after synchronising
+        (rows of diverged slots are not finite; see sync())."""
         self.run_async(k_steps)
-        torch.cuda.current_stream(self.device).synchronize()
+        self.last_status = self.sync()
         return self.moments_host.numpy().copy()

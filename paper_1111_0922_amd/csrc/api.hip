@@ -95,7 +95,13 @@ uint32_t update_blocks(const lbm_grid *g, const KArgs &a)
 void set_block_order(const lbm_grid *g, KArgs &a, int kind)
 {
     a.remap = g->remap;
-    if (g->d.addressing != LBM_DIRECT) return;
+    if (g->d.addressing != LBM_DIRECT) {
+        if (g->order && g->order_n == (int64_t)update_blocks(g, a)) {
+            a.remap = 3;
+            a.order = g->order;
+        }
+        return;
+    }
     int64_t band = g->band;
     if (band < 0) {
         const int R = rmap_of(kind), W = wmap_of(kind);
@@ -363,6 +369,23 @@ int lbm_set_option(lbm_grid *g, int32_t option, int64_t value)
     return fail(LBM_E_ARG, "unknown option %d", option);
 }
 
+int lbm_set_block_order(lbm_grid *g, const uint32_t *d_order, int64_t n_blocks)
+{
+    if (!g) return fail(LBM_E_ARG, "null grid");
+    if (g->d.addressing != LBM_INDIRECT) return fail(LBM_E_UNSUPPORTED, "block-order tables are for indirect grids");
+    if (!d_order) {
+        g->order = nullptr;
+        g->order_n = 0;
+        return LBM_OK;
+    }
+    if (g->idx_phase < 1) return fail(LBM_E_STATE, "build the index first: the block count follows N_f");
+    const int64_t nb = (int64_t)node_blocks(g);
+    if (n_blocks != nb) return fail(LBM_E_ARG, "table of %lld entries for %lld node blocks", (long long)n_blocks, (long long)nb);
+    g->order = d_order;
+    g->order_n = n_blocks;
+    return LBM_OK;
+}
+
 int lbm_query_sizes(const lbm_grid *g, int32_t scheme, lbm_sizes *out)
 {
     if (!g || !out) return fail(LBM_E_ARG, "null argument");
@@ -451,6 +474,8 @@ int lbm_build_idx(lbm_grid *g, const uint8_t *d_mask, int32_t *d_cellmap, int32_
         g->n_ghost = g->d.et_ghosts ? totals[1] : 0;
         g->idx_phase = 1;
         g->scheme = -1;
+        g->order = nullptr; // the block count may have changed
+        g->order_n = 0;
         if (n_fluid_out) *n_fluid_out = g->n_nodes;
         return LBM_OK;
     }

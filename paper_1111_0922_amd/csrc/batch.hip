@@ -18,7 +18,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
+#include <string>
 #include <vector>
 
 #include "common.hpp"
@@ -247,6 +249,7 @@ struct lbm_batch {
     // host mirror
     std::vector<SlotDesc> slots;
     std::vector<lbm_grid *> grids;
+    std::vector<uint8_t> in_last_run; // slot took part in the last run (its moments row is current)
     std::vector<Tile> tiles;
     bool tiles_dirty = true;
     uint32_t hdr_host[64] = {0};
@@ -286,8 +289,18 @@ int64_t ws_offset(const lbm_batch *b, const void *p)
     return (int64_t)(reinterpret_cast<uintptr_t>(p) - reinterpret_cast<uintptr_t>(ws_base(b)));
 }
 
-// Workgroups of the batched launches: one per tile.
-uint32_t batch_blocks(const lbm_batch *b) { return b->hdr_host[0] > 0 ? b->hdr_host[0] : 1u; }
+// Workgroups of the batched launches: one per tile, the count rounded up to a
+// multiple of 1/16 of its leading power of two (at most 6.25% more; the extra
+// workgroups find no tile and return at once).  Admissions and retirements
+// that keep the count in its bucket then reuse the captured graph instead of
+// capturing and instantiating a new one.
+uint32_t batch_blocks(const lbm_batch *b)
+{
+    const uint32_t n = b->hdr_host[0];
+    if (n <= 16) return n > 0 ? n : 1u;
+    const uint32_t step = (1u << (31 - __builtin_clz(n))) >> 4;
+    return (n + step - 1) / step * step;
+}
 
 // Cooperative run: one launch of all steps, workgroups limited to what the
 // device keeps resident at once.
@@ -398,6 +411,7 @@ int lbm_batch_create(int32_t max_slots, int64_t max_tiles, int32_t precision, vo
     b->d_moments = reinterpret_cast<double *>(ws + w.moments);
     b->slots.assign(max_slots, SlotDesc{});
     b->grids.assign(max_slots, nullptr);
+    b->in_last_run.assign(max_slots, 0);
     int rc = hip_check(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "lbm_batch_create (capture stream)");
     if (rc) {
         delete b;
@@ -456,6 +470,7 @@ int lbm_batch_add(lbm_batch *b, lbm_grid *g, int32_t *slot_out)
     std::memcpy(sd.bc_f, a.bc_f, sizeof sd.bc_f);
     b->slots[free_slot] = sd;
     b->grids[free_slot] = g;
+    b->in_last_run[free_slot] = 0;
     b->tiles_dirty = true;
     *slot_out = free_slot;
     return LBM_OK;
@@ -467,6 +482,7 @@ int lbm_batch_remove(lbm_batch *b, int32_t slot)
     if (!b->slots[slot].active) return fail(LBM_E_STATE, "slot %d is empty", slot);
     std::memset(&b->slots[slot], 0, sizeof(SlotDesc));
     b->grids[slot] = nullptr;
+    b->in_last_run[slot] = 0;
     b->tiles_dirty = true;
     return LBM_OK;
 }
@@ -549,8 +565,38 @@ int lbm_batch_run(lbm_batch *b, int32_t k_steps, double *h_moments, int32_t use_
         rc = hip_check(hipGetLastError(), "lbm_batch_run (launch)");
         if (rc) return rc;
     }
-    for (int32_t sl = 0; sl < b->max_slots; ++sl)
+    for (int32_t sl = 0; sl < b->max_slots; ++sl) {
+        b->in_last_run[sl] = b->slots[sl].active ? 1 : 0;
         if (b->slots[sl].active) b->grids[sl]->t += k_steps;
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_sync(lbm_batch *b, int32_t *h_status, void *stream)
+{
+    if (!b) return fail(LBM_E_ARG, "null batch");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<double> m((size_t)b->max_slots * 4);
+    int rc = hip_check(hipMemcpyAsync(m.data(), b->d_moments, m.size() * sizeof(double), hipMemcpyDeviceToHost, s),
+                       "lbm_batch_sync (moments)");
+    if (rc) return rc;
+    rc = hip_check(hipStreamSynchronize(s), "lbm_batch_sync (wait)");
+    if (rc) return rc;
+    std::string bad;
+    int n_bad = 0;
+    for (int32_t sl = 0; sl < b->max_slots; ++sl) {
+        bool diverged = false;
+        if (b->in_last_run[sl] && b->slots[sl].active)
+            for (int q = 0; q < 4; ++q) diverged = diverged || !std::isfinite(m[4 * (size_t)sl + q]);
+        if (h_status) h_status[sl] = diverged ? 1 : 0;
+        if (diverged) {
+            if (n_bad < 16) bad += (n_bad ? ", " : "") + std::to_string(sl);
+            ++n_bad;
+        }
+    }
+    if (n_bad)
+        return fail(LBM_E_DIVERGED, "%d slot(s) diverged (non-finite moments): %s%s", n_bad, bad.c_str(),
+                    n_bad > 16 ? ", ..." : "");
     return LBM_OK;
 }
 

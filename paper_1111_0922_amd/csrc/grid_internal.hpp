@@ -30,6 +30,8 @@ struct lbm_grid {
     int row_stage = 1;     // allow the row-staged direct SoA kernels
     int pair = -1;         // two nodes per lane on direct SoA grids: 1 on, 0 off, -1 default
     int band = -1;         // XCD band height (blocks) of the direct-grid block order, 0 = off, -1 = default
+    const uint32_t *order = nullptr; // indirect grids: caller's block-order table (lbm_set_block_order)
+    int64_t order_n = 0;
     // open-boundary classes 1..4 (indirect grids): kind, density, velocity
     int bc_kind[4] = {0, 0, 0, 0};
     double bc_rho[4] = {1.0, 1.0, 1.0, 1.0};

@@ -118,7 +118,8 @@ struct KArgs {
     uint32_t n_nodes;
     int32_t nx, ny, nz, z0, wall;
     FastDiv dvx, dvy;
-    int32_t remap;         // block order: 0 natural, 1 XCD chunks, 2 XCD bands (logical_block)
+    int32_t remap;         // block order: 0 natural, 1 XCD chunks, 2 XCD bands, 3 table (logical_block)
+    const uint32_t *order; // remap 3: node block of each workgroup
     uint32_t band_yb, band_ty, band_z;
     uint32_t lds_bytes;    // dynamic LDS reserved per update workgroup (caps residency)
     int32_t row_staged;    // direct SoA, x-shifted accesses through LDS: 1 nx divides BLOCK, 2 BLOCK divides nx, 3 other nx
@@ -234,10 +235,14 @@ __device__ __forceinline__ int et_write_class(const KArgs &a, const N &nd, int i
 //            rows a node reads from or writes to (y +- 1, z +- 1) then run
 //            close in time on the same XCD.  Requires band_yb % (8 band_ty)
 //            == 0 and gridDim.x = band_z * band_yb.
+//   remap 3: a caller's table (indirect grids): workgroup b updates node
+//            block order[b].
 __device__ __forceinline__ uint32_t logical_block(const KArgs &a)
 {
     uint32_t b = blockIdx.x;
-    if (a.remap == 1) {
+    if (a.remap == 3) {
+        b = a.order[b];
+    } else if (a.remap == 1) {
         const uint32_t G = gridDim.x, x = b & 7u, s = b >> 3, q = G >> 3, r = G & 7u;
         b = (x < r) ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
     } else if (a.remap == 2) {

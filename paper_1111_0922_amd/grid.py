@@ -113,6 +113,17 @@ class Grid:
     def set_option(self, option, value):
         L.check(self.lib.lbm_set_option(self._h, int(option), int(value)))
 
+    def set_block_order(self, order: torch.Tensor | None):
+        """Indirect grids: workgroup b of the update kernels takes node block order[b] (int32/uint32
+        device tensor, a permutation of the ceil(N_f / 256) blocks), or the natural order for None."""
+        if order is None:
+            L.check(self.lib.lbm_set_block_order(self._h, None, 0))
+            self._order = None
+            return
+        assert order.dtype in (torch.int32,) and order.is_contiguous() and order.device.type == "cuda"
+        self._order = order   # the library keeps the pointer
+        L.check(self.lib.lbm_set_block_order(self._h, _ptr(order), order.numel()))
+
     # ---------------------------------------------------------- setup
     def build_idx(self, mask: torch.Tensor) -> int:
         """Indirect grids: cellmap, IDX (and the ET table) from a uint8 solid mask [nz, ny, nx]."""

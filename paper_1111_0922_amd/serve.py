@@ -4,16 +4,25 @@ Requests (porous permeability solves of uneven sizes) arrive over time.  The
 scheduler prepares each one on host threads (geometry), admits prepared
 requests in arrival order while a slot is free and the device-memory budget
 holds their footprint, runs all admitted lattices together K steps at a time
-on the executor, and retires each lattice once its mean velocity has
-converged (relative change per K steps below `tol`) or `max_steps` is
-reached.  Requests that arrive while others run join at the next K-step
-boundary, so their work overlaps on the device.
+on the executor, and retires each lattice once its mean velocity is steady
+(paper_1111_0922_amd.steady: converged, or at the rounding-noise floor of its
+storage), once it diverges, or at `max_steps`.  Requests that arrive while
+others run join at the next K-step boundary, so their work overlaps on the
+device.
+
+The loop keeps the device busy: while one run of K steps is in flight, the
+scheduler admits the next requests, whose set-up (index build, equilibrium
+start) the executor runs on a second stream; it then waits for the run,
+retires finished lattices and starts the next run with the new ones in it.
 
 The executor interface (GpuExecutor below; tests use a fake one):
     prepare(req)  -> footprint in bytes (host work, may run on a pool thread)
-    admit(req)    -> slot               (allocates and initialises the lattice)
-    run(k)        -> {slot: (M, Jx, Jy, Jz)} after k more steps of every slot
+    admit(req)                          (allocates and initialises the lattice;
+                                         it joins the batch at the next start)
+    start(k)                            (k more steps of every admitted lattice, asynchronous)
+    finish()      -> {rid: (M, Jx, Jy, Jz)} of the lattices in the run, after it
     release(req)                        (frees the lattice)
+    busy_seconds  device time spent in runs so far
 """
 from __future__ import annotations
 
@@ -23,6 +32,10 @@ import time
 from dataclasses import dataclass, field
 
 import numpy as np
+
+from .steady import CONVERGED, DIVERGED, NOISE_FLOOR, RUNNING, SteadyMonitor
+
+CAP, OVERSIZE = "cap", "oversize"
 
 
 @dataclass
@@ -40,8 +53,13 @@ class Request:
     steps: int = 0
     velocity: float | None = None       # mass-weighted mean u_x at retirement
     permeability: float | None = None
-    converged: bool = False
+    status: str = RUNNING               # converged, noise_floor, diverged, cap, oversize
     history: list = field(default_factory=list)
+
+    @property
+    def converged(self) -> bool:
+        """Steady at retirement (converged or at its storage's noise floor)."""
+        return self.status in (CONVERGED, NOISE_FLOOR)
 
     @property
     def latency(self):
@@ -79,22 +97,19 @@ class Scheduler:
         self.prep_threads = int(prep_threads)
         self.clock = clock or time.perf_counter
         self.sleep = sleep or time.sleep
-        self.busy = 0.0           # time spent inside executor.run
         self.lups = 0             # lattice-node updates performed
         self.used = 0             # device bytes held by admitted requests
         self.peak_used = 0
         self.admission_order = []
+        self.makespan = 0.0
 
-    def _converged(self, req):
-        h = req.history
-        if req.steps >= self.max_steps:
-            return True, False
-        if len(h) >= 2 and h[-1] != 0.0 and math.isfinite(h[-1]):
-            if abs(h[-1] - h[-2]) / abs(h[-1]) < self.tol:
-                return True, True
-        if not math.isfinite(h[-1]):
-            return True, False
-        return False, False
+    def _retire(self, r, status, u, now):
+        r.status = status
+        r.velocity = float(u)
+        nu = (1.0 / self.omega - 0.5) / 3.0
+        phi = r.n_fluid / r.n_cells if r.n_cells else float("nan")
+        r.permeability = nu * phi * float(u) / self.g
+        r.finished = now
 
     def serve(self, requests):
         """Serves `requests` (sorted by arrival); returns them with timings and results filled in."""
@@ -102,7 +117,9 @@ class Scheduler:
         pending = list(reqs)
         preparing = {}
         ready = []
-        active = {}
+        active = {}               # rid -> request (admitted, not retired)
+        monitors = {}
+        in_flight = False
         t0 = self.clock()
         now = lambda: self.clock() - t0  # noqa: E731
         pool = cf.ThreadPoolExecutor(max_workers=self.prep_threads) if self.prep_threads > 0 else None
@@ -122,68 +139,100 @@ class Scheduler:
                         del preparing[rid]
                         ready.append(r)
                 ready.sort(key=lambda r: (r.arrival, r.rid))
-                # admission: arrival order, slot and budget permitting
+                # admission (arrival order, slot and budget permitting), overlapping the run in flight
                 while ready and len(active) < self.max_slots and self.used + ready[0].footprint <= self.budget:
                     r = ready.pop(0)
-                    r.slot = self.ex.admit(r)
+                    self.ex.admit(r)
                     r.admitted = now()
                     self.used += r.footprint
                     self.peak_used = max(self.peak_used, self.used)
-                    active[r.slot] = r
+                    active[r.rid] = r
+                    monitors[r.rid] = SteadyMonitor(self.tol)
                     self.admission_order.append(r.rid)
                 if ready and not active and ready[0].footprint > self.budget:
                     r = ready.pop(0)  # can never fit: fail it rather than stall the queue
                     r.finished = now()
-                    r.converged = False
+                    r.status = OVERSIZE
                     continue
-                if active:
-                    t_run = self.clock()
-                    moms = self.ex.run(self.k)
-                    self.busy += self.clock() - t_run
-                    for slot, r in list(active.items()):
+                if in_flight:
+                    moms = self.ex.finish()
+                    in_flight = False
+                    for rid, m in moms.items():
+                        r = active[rid]
                         r.steps += self.k
                         self.lups += r.n_fluid * self.k
-                        u = mean_velocity_x(moms[slot], self.g)
+                        u = mean_velocity_x(m, self.g)
                         r.history.append(float(u))
-                        done, conv = self._converged(r)
-                        if done:
-                            r.velocity = float(u)
-                            nu = (1.0 / self.omega - 0.5) / 3.0
-                            phi = r.n_fluid / r.n_cells if r.n_cells else float("nan")
-                            r.permeability = nu * phi * float(u) / self.g
-                            r.converged = conv
-                            r.finished = now()
+                        st = monitors[rid].push(u)
+                        if st == RUNNING and r.steps >= self.max_steps:
+                            st = CAP
+                        if st != RUNNING:
+                            self._retire(r, st, u, now())
                             self.ex.release(r)
                             self.used -= r.footprint
-                            del active[slot]
+                            del active[rid], monitors[rid]
+                if active:
+                    self.ex.start(self.k)
+                    in_flight = True
+                elif not (pending or preparing or ready):
+                    break
                 else:
                     # idle: wait for the next arrival or preparation
                     nxt = pending[0].arrival - now() if pending else 0.001
                     self.sleep(max(min(nxt, 0.005), 0.0005))
         finally:
+            if in_flight:
+                self.ex.finish()
             if pool:
                 pool.shutdown(wait=True)
         self.makespan = now()
         return reqs
 
-    def report(self, reqs, warmup: int = 0):
+    def report(self, reqs, warmup: int = 0, bytes_per_lup: float | None = None, hbm_peak_gbs: float = 8000.0):
+        """Throughput and latency over the requests after the first `warmup` (by arrival).
+
+        Latency percentiles are given over every finished request and, separately, over the steady
+        ones (converged or at their noise floor); requests that hit the step cap, diverged or could
+        never fit are counted, not hidden.
+        """
         done = [r for r in reqs[warmup:] if r.finished is not None]
+        steady = [r for r in done if r.converged]
         lat = np.array([r.latency for r in done]) if done else np.zeros(0)
+        lat_s = np.array([r.latency for r in steady]) if steady else np.zeros(0)
         span = (max(r.finished for r in done) - min(r.arrival for r in done)) if done else 0.0
-        return {
+        busy = float(getattr(self.ex, "busy_seconds", float("nan")))
+        pct = lambda a, q: float(np.percentile(a, q)) if len(a) else float("nan")  # noqa: E731
+        out = {
             "requests": len(done),
-            "converged": int(sum(r.converged for r in done)),
+            "converged": int(sum(r.status == CONVERGED for r in done)),
+            "noise_floor": int(sum(r.status == NOISE_FLOOR for r in done)),
+            "cap": int(sum(r.status == CAP for r in done)),
+            "diverged": int(sum(r.status == DIVERGED for r in done)),
+            "oversize": int(sum(r.status == OVERSIZE for r in done)),
             "solves_per_s": len(done) / span if span > 0 else float("nan"),
-            "p50_latency_s": float(np.percentile(lat, 50)) if len(lat) else float("nan"),
-            "p99_latency_s": float(np.percentile(lat, 99)) if len(lat) else float("nan"),
-            "gpu_busy_frac": self.busy / self.makespan if getattr(self, "makespan", 0) else float("nan"),
-            "mflups": self.lups / self.busy / 1e6 if self.busy > 0 else float("nan"),
+            "p50_latency_s": pct(lat, 50),
+            "p99_latency_s": pct(lat, 99),
+            "p50_latency_steady_s": pct(lat_s, 50),
+            "p99_latency_steady_s": pct(lat_s, 99),
+            "gpu_busy_frac": busy / self.makespan if self.makespan > 0 and math.isfinite(busy) else float("nan"),
+            "mflups": self.lups / busy / 1e6 if busy > 0 else float("nan"),
             "peak_bytes": self.peak_used,
         }
+        if bytes_per_lup and busy > 0:
+            gbs = self.lups * bytes_per_lup / busy / 1e9
+            out["GB/s"] = gbs
+            out["frac_hbm"] = gbs / hbm_peak_gbs
+            out["bytes_per_lup"] = bytes_per_lup
+        return out
 
 
 class GpuExecutor:
-    """Executor on one GPU: each request a porous indirect AA lattice in one shared Batch."""
+    """Executor on one GPU: each request a porous indirect AA lattice in one shared Batch.
+
+    Runs go on the current stream; the set-up of admitted lattices (index build, binding,
+    equilibrium start) goes on a second stream of default priority, so that it overlaps the run
+    in flight.  The device time of every run is taken with events on the run's stream.
+    """
 
     def __init__(self, max_slots=64, max_tiles=1 << 20, precision="f32", omega=1.0, g=1e-6, use_graph=True,
                  device=None):
@@ -192,11 +241,18 @@ class GpuExecutor:
         from .batch import Batch
         self.torch = torch
         self.batch = Batch(max_slots, max_tiles, precision, use_graph=use_graph, device=device)
+        self.device = self.batch.device
+        self.setup_stream = torch.cuda.Stream(device=self.device)
         self.precision = precision
         self.omega = float(omega)
         self.g = float(g)
-        self.grids = {}
+        self.grids = {}           # rid -> grid in the batch
+        self.slots = {}           # rid -> slot
+        self.joining = {}         # rid -> grid set up, joins at the next start
         self.masks = {}
+        self.in_run = []          # rids of the run in flight
+        self.events = None
+        self.busy_seconds = 0.0
         self.pdf_size = {"f64": 8, "f32": 4, "f16s": 2, "f32s": 4}[precision]
 
     def prepare(self, req):
@@ -214,23 +270,42 @@ class GpuExecutor:
         from .grid import Grid
         torch = self.torch
         e = req.params["edge"]
-        grid = Grid(e, e, e, addressing="indirect", precision=self.precision, omega=self.omega,
-                    g=(self.g, 0.0, 0.0), f16_scale=1024.0)
-        mask = torch.from_numpy(self.masks.pop(req.rid)).to(self.batch.device)
-        nf = grid.build_idx(mask)
-        assert nf == req.n_fluid
-        grid.cellmap = None   # the index is built; the cellmap is no longer needed
-        grid._mask = None
-        grid.bind("aa")
-        grid.init_equilibrium()
-        slot = self.batch.add(grid)
-        self.grids[slot] = grid
-        return slot
+        with torch.cuda.stream(self.setup_stream):
+            grid = Grid(e, e, e, addressing="indirect", precision=self.precision, omega=self.omega,
+                        g=(self.g, 0.0, 0.0), f16_scale=1024.0, device=self.device)
+            mask = torch.from_numpy(self.masks.pop(req.rid)).to(self.device, non_blocking=False)
+            nf = grid.build_idx(mask)
+            assert nf == req.n_fluid
+            grid.cellmap = None   # the index is built; the cellmap is no longer needed
+            grid._mask = None
+            grid.bind("aa")
+            grid.init_equilibrium()
+        # the run stream reads this lattice only after the host has seen its set-up finish
+        self.setup_stream.synchronize()
+        self.joining[req.rid] = grid
 
-    def run(self, k):
-        m = self.batch.run(k)
-        return {s: m[s] for s in self.grids}
+    def start(self, k):
+        torch = self.torch
+        for rid, grid in self.joining.items():
+            self.slots[rid] = self.batch.add(grid)
+            self.grids[rid] = grid
+        self.joining = {}
+        self.in_run = list(self.grids)
+        stream = torch.cuda.current_stream(self.device)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        self.batch.run_async(k)
+        ev1.record(stream)
+        self.events = (ev0, ev1)
+
+    def finish(self):
+        self.batch.last_status = self.batch.sync()
+        ev0, ev1 = self.events
+        self.busy_seconds += ev0.elapsed_time(ev1) * 1e-3
+        m = self.batch.moments_host.numpy()
+        return {rid: m[self.slots[rid]].copy() for rid in self.in_run}
 
     def release(self, req):
-        self.batch.remove(req.slot)
-        self.grids.pop(req.slot, None)
+        slot = self.slots.pop(req.rid)
+        self.batch.remove(slot)
+        self.grids.pop(req.rid, None)

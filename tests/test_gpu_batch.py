@@ -164,3 +164,102 @@ def test_empty_batch_runs_and_reports_nothing():
     ref.step(6)
     assert np.array_equal(from_device(grid.get_pdfs()).view(np.int64), from_device(ref.get_pdfs()).view(np.int64))
     assert np.array_equal(m[s], from_device(ref.moments()))
+
+
+def _poison(grid, node=7):
+    """Replaces one node's canonical PDFs by NaN (a diverged lattice)."""
+    f = grid.get_pdfs()
+    f[:, node] = float("nan")
+    grid.set_pdfs(f)
+
+
+def test_diverged_slot_is_reported_alone_and_batch_mates_continue():
+    """A lattice with a NaN node: lbm_batch_sync returns LBM_E_DIVERGED and marks that slot only; the
+    other slots keep the bits they have alone, before and after the diverged one leaves."""
+    import paper_1111_0922_amd as P
+    from paper_1111_0922_amd.grid import _stream
+    K = 10
+    batch = P.Batch(8, 4096, "f32")
+    grids = [_grid(*gm, "f32")[0] for gm in GEOMS]
+    _poison(grids[2])
+    slots = [batch.add(g) for g in grids]
+    batch.run_async(K)
+    status = np.zeros(batch.max_slots, dtype=np.int32)
+    import ctypes
+    rc = batch.lib.lbm_batch_sync(batch._h, ctypes.c_void_p(status.ctypes.data), _stream(batch.device))
+    assert rc == P._lib.LBM_E_DIVERGED
+    assert f"{slots[2]}".encode() in batch.lib.lbm_last_error()
+    assert [int(status[s]) for s in slots] == [0, 0, 1, 0]
+    m = batch.moments_host.numpy().copy()
+    assert not np.isfinite(m[slots[2]]).all()
+    batch.remove(slots[2])
+    m2 = batch.run(K)
+    assert not batch.last_status.any()
+    for i in (0, 1, 3):
+        ref = _grid(*GEOMS[i], "f32")[0]
+        ref.step(K)
+        assert np.array_equal(m[slots[i]], from_device(ref.moments()))
+        ref.step(K)
+        assert np.array_equal(m2[slots[i]], from_device(ref.moments()))
+        assert np.array_equal(from_device(grids[i].get_pdfs()).view(np.int64), from_device(ref.get_pdfs()).view(np.int64))
+
+
+def test_alone_equals_mix_with_a_192cube_request():
+    """The largest serving lattice (192^3, request seed 7008) in a mix with smaller ones: every lattice
+    ends with the bits it has alone (FP32, graph runs, two runs of K steps)."""
+    import paper_1111_0922_amd as P
+
+    def serving_grid(seed):
+        mask, p = lbm_inputs.serving_geometry(seed)
+        e = p["edge"]
+        grid = P.Grid(e, e, e, addressing="indirect", precision="f32", omega=1.0, g=(1e-6, 0, 0), f16_scale=1024.0)
+        grid.build_idx(torch.from_numpy(mask).cuda())
+        grid.bind("aa")
+        grid.init_equilibrium()
+        return grid, e
+
+    seeds = (7008, 7004, 7030, 7001)
+    K = 50
+    alone = []
+    for s in seeds:
+        grid, e = serving_grid(s)
+        grid.step(2 * K)
+        alone.append((from_device(grid.get_pdfs()), from_device(grid.moments()), e))
+        del grid
+    assert alone[0][2] == 192
+    batch = P.Batch(8, 1 << 16, "f32")
+    mix = [serving_grid(s)[0] for s in seeds]
+    slots = [batch.add(g) for g in mix]
+    for _ in range(2):
+        m = batch.run(K)
+    for s, g, (f, mo, _) in zip(slots, mix, alone):
+        assert np.array_equal(from_device(g.get_pdfs()).view(np.int64), f.view(np.int64)), s
+        assert np.array_equal(m[s].view(np.int64), mo.view(np.int64)), s
+
+
+def test_scheduler_on_gpu_fails_only_the_diverged_request():
+    """Served on the GPU executor, a request whose lattice is poisoned at admission ends as diverged;
+    the others reach a steady state with the permeability they reach when served without it."""
+    from paper_1111_0922_amd.serve import GpuExecutor, Request, Scheduler
+
+    class Poisoning(GpuExecutor):
+        def admit(self, req):
+            super().admit(req)
+            if req.seed == 7006:
+                _poison(self.joining[req.rid])
+                torch.cuda.synchronize()
+
+    def serve(ex_cls, seeds):
+        ex = ex_cls(max_slots=4, max_tiles=1 << 14, precision="f32")
+        sch = Scheduler(ex, hbm_budget=8 << 30, max_slots=4, k_steps=100, tol=1e-6, max_steps=6000, prep_threads=2)
+        out = sch.serve([Request(rid=i, seed=s, arrival=0.01 * i) for i, s in enumerate(seeds)])
+        return {r.seed: r for r in out}, sch
+
+    ref, _ = serve(GpuExecutor, (7004, 7039))
+    got, sch = serve(Poisoning, (7004, 7006, 7039))
+    assert got[7006].status == "diverged" and got[7006].steps == 100
+    for s in (7004, 7039):
+        assert got[s].status == ref[s].status and got[s].steps == ref[s].steps
+        assert got[s].permeability == ref[s].permeability
+    rep = sch.report(list(got.values()))
+    assert rep["diverged"] == 1 and rep["requests"] == 3

@@ -116,3 +116,27 @@ def test_all_solid_mask_has_no_nodes_and_refuses_steps():
         grid.step(1)
     with pytest.raises(P.LbmError):
         grid.moments()
+
+
+def test_mask_values_above_five_are_plain_walls_on_the_gpu():
+    """Any mask value other than 0 and 2..5 is a plain wall: the GPU builder gives the cellmap and IDX
+    of the same mask with every such value replaced by 1 (and the oracle's)."""
+    solid = lbm_inputs.sphere_pack((21, 13, 10), 3, 0.55, seed=9)[0]
+    m = solid.copy()
+    big = np.array([6, 7, 9, 64, 200, 255], np.uint8)
+    m[solid == 1] = big[np.arange(int(solid.sum())) % len(big)]
+    out = []
+    for mask in (solid, m):
+        grid = make_grid(mask, "aa", addressing="indirect")
+        torch.cuda.synchronize()
+        s = grid.sizes("aa")
+        nf = grid.n_nodes
+        cm = grid.cellmap[: mask.size].cpu().numpy()
+        idx = grid.idx.view(-1)[: 18 * s.idx_pitch].view(18, s.idx_pitch)[:, :nf].cpu().numpy()
+        out.append((nf, cm, idx))
+    assert out[0][0] == out[1][0]
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+    np.testing.assert_array_equal(out[0][2], out[1][2])
+    c_o, idx_o, nf_o = oracle.build_idx(m)
+    assert nf_o == out[1][0]
+    np.testing.assert_array_equal(out[1][2], idx_o)

@@ -108,3 +108,17 @@ def test_option_ranges_without_gpu():
     assert g.sizes("aa").pitch == p0 + 128
     g.set_option(L.OPT_PITCH_PAD, 0)
     assert g.sizes("aa").pitch == p0
+
+
+def test_every_declaration_cites_a_passage_or_says_it_has_none():
+    """Each entry point's comment in lbm355.h names the paper passage that defines it (a section,
+    table or figure) or says that it has none (an addition of this library)."""
+    with open(os.path.join(ROOT, "include", "lbm355.h")) as fh:
+        src = fh.read()
+    missing = []
+    for m in re.finditer(r"^(?:const char \*|int64_t |double |int )(lbm_\w+)\(", src, flags=re.M):
+        head = src[:m.start()]
+        comment = " ".join(head[head.rfind("/*"):].replace("*", " ").split())
+        if not re.search(r"\b(Secs?\.|Tables?|Fig\.)\s*\d|No paper passage|cannot allocate", comment):
+            missing.append(m.group(1))
+    assert not missing, missing

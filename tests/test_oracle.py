@@ -528,3 +528,25 @@ def test_bc_idx_codes():
     # the fluid cell at (0, 0, 1) has the plain solid cell at -z (direction 6, row 5)
     assert idx[5][cellmap[1, 0, 0]] == -1
     assert sorted(set(idx[idx < 0].tolist())) == [-4, -1]
+
+
+def test_mask_values_above_five_are_plain_walls():
+    """Mask values 2..5 name boundary classes 1..4; every other non-zero value is a plain wall:
+    -1 in IDX and plain bounce-back, even when every class is an open boundary."""
+    solid = lbm_inputs.sphere_pack((12, 10, 9), 3, 0.6, seed=8)[0]
+    m = solid.copy()
+    big = np.array([6, 7, 9, 64, 200, 255], np.uint8)
+    m[solid == 1] = big[np.arange(int(solid.sum())) % len(big)]
+    c1, idx1, nf1 = oracle.build_idx(solid)
+    c2, idx2, nf2 = oracle.build_idx(m)
+    assert nf1 == nf2
+    np.testing.assert_array_equal(c1, c2)
+    np.testing.assert_array_equal(idx1, idx2)
+    assert set(np.unique(idx2[idx2 < 0]).tolist()) == {-1}
+    ru = lbm_inputs.rho_u_field(solid.shape, lbm_inputs.velocity_noise(solid.shape, 1e-3, seed=4))
+    f0 = oracle.init_equilibrium(ru, solid)
+    bc = {1: ("velocity", 1.0, (0.05, 0, 0)), 2: ("pressure", 1.1, (0, 0, 0)),
+          3: ("velocity", 0.9, (0, 0.02, 0)), 4: ("pressure", 1.0, (0.01, 0, 0))}
+    want = oracle.run_ts(f0, solid, 7, 1.3, (1e-5, 0, 0))
+    got = oracle.run_ts(f0, m, 7, 1.3, (1e-5, 0, 0), bc=bc)
+    assert np.array_equal(got, want)

@@ -21,18 +21,23 @@ class FakeClock:
 
 
 class FakeExecutor:
-    """Request r 'converges' after s_r steps: its mean velocity ramps linearly, then stays flat."""
+    """Request r 'converges' after s_r steps: its mean velocity ramps linearly, then stays flat.
+    A request whose seed is in `poison` returns non-finite moments (a diverged lattice)."""
 
-    def __init__(self, clock, cost_per_step=1e-5, slots=8):
+    def __init__(self, clock, cost_per_step=1e-5, slots=8, poison=()):
         self.clock = clock
         self.cost = cost_per_step
-        self.free = list(range(slots))
+        self.slots = slots
+        self.poison = set(poison)
         self.active = {}
+        self.joining = {}
         self.t = {}
         self.used = 0
         self.max_used = 0
         self.max_active = 0
         self.events = []
+        self.busy_seconds = 0.0
+        self.k = 0
 
     def prepare(self, req):
         req.n_fluid = 1000 * (1 + req.seed % 5)
@@ -41,36 +46,42 @@ class FakeExecutor:
         return 10 * req.n_fluid
 
     def admit(self, req):
-        slot = self.free.pop(0)
-        self.active[slot] = req
-        self.t[slot] = 0
+        assert len(self.active) + len(self.joining) < self.slots
+        self.joining[req.rid] = req
+        self.t[req.rid] = 0
         self.used += req.footprint
         self.max_used = max(self.max_used, self.used)
-        self.max_active = max(self.max_active, len(self.active))
+        self.max_active = max(self.max_active, len(self.active) + len(self.joining))
         self.events.append(("admit", req.rid, self.clock()))
-        return slot
 
-    def run(self, k):
-        self.clock.t += self.cost * k * len(self.active)
+    def start(self, k):
+        self.active.update(self.joining)
+        self.joining = {}
+        self.k = k
+
+    def finish(self):
+        dt = self.cost * self.k * len(self.active)
+        self.clock.t += dt
+        self.busy_seconds += dt
         out = {}
-        for slot, req in self.active.items():
-            self.t[slot] += k
+        for rid, req in self.active.items():
+            self.t[rid] += self.k
             s = req.params["conv_steps"]
-            U = 1e-3 * min(self.t[slot], s) / s
-            out[slot] = np.array([1.0, U - 0.5 * G, 0.0, 0.0])
+            U = 1e-3 * min(self.t[rid], s) / s
+            out[rid] = np.array([1.0, U - 0.5 * G, 0.0, 0.0])
+            if req.seed in self.poison and self.t[rid] >= 300:
+                out[rid] = np.array([np.nan, np.nan, 0.0, 0.0])
         return out
 
     def release(self, req):
-        del self.active[req.slot]
-        self.free.append(req.slot)
-        self.free.sort()
+        del self.active[req.rid]
         self.used -= req.footprint
         self.events.append(("release", req.rid, self.clock()))
 
 
-def _serve(n=40, rate=50.0, budget=60000, slots=8, **kw):
+def _serve(n=40, rate=50.0, budget=60000, slots=8, poison=(), **kw):
     clock = FakeClock()
-    ex = FakeExecutor(clock, slots=slots)
+    ex = FakeExecutor(clock, slots=slots, poison=poison)
     sch = Scheduler(ex, hbm_budget=budget, max_slots=slots, k_steps=100, tol=1e-6, prep_threads=0, clock=clock,
                     sleep=clock.sleep, g=G, **kw)
     arr = poisson_arrivals(n, rate, seed=1)
@@ -82,11 +93,11 @@ def _serve(n=40, rate=50.0, budget=60000, slots=8, **kw):
 def test_every_request_served_and_converged():
     sch, ex, out = _serve()
     assert all(r.finished is not None for r in out)
-    assert all(r.converged for r in out)
+    assert all(r.converged and r.status == "converged" for r in out)
     for r in out:
         s = r.params["conv_steps"]
-        # flat after s steps; detected at the first K boundary with two equal readings
-        assert r.steps == (math.ceil(s / 100) + 1) * 100
+        # flat from the first K boundary at or after s steps; steady after three unchanged windows
+        assert r.steps == (math.ceil(s / 100) + 3) * 100
         assert abs(r.velocity - 1e-3) < 1e-15
 
 
@@ -121,16 +132,35 @@ def test_oversized_request_fails_without_blocking():
     out = sch.serve(reqs)
     big = [r for r in out if r.rid == 0][0]
     small = [r for r in out if r.rid == 1][0]
-    assert big.finished is not None and not big.converged and big.steps == 0
+    assert big.finished is not None and not big.converged and big.steps == 0 and big.status == "oversize"
     assert small.converged
+    rep = sch.report(out)
+    assert rep["oversize"] == 1 and rep["converged"] == 1
 
 
 def test_max_steps_cap():
     sch, ex, out = _serve(n=5, max_steps=300)
     for r in out:
         assert r.steps <= 300
-        if r.params["conv_steps"] >= 300:
-            assert not r.converged
+        if r.params["conv_steps"] >= 200:
+            assert not r.converged and r.status == "cap"
+
+
+def test_diverged_request_fails_alone():
+    """A lattice whose moments turn non-finite is retired as diverged; every other request converges
+    as it would without it."""
+    _, _, ref = _serve(n=12, rate=100.0)
+    sch, ex, out = _serve(n=12, rate=100.0, poison=(103, 107))
+    by_rid = {r.rid: r for r in ref}
+    for r in out:
+        if r.seed in (103, 107):
+            assert r.status == "diverged" and not r.converged and r.steps == 300
+        else:
+            assert r.status == "converged" and r.steps == by_rid[r.rid].steps
+            assert r.velocity == by_rid[r.rid].velocity
+    rep = sch.report(out)
+    assert rep["diverged"] == 2 and rep["converged"] == 10
+    assert ex.used == 0 and not ex.active
 
 
 def test_report_percentiles():
@@ -141,7 +171,29 @@ def test_report_percentiles():
     assert rep["p50_latency_s"] == pytest.approx(np.percentile(lat, 50))
     assert rep["p99_latency_s"] == pytest.approx(np.percentile(lat, 99))
     assert rep["p99_latency_s"] >= rep["p50_latency_s"] > 0
+    assert rep["p50_latency_steady_s"] == pytest.approx(rep["p50_latency_s"])
     assert 0 < rep["gpu_busy_frac"] <= 1
+    rep = sch.report(out, bytes_per_lup=188.0)
+    assert rep["frac_hbm"] == pytest.approx(sch.lups * 188.0 / ex.busy_seconds / 1e9 / 8000.0)
+
+
+def test_steady_monitor_tells_noise_from_approach():
+    """A geometric approach with one overshoot converges (three small windows); a level with
+    alternating rounding noise above tol is a noise floor; a NaN is a divergence."""
+    from paper_1111_0922_amd.steady import SteadyMonitor
+    m = SteadyMonitor(1e-7)
+    u = [1.0 - 0.5 ** j * (1.0 if j < 6 else -0.3) for j in range(1, 60)]
+    st = [m.push(x) for x in u]
+    first = st.index("converged")
+    assert "noise_floor" not in st[:first]
+    assert all(abs(u[first - j] - u[first - j - 1]) < 1e-7 * u[first] for j in range(3))
+    m = SteadyMonitor(1e-7)
+    rng = np.random.default_rng(0)
+    st = [m.push(1.0 + 5e-7 * rng.standard_normal()) for _ in range(40)]
+    assert "noise_floor" in st and "converged" not in st[:st.index("noise_floor")]
+    assert m.noise > 1e-7 and m.trend < 1e-7
+    m = SteadyMonitor(1e-7)
+    assert m.push(1.0) == "running" and m.push(float("nan")) == "diverged"
 
 
 def test_mean_velocity_and_arrivals():
