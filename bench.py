@@ -40,7 +40,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "MFLUP/s D3Q19 AA (fp64/fp32, %HBM roofline); served solves/s + p99 latency"
-KERNEL_SOURCES = ["kernels.hpp", "collide.hpp", "storage.hpp", "d3q19.hpp"]
+# the kernels and their launch policy (block order, residency, kernel family: api.hip; batched
+# launches: batch.hip): a change to any of them makes the committed counter summaries stale
+KERNEL_SOURCES = ["kernels.hpp", "collide.hpp", "storage.hpp", "d3q19.hpp", "api.hip", "batch.hip"]
 
 
 def kernel_hash() -> str:
@@ -78,7 +80,8 @@ def measured_traffic(kernel: str, workload: str):
 
 def channel_grid(P, torch, n, scheme, layout, precision="f64"):
     import lbm_inputs
-    grid = P.Grid(n, n, n, layout=layout, precision=precision, wall_z=True, omega=1.6, g=(1e-6, 0.0, 0.0))
+    grid = P.Grid(n, n, n, layout=layout, precision=precision, wall_z=True, omega=1.6, g=(1e-6, 0.0, 0.0),
+                  f16_scale=1024.0)
     grid.bind(scheme)
     nf = grid.n_nodes
     u = torch.from_numpy(lbm_inputs.velocity_noise((n - 2, n, n), 1e-3, seed=1).reshape(3, -1))
@@ -97,24 +100,15 @@ def time_steps(torch, grid, steps, warmup):
     return time.perf_counter() - t0
 
 
-def time_steps_collider(torch, grid, steps, warmup, collider):
-    grid.step(warmup, collider=collider)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    grid.step(steps, collider=collider)
-    torch.cuda.synchronize()
-    return time.perf_counter() - t0
-
-
-def per_launch_ms(torch, grid, launches):
-    """Average duration of single-step launches measured with events on the launch stream."""
+def per_launch_ms(torch, grid, launches, collider="bgk"):
+    """Average duration of single steps by parity, measured with events on the launch stream."""
     stream = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * launches)]
     per_kind = {0: [], 1: []}
     for k in range(launches):
         parity = grid.t & 1
         ev[2 * k].record(stream)
-        grid.step(1)
+        grid.step(1, collider=collider)
         ev[2 * k + 1].record(stream)
         per_kind[parity].append(k)
     torch.cuda.synchronize()
@@ -123,6 +117,116 @@ def per_launch_ms(torch, grid, launches):
         if ks:
             out[parity] = float(np.mean([ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in ks]))
     return out
+
+
+# kernels one step launches, by step parity (the two-step scheme's collision and propagation
+# kernels are timed together as one step)
+STEP_KERNELS = {"ts": ("ts_step", "ts_step"), "os_push": ("os_push", "os_push"), "os_pull": ("os_pull", "os_pull"),
+                "aa": ("aa_even", "aa_odd"), "et": ("et_even", "et_odd")}
+PDF_SIZE = {"f64": 8, "f32": 4, "f16s": 2, "f32s": 4}
+IDX_BYTES = {"ts_step": 72, "os_push": 72, "os_pull": 72, "aa_even": 0, "aa_odd": 72, "et_even": 28, "et_odd": 28}
+
+
+def kernel_bytes(name, addressing, precision, nodes):
+    """Algorithmic HBM bytes of one launch (one step for ts_step): each PDF read and written once,
+    no write-allocate, plus the IDX or esoteric-twist table entries an indirect kernel reads."""
+    pdf = 2 * 19 * PDF_SIZE[precision] * (2 if name == "ts_step" else 1)
+    return (pdf + (IDX_BYTES[name] if addressing == "indirect" else 0)) * nodes
+
+
+def counter_table(workload):
+    """{label: HBM bytes per launch} from profiles/counters_<workload>.md while its kernel hash is current."""
+    path = os.path.join(ROOT, "profiles", f"counters_{workload}.md")
+    if not os.path.exists(path):
+        return {}
+    rows, current = {}, False
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("kernel_source_hash:"):
+                current = line.split(":", 1)[1].strip() == kernel_hash()
+            cells = [c.strip() for c in line.strip().strip("|").split("|")]
+            if len(cells) >= 8 and "/" in cells[0]:
+                try:
+                    rows[cells[0]] = float(cells[5])
+                except ValueError:
+                    pass
+    return rows if current else {}
+
+
+def measure_row(P, torch, grid, scheme, addressing, precision, workload, steps=100, warmup=10, launches=40,
+                collider="bgk", counters=None, layout="soa"):
+    """Wall-clock MFLUP/s over `steps` steps, and every kernel's event-timed launch duration, achieved
+    GB/s of its algorithmic bytes and fraction of the HBM peak (plus the counters' bytes if current)."""
+    nodes = grid.n_nodes
+    grid.step(warmup, collider=collider)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    grid.step(steps, collider=collider)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    mf = nodes * steps / dt / 1e6
+    bl = P.model_bytes(scheme, addressing, precision)
+    row = {"MFLUP/s": round(mf, 1), "bytes_per_lup": bl, "GB/s": round(mf * bl / 1e3, 1),
+           "frac_hbm_wall": round(mf * bl / 1e3 / HBM_PEAK_GBS, 4), "kernels": {}}
+    ms = per_launch_ms(torch, grid, launches, collider)
+    fr = []
+    for parity, t in ms.items():
+        name = STEP_KERNELS[scheme][parity]
+        if name in row["kernels"]:
+            continue
+        t = float(np.mean([ms[p] for p in ms if STEP_KERNELS[scheme][p] == name]))
+        b = kernel_bytes(name, addressing, precision, nodes)
+        k = {"ms": round(t, 4), "algorithmic_bytes": int(b), "GB/s": round(b / (t * 1e-3) / 1e9, 1),
+             "frac_hbm": round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        label = f"{workload}/{scheme}/{layout}/{precision}/{name}"
+        if counters and label in counters:
+            k["traffic"] = counters[label]
+            k["traffic_over_algorithmic"] = round(counters[label] / b, 4)
+        row["kernels"][name] = k
+        fr.append(k["frac_hbm"])
+    row["frac_hbm"] = min(fr)  # the slowest kernel's event-timed fraction
+    return row
+
+
+def pack_grid(P, torch, mask_t, scheme, n=512, precision="f64", omega=1.6):
+    """The sphere pack on an indirect SoA grid bound to `scheme`, rest start."""
+    g = P.Grid(n, n, n, addressing="indirect", precision=precision, omega=omega, g=(1e-6, 0, 0),
+               et_ghosts=(scheme == "et"))
+    g.build_idx(mask_t)
+    g.cellmap = None
+    g._mask = None
+    g.bind(scheme)
+    g.init_equilibrium()
+    return g
+
+
+CHANNEL_SET = [(sc, lay, "f64") for lay in ("soa", "aos") for sc in ("ts", "os_push", "os_pull", "aa", "et")] + \
+              [("aa", "soa", p) for p in ("f32", "f32s", "f16s")]
+PACK_SET = [(sc, "soa", "f64") for sc in ("ts", "os_push", "os_pull", "aa", "et")]
+
+
+def profile_set(P, torch, which, steps, warmup, log):
+    """Every kernel of one workload for a profiler: `warmup` + `steps` steps per configuration."""
+    if which == "channel":
+        for scheme, layout, prec in CHANNEL_SET:
+            g = channel_grid(P, torch, 256, scheme, layout, prec)
+            dt = time_steps(torch, g, steps, warmup)
+            print(json.dumps({"profile": f"channel256/{scheme}/{layout}/{prec}", "steps": steps,
+                              "MFLUP/s": round(g.n_nodes * steps / dt / 1e6, 1)}), flush=True)
+            del g
+            torch.cuda.empty_cache()
+    else:
+        import lbm_inputs
+        mask, _ = lbm_inputs.sphere_pack(512, 8, 0.40, seed=3)
+        mask_t = torch.from_numpy(mask).cuda()
+        del mask
+        for scheme, layout, prec in PACK_SET:
+            g = pack_grid(P, torch, mask_t, scheme)
+            dt = time_steps(torch, g, steps, warmup)
+            print(json.dumps({"profile": f"pack512/{scheme}/{layout}/{prec}", "steps": steps, "nodes": g.n_nodes,
+                              "MFLUP/s": round(g.n_nodes * steps / dt / 1e6, 1)}), flush=True)
+            del g
+            torch.cuda.empty_cache()
 
 
 def bench_copy(P, torch, nbytes=4 << 30, reps=10):
@@ -338,6 +442,9 @@ def main():
                     help="only the AA 256^3 channel run in this storage (for profiling)")
     ap.add_argument("--profile-porous", action="store_true",
                     help="only AA FP64 on the 512^3 sphere pack, indirect addressing (for profiling)")
+    ap.add_argument("--profile-set", choices=["channel", "pack"], default=None,
+                    help="only every kernel of the 256^3 channel (10 scheme x layout, AA FP32/F32S/FP16S) or of "
+                         "the 512^3 pack (5 schemes), --warmup + --steps steps each (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the copy kernel on 1 GiB, 3 times (counter calibration)")
     args = ap.parse_args()
@@ -384,6 +491,9 @@ def main():
     if args.precision_study:
         print(json.dumps({"precision_study": precision_study(log)}), flush=True)
         return
+    if args.profile_set:
+        profile_set(P, torch, args.profile_set, args.steps, args.warmup, log)
+        return
 
     n = 256
     log(f"[bench] AA SoA FP64 256^3 channel: warmup {args.warmup}, steps {args.steps}")
@@ -427,42 +537,23 @@ def main():
     if not args.only_main:
         log("[bench] copy calibration")
         result["copy"] = {"GB/s": round(bench_copy(P, torch), 1)}
-        log("[bench] scheme x layout table, 256^3 channel FP64")
+        log("[bench] scheme x layout table, 256^3 channel (FP64; AA also FP32, F32S, FP16S)")
         table = {}
-        for layout in ("soa", "aos"):
-            for scheme in ("ts", "os_push", "os_pull", "aa", "et"):
-                g = channel_grid(P, torch, n, scheme, layout)
-                steps = 100
-                dts = time_steps(torch, g, steps, 10)
-                mf = g.n_nodes * steps / dts / 1e6
-                bl = P.model_bytes(scheme, "direct", "f64")
-                table[f"{scheme}/{layout}"] = {"MFLUP/s": round(mf, 1), "GB/s": round(mf * bl / 1e3, 1),
-                                               "bytes_per_lup": bl, "frac_hbm": round(mf * bl / 1e3 / HBM_PEAK_GBS, 4)}
-                del g
-                torch.cuda.empty_cache()
-                log(f"[bench]   {scheme}/{layout}: {mf:.0f} MFLUP/s")
-        for prec in ("f32", "f32s", "f16s"):
-            g = P.Grid(n, n, n, precision=prec, wall_z=True, omega=1.6, g=(1e-6, 0.0, 0.0), f16_scale=1024.0)
-            g.bind("aa")
-            g.init_equilibrium()
-            dts = time_steps(torch, g, 200, 10)
-            mf = g.n_nodes * 200 / dts / 1e6
-            bl = P.model_bytes("aa", "direct", prec)
-            table[f"aa/soa/{prec}"] = {"MFLUP/s": round(mf, 1), "GB/s": round(mf * bl / 1e3, 1), "bytes_per_lup": bl,
-                                       "frac_hbm": round(mf * bl / 1e3 / HBM_PEAK_GBS, 4)}
+        cc = counter_table("channel256")
+        for scheme, layout, prec in CHANNEL_SET:
+            g = channel_grid(P, torch, n, scheme, layout, prec)
+            key = f"{scheme}/{layout}" + ("" if prec == "f64" else f"/{prec}")
+            table[key] = measure_row(P, torch, g, scheme, "direct", prec, "channel256", counters=cc, layout=layout,
+                                     steps=100 if prec == "f64" else 200)
             del g
             torch.cuda.empty_cache()
-            log(f"[bench]   aa/soa/{prec}: {mf:.0f} MFLUP/s")
+            log(f"[bench]   {key}: {table[key]['MFLUP/s']:.0f} MFLUP/s, slowest kernel {table[key]['frac_hbm']:.3f} of HBM")
         # the paper's collision (TRT, Lambda = 3/16) on the same kernels
         g = channel_grid(P, torch, n, "aa", "soa")
-        dts = time_steps_collider(torch, g, 200, 10, "trt")
-        mf = g.n_nodes * 200 / dts / 1e6
-        bl = P.model_bytes("aa", "direct", "f64")
-        table["aa/soa/trt"] = {"MFLUP/s": round(mf, 1), "GB/s": round(mf * bl / 1e3, 1), "bytes_per_lup": bl,
-                               "frac_hbm": round(mf * bl / 1e3 / HBM_PEAK_GBS, 4)}
+        table["aa/soa/trt"] = measure_row(P, torch, g, "aa", "direct", "f64", "channel256", collider="trt", steps=200)
         del g
         torch.cuda.empty_cache()
-        log(f"[bench]   aa/soa/trt: {mf:.0f} MFLUP/s")
+        log(f"[bench]   aa/soa/trt: {table['aa/soa/trt']['MFLUP/s']:.0f} MFLUP/s")
         # open boundaries: 256^3 duct (indirect), velocity inlet x = 0, pressure outlet x = 255,
         # walls z = 0 and z = 255, periodic in y
         duct = np.zeros((n, n, n), np.uint8)
@@ -476,38 +567,28 @@ def main():
         g.set_boundary(2, "pressure", 1.0, (0.01, 0.0, 0.0))
         g.bind("aa")
         g.init_equilibrium()
-        dts = time_steps(torch, g, 200, 10)
-        mf = g.n_nodes * 200 / dts / 1e6
-        bl = P.model_bytes("aa", "indirect", "f64")
-        table["aa/indirect/duct_open_boundaries"] = {"MFLUP/s": round(mf, 1), "GB/s": round(mf * bl / 1e3, 1),
-                                                     "bytes_per_lup": bl,
-                                                     "frac_hbm": round(mf * bl / 1e3 / HBM_PEAK_GBS, 4)}
+        key = "aa/indirect/duct_open_boundaries"
+        table[key] = measure_row(P, torch, g, "aa", "indirect", "f64", "duct256", steps=200)
         del g, duct
         torch.cuda.empty_cache()
-        log(f"[bench]   aa/indirect/duct_open_boundaries: {mf:.0f} MFLUP/s")
+        log(f"[bench]   {key}: {table[key]['MFLUP/s']:.0f} MFLUP/s")
         result["schemes"] = table
 
-        log("[bench] 512^3 sphere pack (r 8, porosity 0.40), indirect, FP64")
+        log("[bench] 512^3 sphere pack (r 8, porosity 0.40), indirect, FP64, every scheme")
         import lbm_inputs
         mask, spheres = lbm_inputs.sphere_pack(512, 8, 0.40, seed=3)
         porous = {"spheres": spheres, "porosity": float(1 - mask.mean())}
         mask_t = torch.from_numpy(mask).cuda()
         del mask
-        for scheme in ("aa", "ts"):
-            g = P.Grid(512, 512, 512, addressing="indirect", omega=1.6, g=(1e-6, 0, 0))
-            nfp = g.build_idx(mask_t)
-            g.bind(scheme)
-            g.init_equilibrium()
-            steps = 100
-            dts = time_steps(torch, g, steps, 10)
-            mf = nfp * steps / dts / 1e6
-            bl = P.model_bytes(scheme, "indirect", "f64")
-            porous[scheme] = {"MFLUP/s": round(mf, 1), "GB/s": round(mf * bl / 1e3, 1), "bytes_per_lup": bl,
-                              "frac_hbm": round(mf * bl / 1e3 / HBM_PEAK_GBS, 4)}
-            porous["nodes"] = nfp
+        cp = counter_table("pack512")
+        for scheme, layout, prec in PACK_SET:
+            g = pack_grid(P, torch, mask_t, scheme)
+            porous["nodes"] = g.n_nodes
+            porous[scheme] = measure_row(P, torch, g, scheme, "indirect", prec, "pack512", counters=cp)
             del g
             torch.cuda.empty_cache()
-            log(f"[bench]   {scheme}: {mf:.0f} MFLUP/s")
+            log(f"[bench]   {scheme}: {porous[scheme]['MFLUP/s']:.0f} MFLUP/s, "
+                f"slowest kernel {porous[scheme]['frac_hbm']:.3f} of HBM")
         result["porous512"] = porous
         del mask_t
         torch.cuda.empty_cache()

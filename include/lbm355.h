@@ -120,7 +120,7 @@ typedef struct {
     int64_t idx_pitch;     /* entries between IDX rows                              */
     int64_t pdf_bytes;     /* one lattice for the queried scheme                    */
     int64_t pdf1_bytes;    /* second lattice (TS, OS push, OS pull) or 0           */
-    int64_t idx_bytes;     /* int32 IDX[18][idx_pitch] (indirect) or 0              */
+    int64_t idx_bytes;     /* int32 IDX[18][idx_pitch] and the block order (indirect) or 0 */
     int64_t aux_bytes;     /* int32 ET table [7][idx_pitch] (indirect ET) or 0      */
     int64_t scratch_bytes; /* moment-reduction partials                             */
     int64_t cellmap_bytes; /* int32 cellmap[n_cells] (indirect)                     */
@@ -219,6 +219,14 @@ int lbm_set_boundary(lbm_grid *g, int32_t cls, int32_t kind, double rho, const d
  *     keeps the natural order.  The default uses bands of 8 (FP64) or 16
  *     workgroups for AoS kernels that access neighbours, and the natural
  *     order otherwise.
+ *   LBM_OPT_SLAB_ORDER (-1 = default, 0 or 1): on an indirect grid, 1 runs
+ *     the update kernels that write to neighbours (AA odd step, one-step push,
+ *     esoteric twist) in the XCD slab order that lbm_build_idx stores after
+ *     the IDX rows: each XCD sweeps the node blocks whose first node lies in
+ *     its own eighth of the y range, plane after plane, so the neighbour rows
+ *     that share partly written cache lines run on one L2.  0 keeps the
+ *     natural order.  The default is 1 on SoA grids, 0 on AoS grids.  A table
+ *     set with lbm_set_block_order takes precedence.
  * Errors: LBM_E_ARG for an unknown option or a value out of range. */
 enum {
     LBM_OPT_XCD_REMAP = 1,
@@ -226,7 +234,8 @@ enum {
     LBM_OPT_WG_LDS = 3,
     LBM_OPT_ROW_STAGE = 4,
     LBM_OPT_PAIR = 5,
-    LBM_OPT_BAND = 6
+    LBM_OPT_BAND = 6,
+    LBM_OPT_SLAB_ORDER = 7
 };
 int lbm_set_option(lbm_grid *g, int32_t option, int64_t value);
 
@@ -271,7 +280,10 @@ int lbm_query_sizes(const lbm_grid *g, int32_t scheme, lbm_sizes *out);
  *      receives the six storage addresses the esoteric twist reads at
  *      x + (1,0,0), (0,1,0), (0,0,1), (1,1,0), (1,0,1), (0,1,1) (fluid id, or
  *      N_f + ghost number for a solid cell) and, in row 6, a bit mask whose
- *      bit i-1 is set when x + c_i is solid.  Asynchronous.
+ *      bit i-1 is set when x + c_i is solid.  When d_scratch is given, the
+ *      ceil(N_f / 256) entries after the 18 IDX rows (idx_bytes covers them)
+ *      receive the XCD slab block order (LBM_OPT_SLAB_ORDER); with d_scratch
+ *      NULL they are left alone and the natural order is used.  Asynchronous.
  * d_scratch: build_scratch_bytes of device memory.  Errors: LBM_E_STATE on a
  * direct grid or when call 2 precedes call 1. */
 int lbm_build_idx(lbm_grid *g, const uint8_t *d_mask, int32_t *d_cellmap, int32_t *d_idx,

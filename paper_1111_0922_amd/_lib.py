@@ -27,6 +27,7 @@ OPT_WG_LDS = 3
 OPT_ROW_STAGE = 4
 OPT_PAIR = 5
 OPT_BAND = 6
+OPT_SLAB_ORDER = 7
 NOALLOC_MAX_NODES = 1 << 26   # LBM_NOALLOC_MAX_NODES
 
 SCHEMES = {"ts": TS, "os_push": OS_PUSH, "os_pull": OS_PULL, "aa": AA, "et": ET,

@@ -55,6 +55,12 @@ bool kernel_scheme(int scheme) { return scheme >= LBM_TS && scheme <= LBM_ET; }
 
 namespace {
 
+// byte offset of the slab keys in the build scratch (after the chunk counts and offsets)
+int64_t order_key_offset(int64_t chunk_blocks)
+{
+    return round_up(round_up(chunk_blocks * 2 * 4, 256) + (2 * chunk_blocks + 2) * 8, 256);
+}
+
 int64_t storage_nodes(const lbm_grid *g, int scheme)
 {
     if (g->d.addressing == LBM_DIRECT) return g->n_cells;
@@ -99,6 +105,22 @@ void set_block_order(const lbm_grid *g, KArgs &a, int kind)
         if (g->order && g->order_n == (int64_t)update_blocks(g, a)) {
             a.remap = 3;
             a.order = g->order;
+            return;
+        }
+        // XCD slab order (built with the index) for the kernels that write to
+        // neighbours: their partly written lines then collect in one L2 before they
+        // leave it.  Measured per launch on the 512^3 pack, FP64: AA odd 4.49 ->
+        // 4.24 ms (FP32 2.75 -> 2.50), one-step push 6.72 -> 5.25, esoteric twist
+        // 6.10 -> 4.97.  Kernels that only gather from neighbours gain nothing
+        // (one-step pull 3.83-4.00 -> 3.88, two-step 6.64 -> 6.66 per step), and
+        // node-local ones lose (AA even 2.77 -> 3.06 / 1.38 -> 1.57): their natural
+        // order keeps the blocks of all XCDs in the same memory pages.
+        const int W = wmap_of(kind);
+        const bool writes_neighbours = W == W_PUSH || W == W_ET0 || W == W_ET1;
+        const int slab = g->slab >= 0 ? g->slab : (g->d.layout == LBM_SOA ? 1 : 0);
+        if (slab && writes_neighbours && g->slab_table) {
+            a.remap = 3;
+            a.order = g->slab_table;
         }
         return;
     }
@@ -353,6 +375,11 @@ int lbm_set_option(lbm_grid *g, int32_t option, int64_t value)
         g->band = (int)value;
         return LBM_OK;
     }
+    if (option == LBM_OPT_SLAB_ORDER) {
+        if (value < -1 || value > 1) return fail(LBM_E_ARG, "slab order must be -1, 0 or 1");
+        g->slab = (int)value;
+        return LBM_OK;
+    }
     if (option == LBM_OPT_WG_LDS) {
         // at most 120 KB: with a kernel's own LDS (up to 40 KB) every
         // workgroup still fits the 160 KB of a CU
@@ -404,10 +431,12 @@ int lbm_query_sizes(const lbm_grid *g, int32_t scheme, lbm_sizes *out)
             nv *= (dims[k] + bk - 1) / bk * bk;
         }
         const int64_t nb = (nv + IDX_CELLS - 1) / IDX_CELLS;
-        out->build_scratch_bytes = round_up(nb * 2 * 4, 256) + (2 * nb + 2) * 8;
+        // chunk counts, 64-bit offsets, then the slab keys of at most ceil(n_cells / 256) node blocks
+        out->build_scratch_bytes = order_key_offset(nb) + round_up((g->n_cells + BLOCK - 1) / BLOCK * 4, 256);
         if (g->idx_phase == 0) return LBM_OK;
         out->idx_pitch = idx_pitch_of(g);
-        out->idx_bytes = 18 * out->idx_pitch * 4;
+        // the 18 IDX rows, then the XCD slab block order (one entry per node block)
+        out->idx_bytes = 18 * out->idx_pitch * 4 + round_up((int64_t)node_blocks(g) * 4, 256);
         if (scheme == LBM_ET) out->aux_bytes = 7 * out->idx_pitch * 4;
     }
     const int64_t ns = storage_nodes(g, scheme);
@@ -485,10 +514,17 @@ int lbm_build_idx(lbm_grid *g, const uint8_t *d_mask, int32_t *d_cellmap, int32_
     b.et_on = b.et ? 1 : 0;
     b.idx_pitch = idx_pitch_of(g);
     b.n_fluid = g->n_nodes;
+    // with the scratch, the block order of the neighbour-side kernels goes after the IDX rows
+    if (d_scratch && g->n_nodes > 0) {
+        b.order_key = reinterpret_cast<uint32_t *>(static_cast<char *>(d_scratch) + order_key_offset(b.n_blocks));
+        b.order = reinterpret_cast<uint32_t *>(d_idx + 18 * b.idx_pitch);
+        b.n_tiles = node_blocks(g);
+    }
     launch_idx_phase2(b, s);
     int rc = hip_check(hipGetLastError(), "index build (fill pass)");
     if (rc) return rc;
     g->idx_phase = 2;
+    g->order_built = b.order != nullptr;
     if (n_fluid_out) *n_fluid_out = g->n_nodes;
     return LBM_OK;
 }
@@ -514,6 +550,7 @@ int lbm_bind(lbm_grid *g, int32_t scheme, void *d_pdf0, void *d_pdf1, const int3
     g->pdf[1] = two_lattices(scheme) ? d_pdf1 : nullptr;
     g->cur = 0;
     g->idx = ind ? d_idx : nullptr;
+    g->slab_table = (ind && g->order_built) ? reinterpret_cast<const uint32_t *>(d_idx + 18 * idx_pitch_of(g)) : nullptr;
     g->aux = (ind && scheme == LBM_ET) ? d_aux : nullptr;
     g->scratch = static_cast<double *>(d_scratch);
     g->pitch = sz.pitch;

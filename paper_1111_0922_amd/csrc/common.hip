@@ -247,6 +247,8 @@ __global__ void __launch_bounds__(BLOCK) k_idx_fill(BuildArgs b)
     if (n < 0) return;
     int x, y, z;
     cell_xyz(b, c, x, y, z);
+    // XCD slab of a node block: the y-eighth of its first node's row
+    if (b.order_key && (n & (BLOCK - 1)) == 0) b.order_key[n / BLOCK] = (uint32_t)(((int64_t)y * 8) / b.ny);
     uint32_t mask = 0;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
@@ -268,6 +270,79 @@ __global__ void __launch_bounds__(BLOCK) k_idx_fill(BuildArgs b)
     }
 }
 
+// Block order from the slab keys (one workgroup).  Workgroup b runs on XCD
+// b mod 8 (round-robin dispatch), so the r-th block of slab k in node order
+// goes to workgroup 8 r + k while every slab still has an r-th block
+// (r < m, m the smallest slab's count); the blocks beyond follow in node
+// order from workgroup 8 m on.  Each XCD then sweeps its own y-eighth of
+// every z-plane, plane after plane, and all XCDs stay in the same planes: the
+// rows a block's odd-step gathers and scatters share cache lines with (y +-
+// 1 and z +- 1) mostly run on the same XCD, in its L2.  A permutation of
+// [0, n_tiles).
+constexpr int ORDER_THREADS = 1024;
+
+__device__ __forceinline__ void block_excl_scan_lds(uint32_t (&v)[9], uint32_t (&tot)[9])
+{
+    __shared__ uint32_t sv[9][ORDER_THREADS];
+    const uint32_t t = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) sv[k][t] = v[k];
+    __syncthreads();
+    for (uint32_t off = 1; off < ORDER_THREADS; off <<= 1) {
+        uint32_t a[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) a[k] = t >= off ? sv[k][t - off] : 0u;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 9; ++k) sv[k][t] += a[k];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        tot[k] = sv[k][ORDER_THREADS - 1];
+        v[k] = sv[k][t] - v[k];
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(ORDER_THREADS) k_order_build(BuildArgs b)
+{
+    const uint32_t T = b.n_tiles;
+    const uint32_t chunk = (T + ORDER_THREADS - 1) / ORDER_THREADS;
+    const uint32_t lo = min(threadIdx.x * chunk, T), hi = min(lo + chunk, T);
+    uint32_t cnt[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, tot[9];
+    for (uint32_t t = lo; t < hi; ++t) ++cnt[min(b.order_key[t], 7u)];
+    block_excl_scan_lds(cnt, tot); // cnt: this thread's first rank in each slab
+    uint32_t m = tot[0];
+#pragma unroll
+    for (int k = 1; k < 8; ++k) m = min(m, tot[k]);
+    uint32_t r[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) r[k] = cnt[k];
+    uint32_t left[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (uint32_t t = lo; t < hi; ++t) {
+        const uint32_t k = min(b.order_key[t], 7u);
+        uint32_t rank = 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (q == (int)k) rank = r[q]++;
+        if (rank >= m) ++left[8];
+    }
+    block_excl_scan_lds(left, tot); // left[8]: this thread's first index among the blocks beyond 8 m
+    uint32_t li = left[8];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) r[k] = cnt[k];
+    for (uint32_t t = lo; t < hi; ++t) {
+        const uint32_t k = min(b.order_key[t], 7u);
+        uint32_t rank = 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (q == (int)k) rank = r[q]++;
+        const uint32_t wg = rank < m ? rank * 8u + k : 8u * m + li++;
+        b.order[wg] = t;
+    }
+}
+
 void launch_idx_phase1(const BuildArgs &b, hipStream_t s)
 {
     hipLaunchKernelGGL(k_idx_count, dim3(b.n_blocks), dim3(BLOCK), 0, s, b);
@@ -279,6 +354,8 @@ void launch_idx_phase2(const BuildArgs &b, hipStream_t s)
 {
     const uint32_t blocks = (b.n_cells + BLOCK - 1) / BLOCK;
     hipLaunchKernelGGL(k_idx_fill, dim3(blocks), dim3(BLOCK), 0, s, b);
+    if (b.order_key && b.order && b.n_tiles > 0)
+        hipLaunchKernelGGL(k_order_build, dim3(1), dim3(ORDER_THREADS), 0, s, b);
 }
 
 } // namespace lbm

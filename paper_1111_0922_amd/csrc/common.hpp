@@ -29,6 +29,11 @@ struct BuildArgs {
     int64_t idx_pitch;
     int64_t n_fluid;
     int32_t et_on;
+    // XCD slab order of the node blocks (phase 2, when both are set): slab key of
+    // each block's first node, then the block order built from the keys
+    uint32_t *order_key;  // [n_tiles] scratch
+    uint32_t *order;      // [n_tiles] after the 18 IDX rows
+    uint32_t n_tiles;     // ceil(n_fluid / BLOCK)
 };
 
 void launch_idx_phase1(const BuildArgs &b, hipStream_t s);

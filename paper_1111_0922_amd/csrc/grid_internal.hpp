@@ -32,6 +32,9 @@ struct lbm_grid {
     int band = -1;         // XCD band height (blocks) of the direct-grid block order, 0 = off, -1 = default
     const uint32_t *order = nullptr; // indirect grids: caller's block-order table (lbm_set_block_order)
     int64_t order_n = 0;
+    bool order_built = false;             // lbm_build_idx wrote the XCD slab order after the IDX rows
+    const uint32_t *slab_table = nullptr; // that table in the bound IDX buffer
+    int slab = -1;                        // LBM_OPT_SLAB_ORDER: 1 on, 0 off, -1 default (SoA on)
     // open-boundary classes 1..4 (indirect grids): kind, density, velocity
     int bc_kind[4] = {0, 0, 0, 0};
     double bc_rho[4] = {1.0, 1.0, 1.0, 1.0};

@@ -95,11 +95,13 @@ def test_option_ranges_without_gpu():
     L = P._lib
     g = P.Grid(64, 8, 8, wall_z=True)
     ok = [(L.OPT_WG_LDS, -1), (L.OPT_WG_LDS, 0), (L.OPT_WG_LDS, 122880), (L.OPT_PAIR, -1), (L.OPT_PAIR, 1),
-          (L.OPT_BAND, -1), (L.OPT_BAND, 4096), (L.OPT_ROW_STAGE, 0), (L.OPT_ROW_STAGE, 1)]
+          (L.OPT_BAND, -1), (L.OPT_BAND, 4096), (L.OPT_ROW_STAGE, 0), (L.OPT_ROW_STAGE, 1),
+          (L.OPT_SLAB_ORDER, -1), (L.OPT_SLAB_ORDER, 0), (L.OPT_SLAB_ORDER, 1)]
     for opt, val in ok:
         g.set_option(opt, val)
     bad = [(L.OPT_WG_LDS, -2), (L.OPT_WG_LDS, 122881), (L.OPT_PAIR, 2), (L.OPT_PAIR, -2), (L.OPT_BAND, -2),
-           (L.OPT_BAND, 4097), (L.OPT_PITCH_PAD, -1), (L.OPT_PITCH_PAD, (1 << 20) + 1), (99, 0)]
+           (L.OPT_BAND, 4097), (L.OPT_PITCH_PAD, -1), (L.OPT_PITCH_PAD, (1 << 20) + 1), (99, 0),
+           (L.OPT_SLAB_ORDER, 2), (L.OPT_SLAB_ORDER, -2)]
     for opt, val in bad:
         with pytest.raises(P.LbmError):
             g.set_option(opt, val)
