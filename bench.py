@@ -59,25 +59,6 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if still current."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.txt")
-    if not os.path.exists(path):
-        return None
-    vals = {}
-    with open(path) as fh:
-        for line in fh:
-            if ":" in line and not line.startswith("#"):
-                k, v = line.split(":", 1)
-                vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_hash") != kernel_hash():
-        return None
-    try:
-        return float(vals["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
-
-
 def channel_grid(P, torch, n, scheme, layout, precision="f64"):
     import lbm_inputs
     grid = P.Grid(n, n, n, layout=layout, precision=precision, wall_z=True, omega=1.6, g=(1e-6, 0.0, 0.0),
@@ -510,7 +491,7 @@ def main():
     kname = "aa_even" if dom == 0 else "aa_odd"
     bytes_per_launch = b_lup * nf
     achieved = bytes_per_launch / (launch[dom] * 1e-3) / 1e9
-    traffic = measured_traffic(kname, "256cube_f64_soa")
+    traffic = counter_table("channel256").get(f"channel256/aa/soa/f64/{kname}")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
                 "avg_launch_ms": {("aa_even" if k == 0 else "aa_odd"): round(v, 4) for k, v in launch.items()},

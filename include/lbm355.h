@@ -383,7 +383,12 @@ int lbm_reduce_moments_noalloc(lbm_grid *g, double *d_out4, void *stream);
  * lbm_step meanwhile.  Callers serialise calls on one batch. */
 typedef struct lbm_batch lbm_batch;
 
-/* Device workspace bytes for max_slots slots and max_tiles tiles in total.
+/* Device workspace bytes for max_slots slots and max_tiles tile entries in
+ * total.  A slot takes ceil(N_f / 256) tiles rounded up to a multiple of 8:
+ * its tiles start at a multiple of 8, so that its node blocks meet the 8 XCDs
+ * as in a single-lattice launch, and its AA odd steps run in the grid's XCD
+ * slab order (LBM_OPT_SLAB_ORDER; the order lbm_build_idx stored after the
+ * IDX rows, unless the option is 0 when the grid is added).
  * The batch calls have no paper passage: the serving executor is an addition
  * of this library, built on the AA pattern because it needs one lattice per
  * solve and independent node updates (Sec. 6 notes that this suits GPUs,

@@ -46,6 +46,7 @@ namespace lbm {
 struct SlotDesc {
     int64_t pdf_off;     // lattice and IDX: byte offsets from the workspace
     int64_t idx_off;
+    int64_t order_off;   // XCD slab block order of the grid (after its IDX rows), or NO_ORDER
     int64_t pitch;
     int64_t idx_pitch;
     double sigma;        // shifted-storage scale (canonical transfer of the moments)
@@ -66,6 +67,24 @@ struct SlotDesc {
 struct Tile {
     uint32_t slot, node0;
 };
+
+// A slot's tiles start at a multiple of 8 in the tile list, so that its r-th
+// block runs on XCD r mod 8 as in a single-lattice launch; the gaps hold
+// padding tiles, which update and reduce nothing.
+constexpr uint32_t PAD_SLOT = 0xFFFFFFFFu;
+constexpr int64_t NO_ORDER = -1;
+
+// Node block of a slot's tile in an odd step: the slot's XCD slab order (the
+// AA odd step writes to neighbours; see LBM_OPT_SLAB_ORDER), natural
+// otherwise.
+__device__ __forceinline__ uint32_t tile_node0(const SlotDesc &sd, const Tile &tl, bool odd, const char *base)
+{
+    if (odd && sd.order_off != NO_ORDER) {
+        const uint32_t *order = reinterpret_cast<const uint32_t *>(base + sd.order_off);
+        return order[tl.node0 / BLOCK] * BLOCK;
+    }
+    return tl.node0;
+}
 
 // A pointer read from device memory is a generic (flat) pointer to the
 // compiler, which then emits flat loads and stores (they wait on both the LDS
@@ -119,12 +138,14 @@ __global__ void __launch_bounds__(BLOCK) k_aa_batched(const SlotDesc *slots, con
     const uint32_t tile = blockIdx.x;
     if (tile >= hdr[0]) return;
     const Tile tl = tiles[tile];
+    if (tl.slot == PAD_SLOT) return;
     const SlotDesc sd = slots[tl.slot];
     const KArgs a = slot_args<PREC>(sd, base);
     slot_bc_table<PREC>(slots + tl.slot);
-    const uint32_t n = tl.node0 + threadIdx.x;
+    const bool odd = (sd.t0 + k) & 1;
+    const uint32_t n = tile_node0(sd, tl, odd, base) + threadIdx.x;
     if (n < sd.n_nodes) {
-        if ((sd.t0 + k) & 1)
+        if (odd)
             update_node<A_INDIRECT, L_SOA, PREC, K_AA_ODD, 1>(a, n);
         else
             update_node<A_INDIRECT, L_SOA, PREC, K_AA_EVEN, 1>(a, n);
@@ -182,15 +203,17 @@ __global__ void __launch_bounds__(BLOCK) k_aa_batched_coop(const SlotDesc *slots
     for (int32_t k = 0; k < k_steps; ++k) {
         for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
             const Tile tl = tiles[tile];
+            if (tl.slot == PAD_SLOT) continue;
             const SlotDesc sd = slots[tl.slot];
             const KArgs a = slot_args<PREC>(sd, base);
             if (sd.bc_on) {
                 __syncthreads(); // the previous tile's links have read the table
                 slot_bc_table<PREC>(slots + tl.slot);
             }
-            const uint32_t n = tl.node0 + threadIdx.x;
+            const bool odd = (sd.t0 + k) & 1;
+            const uint32_t n = tile_node0(sd, tl, odd, base) + threadIdx.x;
             if (n < sd.n_nodes) {
-                if ((sd.t0 + k) & 1)
+                if (odd)
                     update_node<A_INDIRECT, L_SOA, PREC, K_AA_ODD, 1>(a, n);
                 else
                     update_node<A_INDIRECT, L_SOA, PREC, K_AA_EVEN, 1>(a, n);
@@ -208,6 +231,7 @@ __global__ void __launch_bounds__(BLOCK) k_seg_partials(const SlotDesc *slots, c
     const uint32_t tile = blockIdx.x;
     if (tile >= hdr[0]) return;
     const Tile tl = tiles[tile];
+    if (tl.slot == PAD_SLOT) return; // no slot reads a padding tile's partial
     const SlotDesc sd = slots[tl.slot];
     const KArgs a = slot_args<PREC>(sd, base);
     const uint32_t n = tl.node0 + threadIdx.x;
@@ -442,20 +466,22 @@ int lbm_batch_add(lbm_batch *b, lbm_grid *g, int32_t *slot_out)
     int32_t free_slot = -1;
     for (int32_t s = 0; s < b->max_slots; ++s) {
         if (b->slots[s].active) {
-            used += b->slots[s].n_tiles;
+            used += (b->slots[s].n_tiles + 7) / 8 * 8;
             if (b->grids[s] == g) return fail(LBM_E_STATE, "grid already in the batch (slot %d)", s);
         } else if (free_slot < 0) {
             free_slot = s;
         }
     }
     if (free_slot < 0) return fail(LBM_E_STATE, "no free slot");
-    if (used + need > b->max_tiles) return fail(LBM_E_STATE, "tile list full (%lld + %lld > %lld)", (long long)used,
-                                                (long long)need, (long long)b->max_tiles);
+    if (used + (need + 7) / 8 * 8 > b->max_tiles)
+        return fail(LBM_E_STATE, "tile list full (%lld + %lld > %lld)", (long long)used, (long long)((need + 7) / 8 * 8),
+                    (long long)b->max_tiles);
     SlotDesc sd;
     std::memset(&sd, 0, sizeof sd);
     const KArgs a = base_args(g);
     sd.pdf_off = ws_offset(b, g->pdf[0]);
     sd.idx_off = ws_offset(b, g->idx);
+    sd.order_off = (g->slab_table && g->slab != 0) ? ws_offset(b, g->slab_table) : NO_ORDER;
     sd.pitch = a.pitch;
     sd.idx_pitch = a.idx_pitch;
     sd.sigma = a.sigma;
@@ -498,6 +524,7 @@ int lbm_batch_run(lbm_batch *b, int32_t k_steps, double *h_moments, int32_t use_
         for (int32_t sl = 0; sl < b->max_slots; ++sl) {
             SlotDesc &sd = b->slots[sl];
             if (!sd.active) continue;
+            while (b->tiles.size() % 8) b->tiles.push_back(Tile{PAD_SLOT, 0});
             sd.tile_begin = (uint32_t)b->tiles.size();
             for (uint32_t t = 0; t < sd.n_tiles; ++t) b->tiles.push_back(Tile{(uint32_t)sl, t * (uint32_t)BLOCK});
         }
