@@ -210,6 +210,58 @@ def profile_set(P, torch, which, steps, warmup, log):
             torch.cuda.empty_cache()
 
 
+def zband_column_order(grid, n, band=8):
+    """Block-order table for lbm_set_block_order on an n^3 lexicographic indirect grid: z-bands of
+    `band` planes, band k on XCD k mod 8, each XCD sweeping its bands column by column (y, then the
+    band's z), so that the rows z +- 1 of a block run right after it."""
+    import torch
+    cm = grid.cellmap[: n ** 3].cpu().numpy()
+    cells = np.flatnonzero(cm >= 0)
+    T = (len(cells) + 255) // 256
+    first = cells[::256][:T]
+    y0, z0 = (first // n) % n, first // (n * n)
+    tiles = np.arange(T)
+    xcd = (z0 // band) % 8
+    lists = [tiles[xcd == x][np.lexsort((tiles[xcd == x], z0[xcd == x], y0[xcd == x], (z0 // band)[xcd == x]))]
+             for x in range(8)]
+    m = min(len(lst) for lst in lists)
+    order = np.empty(T, np.int64)
+    for x in range(8):
+        order[x: 8 * m: 8] = lists[x][:m]
+    rest = np.sort(np.concatenate([lst[m:] for lst in lists]))
+    order[8 * m:] = rest
+    return torch.from_numpy(order.astype(np.int32)).cuda()
+
+
+PACK_ORDERS = [("lexicographic, natural order", None, 0, False), ("lexicographic, XCD slab order", None, -1, False),
+               ("lexicographic, z-band columns", None, 0, True), ("bands nx x 16 x nz, XCD slab order", (512, 16, 512), -1, False)]
+
+
+def profile_orders(P, torch, log, launches=4):
+    """AA FP64 on the 512^3 pack under the block orders and numberings of PACK_ORDERS, in that
+    sequence: `launches` even and odd steps each (for a counter pass), then event-timed launches."""
+    import lbm_inputs
+    mask, _ = lbm_inputs.sphere_pack(512, 8, 0.40, seed=3)
+    mask_t = torch.from_numpy(mask).cuda()
+    del mask
+    for name, brick, slab, columns in PACK_ORDERS:
+        g = P.Grid(512, 512, 512, addressing="indirect", omega=1.6, g=(1e-6, 0, 0), brick=brick)
+        g.build_idx(mask_t)
+        g.set_option(P._lib.OPT_SLAB_ORDER, slab)
+        if columns:
+            g.set_block_order(zband_column_order(g, 512))
+        g.cellmap = None
+        g._mask = None
+        g.bind("aa")
+        g.init_equilibrium()
+        g.step(2 * launches)
+        ms = per_launch_ms(torch, g, 20)
+        print(json.dumps({"profile_order": name, "aa_even_ms": round(ms[0], 4), "aa_odd_ms": round(ms[1], 4)}),
+              flush=True)
+        del g
+        torch.cuda.empty_cache()
+
+
 def bench_copy(P, torch, nbytes=4 << 30, reps=10):
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
@@ -426,6 +478,8 @@ def main():
     ap.add_argument("--profile-set", choices=["channel", "pack"], default=None,
                     help="only every kernel of the 256^3 channel (10 scheme x layout, AA FP32/F32S/FP16S) or of "
                          "the 512^3 pack (5 schemes), --warmup + --steps steps each (for profiling)")
+    ap.add_argument("--profile-orders", action="store_true",
+                    help="only AA FP64 on the 512^3 pack under several block orders and numberings (profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the copy kernel on 1 GiB, 3 times (counter calibration)")
     args = ap.parse_args()
@@ -474,6 +528,9 @@ def main():
         return
     if args.profile_set:
         profile_set(P, torch, args.profile_set, args.steps, args.warmup, log)
+        return
+    if args.profile_orders:
+        profile_orders(P, torch, log)
         return
 
     n = 256
