@@ -350,19 +350,21 @@ def cpu_baseline():
             "configs": out, "cpu": cpu_info()}
 
 
-def serving_bench(log, n_requests, n_light=100, seed_base=100000):
+def serving_bench(log, n_requests, n_light=100, n_shifted=300, seed_base=100000):
     """Porous permeability solves of uneven sizes (FP32 AA indirect), continuous batching.
 
     Three runs: all `n_requests` at t = 0 (saturated), then Poisson arrivals at 0.9x and 0.5x of the
     saturated rate (`n_requests` and `n_light` requests).  The first tenth of each run's requests,
-    by arrival, is warm-up and left out of the figures.
+    by arrival, is warm-up and left out of the figures.  A fourth run serves the first `n_shifted`
+    of the same requests saturated in FP32 words holding the deviation f - w (F32S: the same bytes
+    per update, far less rounding), whose flows reach the steady state in fewer steps.
     """
     import paper_1111_0922_amd as P
     from paper_1111_0922_amd.serve import GpuExecutor, Request, Scheduler, poisson_arrivals
     bl = P.model_bytes("aa", "indirect", "f32")
 
-    def run(rate, seed0, n):
-        ex = GpuExecutor(max_slots=64, max_tiles=1 << 20, precision="f32", omega=1.0, g=1e-6)
+    def run(rate, seed0, n, precision="f32"):
+        ex = GpuExecutor(max_slots=64, max_tiles=1 << 20, precision=precision, omega=1.0, g=1e-6)
         sch = Scheduler(ex, hbm_budget=64 << 30, max_slots=64, k_steps=100, tol=1e-6, max_steps=20000,
                         omega=1.0, g=1e-6, prep_threads=8)
         arr = poisson_arrivals(n, rate, seed=seed0)
@@ -374,6 +376,8 @@ def serving_bench(log, n_requests, n_light=100, seed_base=100000):
         rep["warmup_discarded"] = n // 10
         rep["steps_mean"] = float(np.mean([r.steps for r in out]))
         rep["makespan_s"] = sch.makespan
+        rep["storage"] = precision
+        rep["permeability"] = {r.seed: r.permeability for r in out}
         log(f"[bench]   {rep['requests']} measured requests, {rep['solves_per_s']:.2f} solves/s, "
             f"p50 {rep['p50_latency_s']:.2f} s, p99 {rep['p99_latency_s']:.2f} s, "
             f"{rep['mflups']:.0f} MFLUP/s, busy {rep['gpu_busy_frac']:.3f}")
@@ -386,6 +390,16 @@ def serving_bench(log, n_requests, n_light=100, seed_base=100000):
         lam = frac * sat["solves_per_s"]
         log(f"[bench] serving: Poisson rate {lam:.2f}/s ({frac} x saturated), {n} requests")
         out[f"poisson_{frac}"] = run(lam, seed_base + 1000 * int(frac * 10), n)
+    if n_shifted > 0:
+        log(f"[bench] serving: saturated, FP32 shifted storage ({n_shifted} requests at t=0)")
+        out["saturated_f32s"] = run(float("inf"), seed_base, n_shifted, "f32s")
+        # the same requests' permeabilities in the two storages
+        k32, k32s = out["saturated"]["permeability"], out["saturated_f32s"]["permeability"]
+        d = np.array([abs(k32[s_] - k32s[s_]) / abs(k32s[s_]) for s_ in k32s if s_ in k32])
+        out["saturated_f32s"]["permeability_rel_diff_vs_f32"] = {"median": float(np.median(d)), "max": float(d.max())}
+    for run_ in out.values():
+        if isinstance(run_, dict):
+            run_.pop("permeability", None)
     out["budget_bytes"] = 64 << 30
     out["max_slots"] = 64
     out["storage"] = "f32"
