@@ -550,3 +550,33 @@ def test_mask_values_above_five_are_plain_walls():
     want = oracle.run_ts(f0, solid, 7, 1.3, (1e-5, 0, 0))
     got = oracle.run_ts(f0, m, 7, 1.3, (1e-5, 0, 0), bc=bc)
     assert np.array_equal(got, want)
+
+
+def test_golden_steady_96cube_starts_as_the_oracle_runs():
+    """tests/golden/steady_96cube.txt was written by make_steady_96cube.py from the oracle alone: its
+    pack and its first window's mean velocity are what the oracle computes now (bit for bit)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "steady_96cube.txt")
+    vals, hist = {}, {}
+    for line in open(path):
+        f = line.split("#", 1)[0].split()
+        if not f:
+            continue
+        if f[0] == "U_at":
+            hist[int(f[1])] = float(f[2])
+        else:
+            vals[f[0]] = f[1]
+    n, g, omega, K = int(vals["lattice"]), float(vals["g"]), float(vals["omega"]), int(vals["K"])
+    solid, spheres = lbm_inputs.sphere_pack(n, int(vals["radius"]), float(vals["porosity_target"]), int(vals["seed"]))
+    assert spheres == int(vals["spheres"]) and int((solid == 0).sum()) == int(vals["n_fluid"])
+    f = oracle.init_equilibrium(lbm_inputs.rho_u_field(solid.shape), solid)
+    f = oracle.run_ts(f, solid, K, omega, (g, 0.0, 0.0))
+    u = float(oracle.mean_velocity(oracle.moments(f, solid), (g, 0.0, 0.0))[0])
+    assert u == hist[K]
+    # the stored result follows from its last window by Darcy's law
+    nu = (1.0 / omega - 0.5) / 3.0
+    phi = int(vals["n_fluid"]) / solid.size
+    assert abs(float(vals["permeability"]) - nu * phi * hist[int(vals["steps"])] / g) <= 1e-12 * float(vals["permeability"])
+    # and the stop rule held: three windows under the stated tolerance
+    s = int(vals["steps"])
+    assert all(abs(hist[s - j * K] - hist[s - (j + 1) * K]) < float(vals["tol"]) * abs(hist[s]) for j in range(3))
