@@ -11,15 +11,18 @@ Besides the headline the JSON line carries:
   roofline      achieved HBM bandwidth of the dominant kernel from its
                 algorithmic bytes per launch and its event-timed average
                 launch duration, against the 8 TB/s HBM3E peak;
-  schemes       MFLUP/s and GB/s of every scheme x layout on the same lattice;
-  schemes       also AA with the TRT collision, and AA on an indirect 256^3 duct with a
-                velocity inlet and a pressure outlet (open boundaries);
-  porous512     AA and two-step on the 512^3 sphere pack (indirect addressing);
+  schemes       every scheme x layout on the same lattice, AA also in FP32, FP32-shifted
+                and FP16-shifted storage, with the TRT collision, and on an indirect 256^3
+                duct with a velocity inlet and a pressure outlet: whole-run MFLUP/s, and
+                each kernel's event-timed duration, GB/s and fraction of the HBM peak
+                (with its counted bytes while profiles/ is current for these kernels);
+  porous512     every scheme on the 512^3 sphere pack (indirect addressing), the same way;
   copy          the STREAM-style copy bandwidth of the device;
   precision     the 384^3 sphere pack run to steady state in every storage form,
                 with each form's permeability error against FP64;
   serving       continuous batching of porous solves: solves/s, p50/p99 latency,
-                aggregate MFLUP/s and share of the HBM roofline;
+                statuses, aggregate MFLUP/s and share of the HBM roofline (FP32 storage,
+                and a saturated run in FP32-shifted storage beside it);
   cpu_baseline  the FP64 oracle timed on the host cores on bounded samples.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--only-main] [--no-cpu]
