@@ -137,6 +137,9 @@ def counter_table(workload):
     return rows if current else {}
 
 
+COPY_GBS = [None]   # the device's measured copy rate, once known (the paper's STREAM yardstick, Table 7)
+
+
 def measure_row(P, torch, grid, scheme, addressing, precision, workload, steps=100, warmup=10, launches=40,
                 collider="bgk", counters=None, layout="soa"):
     """Wall-clock MFLUP/s over `steps` steps, and every kernel's event-timed launch duration, achieved
@@ -162,6 +165,8 @@ def measure_row(P, torch, grid, scheme, addressing, precision, workload, steps=1
         b = kernel_bytes(name, addressing, precision, nodes)
         k = {"ms": round(t, 4), "algorithmic_bytes": int(b), "GB/s": round(b / (t * 1e-3) / 1e9, 1),
              "frac_hbm": round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        if COPY_GBS[0]:
+            k["frac_copy"] = round(b / (t * 1e-3) / 1e9 / COPY_GBS[0], 4)
         label = f"{workload}/{scheme}/{layout}/{precision}/{name}"
         if counters and label in counters:
             k["traffic"] = counters[label]
@@ -592,6 +597,8 @@ def main():
     if not args.only_main:
         log("[bench] copy calibration")
         result["copy"] = {"GB/s": round(bench_copy(P, torch), 1)}
+        COPY_GBS[0] = result["copy"]["GB/s"]
+        roofline["frac_of_copy"] = round(roofline["achieved"] / COPY_GBS[0], 4)
         log("[bench] scheme x layout table, 256^3 channel (FP64; AA also FP32, F32S, FP16S)")
         table = {}
         cc = counter_table("channel256")
