@@ -124,3 +124,20 @@ def test_every_declaration_cites_a_passage_or_says_it_has_none():
         if not re.search(r"\b(Secs?\.|Tables?|Fig\.)\s*\d|No paper passage|cannot allocate", comment):
             missing.append(m.group(1))
     assert not missing, missing
+
+
+def test_block_order_and_batch_sync_validation_without_gpu():
+    """lbm_set_block_order is refused on a direct grid and before the index exists; lbm_batch_sync and
+    lbm_reduce_moments_noalloc refuse null handles; none of these touches the GPU."""
+    import paper_1111_0922_amd as P
+    L = P._lib
+    lib = L.load()
+    fake = ctypes.c_void_p(256)
+    direct = P.Grid(8, 8, 8)
+    assert lib.lbm_set_block_order(direct._h, fake, 1) == L.LBM_E_UNSUPPORTED
+    ind = P.Grid(16, 16, 16, addressing="indirect")
+    assert lib.lbm_set_block_order(ind._h, fake, 1) == L.LBM_E_STATE
+    assert lib.lbm_set_block_order(ind._h, None, 0) == L.LBM_OK      # natural order: always allowed
+    assert lib.lbm_set_block_order(None, None, 0) == L.LBM_E_ARG
+    assert lib.lbm_batch_sync(None, None, None) == L.LBM_E_ARG
+    assert lib.lbm_reduce_moments_noalloc(None, fake, None) == L.LBM_E_ARG
