@@ -111,11 +111,17 @@ PDF_SIZE = {"f64": 8, "f32": 4, "f16s": 2, "f32s": 4}
 IDX_BYTES = {"ts_step": 72, "os_push": 72, "os_pull": 72, "aa_even": 0, "aa_odd": 72, "et_even": 28, "et_odd": 28}
 
 
-def kernel_bytes(name, addressing, precision, nodes):
+def kernel_bytes(name, addressing, precision, nodes, rank=False, cells=0):
     """Algorithmic HBM bytes of one launch (one step for ts_step): each PDF read and written once,
-    no write-allocate, plus the IDX or esoteric-twist table entries an indirect kernel reads."""
+    no write-allocate, plus the IDX or esoteric-twist table entries an indirect kernel reads.  With
+    neighbour ids looked up by rank, a kernel that reads them reads one 4-byte cell_of entry per node
+    instead of 18 IDX entries, and the 8-byte words of ceil(cells / 32) once."""
     pdf = 2 * 19 * PDF_SIZE[precision] * (2 if name == "ts_step" else 1)
-    return (pdf + (IDX_BYTES[name] if addressing == "indirect" else 0)) * nodes
+    if addressing != "indirect":
+        return pdf * nodes
+    if rank and IDX_BYTES[name] == 72:
+        return (pdf + 4) * nodes + 8 * ((cells + 31) // 32)
+    return (pdf + IDX_BYTES[name]) * nodes
 
 
 def counter_table(workload):
@@ -145,6 +151,8 @@ def measure_row(P, torch, grid, scheme, addressing, precision, workload, steps=1
     """Wall-clock MFLUP/s over `steps` steps, and every kernel's event-timed launch duration, achieved
     GB/s of its algorithmic bytes and fraction of the HBM peak (plus the counters' bytes if current)."""
     nodes = grid.n_nodes
+    rank = addressing == "indirect" and grid.rank_lookup
+    cells = int(np.prod(grid.shape))
     grid.step(warmup, collider=collider)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -152,8 +160,8 @@ def measure_row(P, torch, grid, scheme, addressing, precision, workload, steps=1
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     mf = nodes * steps / dt / 1e6
-    bl = P.model_bytes(scheme, addressing, precision)
-    row = {"MFLUP/s": round(mf, 1), "bytes_per_lup": bl, "GB/s": round(mf * bl / 1e3, 1),
+    bl = P.model_bytes(scheme, addressing, precision, model="gpu_rank" if rank else "gpu")
+    row = {"MFLUP/s": round(mf, 1), "bytes_per_lup": bl, "neighbour_ids": "rank" if rank else "idx", "GB/s": round(mf * bl / 1e3, 1),
            "frac_hbm_wall": round(mf * bl / 1e3 / HBM_PEAK_GBS, 4), "kernels": {}}
     ms = per_launch_ms(torch, grid, launches, collider)
     fr = []
@@ -162,7 +170,7 @@ def measure_row(P, torch, grid, scheme, addressing, precision, workload, steps=1
         if name in row["kernels"]:
             continue
         t = float(np.mean([ms[p] for p in ms if STEP_KERNELS[scheme][p] == name]))
-        b = kernel_bytes(name, addressing, precision, nodes)
+        b = kernel_bytes(name, addressing, precision, nodes, rank, cells)
         k = {"ms": round(t, 4), "algorithmic_bytes": int(b), "GB/s": round(b / (t * 1e-3) / 1e9, 1),
              "frac_hbm": round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         if COPY_GBS[0]:
@@ -459,7 +467,7 @@ def precision_study(log, n=384, radius=8, porosity=0.6, seed=4, tol=1e-7, max_st
         dt = time.perf_counter() - t0
         U = mon.history[-1]
         mf = nf * steps / dt / 1e6
-        bl = P.model_bytes("aa", "indirect", prec)
+        bl = P.model_bytes("aa", "indirect", prec, model="gpu_rank" if grid.rank_lookup else "gpu")
         res[key] = {"steps": steps, "status": mon.status if mon.status != "running" else "cap",
                     "U": U, "permeability": nu * phi * U / g, "MFLUP/s": round(mf, 1),
                     "frac_hbm": round(mf * bl / 1e3 / HBM_PEAK_GBS, 4), "bytes_per_lup": bl,

@@ -120,7 +120,8 @@ typedef struct {
     int64_t idx_pitch;     /* entries between IDX rows                              */
     int64_t pdf_bytes;     /* one lattice for the queried scheme                    */
     int64_t pdf1_bytes;    /* second lattice (TS, OS push, OS pull) or 0           */
-    int64_t idx_bytes;     /* int32 IDX[18][idx_pitch] and the block order (indirect) or 0 */
+    int64_t idx_bytes;     /* int32 IDX[18][idx_pitch], the block order and (lexicographic
+                              numbering) the rank-lookup arrays (indirect) or 0       */
     int64_t aux_bytes;     /* int32 ET table [7][idx_pitch] (indirect ET) or 0      */
     int64_t scratch_bytes; /* moment-reduction partials                             */
     int64_t cellmap_bytes; /* int32 cellmap[n_cells] (indirect)                     */
@@ -198,7 +199,10 @@ int lbm_set_boundary(lbm_grid *g, int32_t cls, int32_t kind, double rho, const d
  *     LDS, 65536 for the others), 40960 (direct) or 53248 (indirect) for
  *     FP32 and 0 for FP16 storage; on AoS grids it is 0, except FP64 AA:
  *     20480 for the even kernel (two workgroups per CU) and 98304 for the
- *     odd kernel (one per CU).
+ *     odd kernel (one per CU).  Indirect SoA kernels that look neighbour ids
+ *     up by rank (LBM_OPT_RANK_LOOKUP) use 32768 for the FP64 one-step pull
+ *     and the FP32 AA odd kernel, 65536 for the other FP64 kernels; with
+ *     IDX the FP64 one-step push uses 98304.
  *   LBM_OPT_ROW_STAGE (0/1, default 1): on a direct SoA grid the x-shifted
  *     PDFs move through LDS, so that all global accesses of a wavefront are
  *     aligned: a workgroup holds whole x-rows where nx is a power of two no
@@ -227,6 +231,16 @@ int lbm_set_boundary(lbm_grid *g, int32_t cls, int32_t kind, double rho, const d
  *     that share partly written cache lines run on one L2.  0 keeps the
  *     natural order.  The default is 1 on SoA grids, 0 on AoS grids.  A table
  *     set with lbm_set_block_order takes precedence.
+ *   LBM_OPT_RANK_LOOKUP (-1 = default, 0 or 1): on an indirect grid numbered
+ *     lexicographically (no desc.brick) whose boundary classes are all walls,
+ *     1 makes the kernels that read neighbour ids compute them instead of
+ *     reading IDX: the id of a fluid cell is the number of fluid cells before
+ *     it, found from the node's cell (4 bytes per node) and, per 32 cells, the
+ *     fluid bits and the count before them (8 bytes, shared by the neighbours
+ *     of all nodes there).  IDX moves 72 bytes per node.  Ignored where it
+ *     does not apply (bricked numbering, open boundaries, direct grids).
+ *     The default is 1 on SoA grids with FP64, FP32 or FP32-shifted storage
+ *     and 0 otherwise.
  * Errors: LBM_E_ARG for an unknown option or a value out of range. */
 enum {
     LBM_OPT_XCD_REMAP = 1,
@@ -235,7 +249,8 @@ enum {
     LBM_OPT_ROW_STAGE = 4,
     LBM_OPT_PAIR = 5,
     LBM_OPT_BAND = 6,
-    LBM_OPT_SLAB_ORDER = 7
+    LBM_OPT_SLAB_ORDER = 7,
+    LBM_OPT_RANK_LOOKUP = 8
 };
 int lbm_set_option(lbm_grid *g, int32_t option, int64_t value);
 
@@ -283,9 +298,17 @@ int lbm_query_sizes(const lbm_grid *g, int32_t scheme, lbm_sizes *out);
  *      bit i-1 is set when x + c_i is solid.  When d_scratch is given, the
  *      ceil(N_f / 256) entries after the 18 IDX rows (idx_bytes covers them)
  *      receive the XCD slab block order (LBM_OPT_SLAB_ORDER); with d_scratch
- *      NULL they are left alone and the natural order is used.  Asynchronous.
- * d_scratch: build_scratch_bytes of device memory.  Errors: LBM_E_STATE on a
- * direct grid or when call 2 precedes call 1. */
+ *      NULL they are left alone and the natural order is used.  On a grid
+ *      numbered lexicographically the entries after that order (idx_bytes
+ *      covers them) receive the arrays of LBM_OPT_RANK_LOOKUP: uint32
+ *      cell_of[idx_pitch] (the cell x + nx (y + ny z) of every node), then per
+ *      32 cells w = 0 .. ceil(n_cells / 32) - 1 a pair of uint32: bit k set
+ *      when cell 32 w + k is fluid, and the fluid id of the word's first fluid
+ *      cell (0 when it has none).  Asynchronous.
+ * d_mask is read by both calls.  d_scratch: build_scratch_bytes of device
+ * memory.  Errors: LBM_E_STATE on a direct grid or when call 2 precedes call
+ * 1; LBM_E_ARG for a missing d_cellmap, or a missing d_mask (either call) or
+ * d_scratch (call 1). */
 int lbm_build_idx(lbm_grid *g, const uint8_t *d_mask, int32_t *d_cellmap, int32_t *d_idx,
                   int32_t *d_et, void *d_scratch, int64_t *n_fluid_out, void *stream);
 
@@ -410,7 +433,8 @@ int lbm_batch_destroy(lbm_batch *b);
  * its step counter; its parity decides which AA kernel each of its nodes
  * runs; its nodes collide with BGK at the grid's omega and force, and its
  * open-boundary classes (lbm_set_boundary) apply as they are set at this
- * call.  Errors: LBM_E_STATE when no slot or tile space is left,
+ * call, as does its neighbour-id lookup (IDX or by rank, LBM_OPT_RANK_LOOKUP).
+ * Errors: LBM_E_STATE when no slot or tile space is left,
  * LBM_E_UNSUPPORTED for other grid kinds.  No paper passage; each slot runs
  * the even and odd kernels of the AA pattern (Sec. 6). */
 int lbm_batch_add(lbm_batch *b, lbm_grid *g, int32_t *slot_out);
@@ -456,9 +480,19 @@ int lbm_stream_copy(const void *d_src, void *d_dst, int64_t bytes, void *stream)
  * model of Tables 1-6 and 8.  model = 0: the paper's counts (write-allocate
  * included, 8-byte PDFs, 4-byte IDX entries, precision ignored).  model = 1:
  * GPU algorithmic bytes of this library (no write-allocate, PDF size of
- * `precision` (8, 4, 2, 4 bytes), this library's IDX use).  Returns < 0 for combinations the
- * model does not cover. */
+ * `precision` (8, 4, 2, 4 bytes), this library's IDX use).  model = 2: as 1,
+ * with the neighbour ids of indirect grids looked up by rank
+ * (LBM_OPT_RANK_LOOKUP): one 4-byte cell_of entry per node update of a kernel
+ * that reads neighbour ids instead of 18 IDX entries (each such launch also
+ * reads the 8-byte words of ceil(n_cells / 32), not counted here as they are
+ * not per node).  Returns < 0 for combinations the model does not cover. */
 double lbm_model_bytes(int32_t scheme, int32_t addressing, int32_t precision, int32_t model);
+
+/* 1 when the bound grid's kernels that read neighbour ids look them up by
+ * rank (LBM_OPT_RANK_LOOKUP in effect: option, numbering, boundary classes),
+ * 0 when they read IDX or the grid is direct; LBM_E_ARG for a null grid,
+ * LBM_E_STATE before lbm_bind.  No paper passage: reports a launch choice. */
+int lbm_rank_lookup_active(const lbm_grid *g);
 
 #ifdef __cplusplus
 }

@@ -61,6 +61,17 @@ int64_t order_key_offset(int64_t chunk_blocks)
     return round_up(round_up(chunk_blocks * 2 * 4, 256) + (2 * chunk_blocks + 2) * 8, 256);
 }
 
+// fluid ids in plain lexicographic order (no brick of desc.brick smaller than the box)
+bool lexicographic(const lbm_grid *g)
+{
+    const int32_t dims[3] = {g->d.nx, g->d.ny, g->d.nz};
+    for (int k = 0; k < 3; ++k)
+        if (g->d.brick[k] > 0 && g->d.brick[k] < dims[k]) return false;
+    return true;
+}
+
+int64_t rank_words_count(const lbm_grid *g) { return (g->n_cells + 31) / 32; }
+
 int64_t storage_nodes(const lbm_grid *g, int scheme)
 {
     if (g->d.addressing == LBM_DIRECT) return g->n_cells;
@@ -84,6 +95,9 @@ const PrecTable &table(int precision)
 int64_t idx_pitch_of(const lbm_grid *g) { return round_up(g->n_nodes > 0 ? g->n_nodes : 1, 64); }
 
 uint32_t node_blocks(const lbm_grid *g) { return (uint32_t)((g->n_nodes + BLOCK - 1) / BLOCK); }
+
+// byte offset of cell_of in the IDX buffer: after the 18 IDX rows and the slab block order
+int64_t rank_offset(const lbm_grid *g) { return 18 * idx_pitch_of(g) * 4 + round_up((int64_t)node_blocks(g) * 4, 256); }
 
 // Workgroups of an update launch.
 uint32_t update_blocks(const lbm_grid *g, const KArgs &a)
@@ -160,13 +174,26 @@ void set_block_order(const lbm_grid *g, KArgs &a, int kind)
 //    residency slows the other AoS kernels, which keep full residency.
 static void set_residency(const lbm_grid *g, KArgs &a, int kind)
 {
-    if (g->wg_lds >= 0 || a.pair || g->d.precision != LBM_F64) return;
+    if (g->wg_lds >= 0 || a.pair) return;
+    // Neighbour ids by rank (indirect SoA) wait on one more load than IDX
+    // does before the gathers, which more resident workgroups cover.  512^3
+    // pack: FP32 AA odd at four workgroups per CU 2.29 ms against 2.45 at
+    // three (the FP32 base); FP64 one-step pull 3.32 at four against 3.47 at
+    // two; FP64 one-step push 4.37 at two against 4.90 at one (its IDX
+    // setting below).  The other FP64 kernels stay at two.
+    if (a.rank_words && g->d.layout == LBM_SOA) {
+        const bool p32 = g->d.precision == LBM_F32 || g->d.precision == LBM_F32S;
+        if (p32 && kind == K_AA_ODD) a.lds_bytes = 32768;
+        if (g->d.precision == LBM_F64) a.lds_bytes = kind == K_OS_PULL ? 32768 : 65536;
+        return;
+    }
+    if (g->d.precision != LBM_F64) return;
     if (g->d.layout == LBM_SOA) {
         const bool staged = g->d.addressing == LBM_DIRECT && a.row_staged && shifts_x(kind);
         a.lds_bytes = staged ? 45056 : 65536;
-        // the one-step push on indirect grids scatters all 18 moving values:
-        // one workgroup per CU (512^3 pack: 5.24 -> 5.03 ms; AA odd and the
-        // esoteric twist are best at two)
+        // the one-step push on indirect grids with IDX scatters all 18 moving
+        // values: one workgroup per CU (512^3 pack: 5.24 -> 5.03 ms; AA odd and
+        // the esoteric twist are best at two)
         if (g->d.addressing == LBM_INDIRECT && kind == K_OS_PUSH) a.lds_bytes = 98304;
     } else {
         if (kind == K_AA_ODD) a.lds_bytes = 98304;
@@ -235,6 +262,17 @@ KArgs base_args(const lbm_grid *g)
     set_collision(a);
     // open boundaries: the constant C_c[d] of each class and direction
     a.bc_on = has_open_boundaries(g) ? 1 : 0;
+    // neighbour ids by rank where the arrays exist and every class is a wall; by
+    // default on SoA grids with 8- and 4-byte storage.  Measured per launch on
+    // the 512^3 pack (SoA, FP64 unless noted; residency as set_residency sets
+    // it): AA odd 4.22 -> 3.80 ms (FP32 2.52 -> 2.24), one-step pull 3.79 ->
+    // 3.32, push 5.05 -> 4.37, two-step 6.56 -> 6.10 per step.  FP16 storage
+    // gains nothing (AA odd 2.18 -> 2.21 ms).
+    const bool rank_default = d.layout == LBM_SOA && d.precision != LBM_F16S;
+    if (g->rank_words && (g->rank > 0 || (g->rank < 0 && rank_default)) && !a.bc_on) {
+        a.cell_of = g->cell_of;
+        a.rank_words = g->rank_words;
+    }
     a.bc_neg = 0;
     for (int c = 0; c < 4; ++c) {
         const double rho = g->bc_rho[c], *u = g->bc_u[c];
@@ -384,6 +422,11 @@ int lbm_set_option(lbm_grid *g, int32_t option, int64_t value)
         g->slab = (int)value;
         return LBM_OK;
     }
+    if (option == LBM_OPT_RANK_LOOKUP) {
+        if (value < -1 || value > 1) return fail(LBM_E_ARG, "rank lookup must be -1, 0 or 1");
+        g->rank = (int)value;
+        return LBM_OK;
+    }
     if (option == LBM_OPT_WG_LDS) {
         // at most 120 KB: with a kernel's own LDS (up to 40 KB) every
         // workgroup still fits the 160 KB of a CU
@@ -439,8 +482,10 @@ int lbm_query_sizes(const lbm_grid *g, int32_t scheme, lbm_sizes *out)
         out->build_scratch_bytes = order_key_offset(nb) + round_up((g->n_cells + BLOCK - 1) / BLOCK * 4, 256);
         if (g->idx_phase == 0) return LBM_OK;
         out->idx_pitch = idx_pitch_of(g);
-        // the 18 IDX rows, then the XCD slab block order (one entry per node block)
-        out->idx_bytes = 18 * out->idx_pitch * 4 + round_up((int64_t)node_blocks(g) * 4, 256);
+        // the 18 IDX rows, then the XCD slab block order (one entry per node block),
+        // then (lexicographic numbering) cell_of and the rank words
+        out->idx_bytes = rank_offset(g);
+        if (lexicographic(g)) out->idx_bytes += out->idx_pitch * 4 + round_up(rank_words_count(g) * 8, 256);
         if (scheme == LBM_ET) out->aux_bytes = 7 * out->idx_pitch * 4;
     }
     const int64_t ns = storage_nodes(g, scheme);
@@ -506,6 +551,7 @@ int lbm_build_idx(lbm_grid *g, const uint8_t *d_mask, int32_t *d_cellmap, int32_
         g->n_nodes = totals[0];
         g->n_ghost = g->d.et_ghosts ? totals[1] : 0;
         g->idx_phase = 1;
+        g->rank_built = false;
         g->scheme = -1;
         g->order = nullptr; // the block count may have changed
         g->order_n = 0;
@@ -513,6 +559,7 @@ int lbm_build_idx(lbm_grid *g, const uint8_t *d_mask, int32_t *d_cellmap, int32_
         return LBM_OK;
     }
     if (g->idx_phase < 1) return fail(LBM_E_STATE, "call lbm_build_idx with d_idx = NULL first");
+    if (!d_mask) return fail(LBM_E_ARG, "d_mask is required (the fill pass reads the boundary classes)");
     b.idx = d_idx;
     b.et = g->d.et_ghosts ? d_et : nullptr;
     b.et_on = b.et ? 1 : 0;
@@ -524,11 +571,17 @@ int lbm_build_idx(lbm_grid *g, const uint8_t *d_mask, int32_t *d_cellmap, int32_
         b.order = reinterpret_cast<uint32_t *>(d_idx + 18 * b.idx_pitch);
         b.n_tiles = node_blocks(g);
     }
+    if (lexicographic(g) && g->n_nodes > 0) {
+        b.cell_of = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(d_idx) + rank_offset(g));
+        b.rank_words = reinterpret_cast<uint2 *>(b.cell_of + idx_pitch_of(g));
+        b.n_words = (uint32_t)rank_words_count(g);
+    }
     launch_idx_phase2(b, s);
     int rc = hip_check(hipGetLastError(), "index build (fill pass)");
     if (rc) return rc;
     g->idx_phase = 2;
     g->order_built = b.order != nullptr;
+    g->rank_built = b.rank_words != nullptr;
     if (n_fluid_out) *n_fluid_out = g->n_nodes;
     return LBM_OK;
 }
@@ -555,6 +608,12 @@ int lbm_bind(lbm_grid *g, int32_t scheme, void *d_pdf0, void *d_pdf1, const int3
     g->cur = 0;
     g->idx = ind ? d_idx : nullptr;
     g->slab_table = (ind && g->order_built) ? reinterpret_cast<const uint32_t *>(d_idx + 18 * idx_pitch_of(g)) : nullptr;
+    g->cell_of = nullptr;
+    g->rank_words = nullptr;
+    if (ind && g->rank_built) {
+        g->cell_of = reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(d_idx) + rank_offset(g));
+        g->rank_words = reinterpret_cast<const uint2 *>(g->cell_of + idx_pitch_of(g));
+    }
     g->aux = (ind && scheme == LBM_ET) ? d_aux : nullptr;
     g->scratch = static_cast<double *>(d_scratch);
     g->pitch = sz.pitch;
@@ -612,8 +671,10 @@ int lbm_step(lbm_grid *g, int32_t scheme, int32_t collider, int64_t n_steps, voi
     const int A = g->d.addressing, L = g->d.layout, C = collider == LBM_IDENTITY ? 0 : 1;
     KArgs a = base_args(g);
     const uint32_t nb = update_blocks(g, a);
+    const uint32_t lds_base = a.lds_bytes;
     auto launch = [&](int kind) {
         set_block_order(g, a, kind);
+        a.lds_bytes = lds_base; // set_residency adjusts per kernel from the base
         set_residency(g, a, kind);
         (a.pair == 2 ? tb.pair_wide[C][kind] : a.pair ? tb.pair[C][kind]
          : a.row_staged == 2 ? tb.wide[C][kind] : a.row_staged == 3 ? tb.gen[C][kind]
@@ -705,22 +766,32 @@ double lbm_model_bytes(int32_t scheme, int32_t addressing, int32_t precision, in
         }
         return pdfs * 8.0 + (ind ? idxs * 4.0 : 0.0);
     }
-    if (model == 1) {
+    if (model == 1 || model == 2) {
         if (precision < LBM_F64 || precision > LBM_F32S) return -1.0;
         const double s = pdf_size(precision);
-        // no write-allocate on the GPU: each PDF is loaded once and stored once per kernel
+        // no write-allocate on the GPU: each PDF is loaded once and stored once per kernel;
+        // a kernel that reads neighbour ids reads q - 1 IDX entries (model 1) or one
+        // cell_of entry (model 2)
+        const double nb = model == 1 ? q - 1 : 1;
         double pdfs, idxs;
         switch (scheme) {
-        case LBM_TS: pdfs = 4 * q; idxs = q - 1; break;           // IDX in the propagation kernel only
+        case LBM_TS: pdfs = 4 * q; idxs = nb; break;              // in the propagation kernel only
         case LBM_OS_PUSH:
-        case LBM_OS_PULL: pdfs = 2 * q; idxs = q - 1; break;
-        case LBM_AA: pdfs = 2 * q; idxs = (q - 1) / 2.0; break;   // q-1 on odd steps, none on even
+        case LBM_OS_PULL: pdfs = 2 * q; idxs = nb; break;
+        case LBM_AA: pdfs = 2 * q; idxs = nb / 2.0; break;        // on odd steps, none on even
         case LBM_ET: pdfs = 2 * q; idxs = 7; break;               // six storage addresses + solid mask
         default: return -1.0;
         }
         return pdfs * s + (ind ? idxs * 4.0 : 0.0);
     }
     return -1.0;
+}
+
+int lbm_rank_lookup_active(const lbm_grid *g)
+{
+    if (!g) return fail(LBM_E_ARG, "null grid");
+    if (g->scheme < 0) return fail(LBM_E_STATE, "no buffers bound (call lbm_bind)");
+    return base_args(g).rank_words ? 1 : 0;
 }
 
 } // extern "C"

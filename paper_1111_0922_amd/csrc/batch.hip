@@ -47,6 +47,11 @@ struct SlotDesc {
     int64_t pdf_off;     // lattice and IDX: byte offsets from the workspace
     int64_t idx_off;
     int64_t order_off;   // XCD slab block order of the grid (after its IDX rows), or NO_ORDER
+    int64_t cell_off;    // neighbour ids by rank: the grid's cell_of and rank words, when rank_on
+    int64_t words_off;
+    int64_t plane;
+    int32_t nx, ny, nz, rank_on;
+    FastDiv dvx, dvy;
     int64_t pitch;
     int64_t idx_pitch;
     double sigma;        // shifted-storage scale (canonical transfer of the moments)
@@ -103,6 +108,18 @@ __device__ __forceinline__ KArgs slot_args(const SlotDesc &sd, char *base)
     a.dst = base + sd.pdf_off;
     a.idx = reinterpret_cast<const int32_t *>(base + sd.idx_off);
     a.et = nullptr;
+    a.cell_of = nullptr;
+    a.rank_words = nullptr;
+    if (sd.rank_on) {
+        a.cell_of = reinterpret_cast<const uint32_t *>(base + sd.cell_off);
+        a.rank_words = reinterpret_cast<const uint2 *>(base + sd.words_off);
+        a.nx = sd.nx;
+        a.ny = sd.ny;
+        a.nz = sd.nz;
+        a.plane = sd.plane;
+        a.dvx = sd.dvx;
+        a.dvy = sd.dvy;
+    }
     a.pitch = sd.pitch;
     a.idx_pitch = sd.idx_pitch;
     a.n_nodes = sd.n_nodes;
@@ -482,6 +499,16 @@ int lbm_batch_add(lbm_batch *b, lbm_grid *g, int32_t *slot_out)
     sd.pdf_off = ws_offset(b, g->pdf[0]);
     sd.idx_off = ws_offset(b, g->idx);
     sd.order_off = (g->slab_table && g->slab != 0) ? ws_offset(b, g->slab_table) : NO_ORDER;
+    // neighbour ids by rank as the grid's own launches use them
+    sd.rank_on = a.rank_words ? 1 : 0;
+    sd.cell_off = a.rank_words ? ws_offset(b, a.cell_of) : 0;
+    sd.words_off = a.rank_words ? ws_offset(b, a.rank_words) : 0;
+    sd.plane = a.plane;
+    sd.nx = a.nx;
+    sd.ny = a.ny;
+    sd.nz = a.nz;
+    sd.dvx = a.dvx;
+    sd.dvy = a.dvy;
     sd.pitch = a.pitch;
     sd.idx_pitch = a.idx_pitch;
     sd.sigma = a.sigma;

@@ -247,6 +247,7 @@ __global__ void __launch_bounds__(BLOCK) k_idx_fill(BuildArgs b)
     if (n < 0) return;
     int x, y, z;
     cell_xyz(b, c, x, y, z);
+    if (b.cell_of) b.cell_of[n] = c;
     // XCD slab of a node block: the y-eighth of its first node's row
     if (b.order_key && (n & (BLOCK - 1)) == 0) b.order_key[n / BLOCK] = (uint32_t)(((int64_t)y * 8) / b.ny);
     uint32_t mask = 0;
@@ -268,6 +269,22 @@ __global__ void __launch_bounds__(BLOCK) k_idx_fill(BuildArgs b)
         }
         b.et[6 * b.idx_pitch + n] = (int32_t)mask;
     }
+}
+
+// Rank words (one thread per 32 cells): bit k set when cell 32 w + k is
+// fluid, and the fluid id of the word's first fluid cell, which in the
+// lexicographic numbering is the number of fluid cells before the word (0
+// for a word without fluid cells, whose rank is never read).
+__global__ void __launch_bounds__(BLOCK) k_rank_words(BuildArgs b)
+{
+    const uint32_t w = blockIdx.x * BLOCK + threadIdx.x;
+    if (w >= b.n_words) return;
+    const uint32_t c0 = w * 32u;
+    uint32_t bits = 0;
+    for (uint32_t k = 0; k < 32u && c0 + k < b.n_cells; ++k)
+        if (!b.mask[c0 + k]) bits |= 1u << k;
+    const uint32_t rank = bits ? (uint32_t)b.cellmap[c0 + (uint32_t)__ffs(bits) - 1u] : 0u;
+    b.rank_words[w] = make_uint2(bits, rank);
 }
 
 // Block order from the slab keys (one workgroup).  Workgroup b runs on XCD
@@ -354,6 +371,8 @@ void launch_idx_phase2(const BuildArgs &b, hipStream_t s)
 {
     const uint32_t blocks = (b.n_cells + BLOCK - 1) / BLOCK;
     hipLaunchKernelGGL(k_idx_fill, dim3(blocks), dim3(BLOCK), 0, s, b);
+    if (b.cell_of && b.rank_words && b.n_words > 0)
+        hipLaunchKernelGGL(k_rank_words, dim3((b.n_words + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, b);
     if (b.order_key && b.order && b.n_tiles > 0)
         hipLaunchKernelGGL(k_order_build, dim3(1), dim3(ORDER_THREADS), 0, s, b);
 }

@@ -34,6 +34,11 @@ struct BuildArgs {
     uint32_t *order_key;  // [n_tiles] scratch
     uint32_t *order;      // [n_tiles] after the 18 IDX rows
     uint32_t n_tiles;     // ceil(n_fluid / BLOCK)
+    // rank lookup (lexicographic numbering only, phase 2, when both are set):
+    // cell of every node, and per 32 cells the fluid bits and the fluid count before
+    uint32_t *cell_of;    // [idx_pitch]
+    uint2 *rank_words;    // [n_words]
+    uint32_t n_words;     // ceil(n_cells / 32)
 };
 
 void launch_idx_phase1(const BuildArgs &b, hipStream_t s);

@@ -35,6 +35,10 @@ struct lbm_grid {
     bool order_built = false;             // lbm_build_idx wrote the XCD slab order after the IDX rows
     const uint32_t *slab_table = nullptr; // that table in the bound IDX buffer
     int slab = -1;                        // LBM_OPT_SLAB_ORDER: 1 on, 0 off, -1 default (SoA on)
+    bool rank_built = false;              // lbm_build_idx wrote cell_of and the rank words after the block order
+    const uint32_t *cell_of = nullptr;    // those arrays in the bound IDX buffer
+    const uint2 *rank_words = nullptr;
+    int rank = -1;                        // LBM_OPT_RANK_LOOKUP: 1 on, 0 off, -1 default
     // open-boundary classes 1..4 (indirect grids): kind, density, velocity
     int bc_kind[4] = {0, 0, 0, 0};
     double bc_rho[4] = {1.0, 1.0, 1.0, 1.0};

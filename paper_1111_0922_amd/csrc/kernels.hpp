@@ -111,6 +111,12 @@ struct KArgs {
     void *dst;             // lattice written (== src for AA and ET)
     const int32_t *idx;    // IDX[18][idx_pitch] (indirect)
     const int32_t *et;     // ET table [7][idx_pitch] (indirect ET)
+    // Neighbour ids by rank instead of IDX (indirect grids numbered
+    // lexicographically, no open boundaries; null otherwise): the node's
+    // cell, and per 32 cells of the box (x fastest) the fluid bits and the
+    // number of fluid cells before the word (rank_neighbours).
+    const uint32_t *cell_of;   // [idx_pitch]
+    const uint2 *rank_words;   // [ceil(n_cells / 32)]
     int64_t pitch;         // SoA elements between direction arrays
     int64_t idx_pitch;
     int64_t plane;         // nx * ny
@@ -301,9 +307,50 @@ struct Node<A_DIRECT, NEED> {
     __device__ __forceinline__ void pin_et(int) {}
 };
 
+// The 18 neighbour ids of node n from the rank words, where the fluid id of a
+// cell is the number of fluid cells before it in x-fastest order: for cell
+// c = 32 w + b, fluid when bit b of word w is set, with id rank(w) +
+// popcount(bits(w) below b).  The result equals IDX with every non-fluid
+// neighbour as -1.  Per node this reads 4 bytes of cell_of; the words (8
+// bytes per 32 cells, about 33 MB for a 512^3 box) are shared by the 18
+// neighbours of ~13 nodes each and mostly come from the cache, where IDX
+// streams 72 bytes per node from memory.
+__device__ __forceinline__ void rank_neighbours(const KArgs &k, uint32_t n, int32_t (&m)[18])
+{
+    const uint32_t c = k.cell_of[n];
+    const uint32_t nx = (uint32_t)k.nx, ny = (uint32_t)k.ny, nz = (uint32_t)k.nz, pl = (uint32_t)k.plane;
+    const uint32_t q = fdiv(c, k.dvx);
+    const uint32_t x = c - q * nx;
+    const uint32_t z = fdiv(q, k.dvy);
+    const uint32_t y = q - z * ny;
+    const uint32_t px[3] = {x == 0 ? nx - 1 : x - 1, x, x + 1 == nx ? 0 : x + 1};
+    const uint32_t py[3] = {(y == 0 ? ny - 1 : y - 1) * nx, y * nx, (y + 1 == ny ? 0 : y + 1) * nx};
+    const uint32_t pz[3] = {(z == 0 ? nz - 1 : z - 1) * pl, z * pl, (z + 1 == nz ? 0 : z + 1) * pl};
+    uint32_t cc[18];
+    uint2 w[18];
+#pragma unroll
+    for (int j = 0; j < 18; ++j) {
+        const int i = j + 1;
+        cc[j] = px[cx(i) + 1] + py[cy(i) + 1] + pz[cz(i) + 1];
+        w[j] = k.rank_words[cc[j] >> 5];
+    }
+    // All 18 words in flight before the first is used: without this opaque use
+    // the compiler loads a word's rank only under the lane's fluid bit and waits
+    // for each load in turn (36 round trips instead of one).
+#pragma unroll
+    for (int j = 0; j < 18; ++j) asm volatile("" : "+v"(w[j].x), "+v"(w[j].y));
+#pragma unroll
+    for (int j = 0; j < 18; ++j) {
+        const uint32_t b = cc[j] & 31u;
+        const int32_t id = (int32_t)(w[j].y + (uint32_t)__popc(w[j].x & ((1u << b) - 1u)));
+        m[j] = ((w[j].x >> b) & 1u) ? id : -1;
+    }
+}
+
 // Indirect addressing (Sec. 1): node ids of fluid nodes; neighbours from
-// IDX (-1 = wall, -1 - c = open-boundary class c); the esoteric twist reads
-// its storage addresses and the solid-neighbour mask from the ET table.
+// IDX (-1 = wall, -1 - c = open-boundary class c) or by rank; the esoteric
+// twist reads its storage addresses and the solid-neighbour mask from the ET
+// table.
 template <int NEED>
 struct Node<A_INDIRECT, NEED> {
     int64_t a;
@@ -315,8 +362,12 @@ struct Node<A_INDIRECT, NEED> {
     {
         a = n;
         if constexpr ((NEED & NEED_NB) != 0) {
+            if (k.rank_words) {
+                rank_neighbours(k, n, m);
+            } else {
 #pragma unroll
-            for (int q = 0; q < 18; ++q) m[q] = k.idx[(int64_t)q * k.idx_pitch + n];
+                for (int q = 0; q < 18; ++q) m[q] = k.idx[(int64_t)q * k.idx_pitch + n];
+            }
         }
         if constexpr ((NEED & NEED_ET) != 0) {
 #pragma unroll

@@ -33,10 +33,11 @@ def lattice():
 
 
 def model_bytes(scheme, addressing="direct", precision="f64", model="gpu"):
-    """Bytes per lattice-node update of the transfer model (model 'paper' or 'gpu')."""
+    """Bytes per lattice-node update of the transfer model: 'paper' (Tables 1-6), 'gpu' (this library
+    with IDX) or 'gpu_rank' (neighbour ids looked up by rank)."""
     lib = L.load()
     return lib.lbm_model_bytes(L.SCHEMES[scheme], L.ADDRESSING[addressing], L.PRECISIONS[precision],
-                               0 if model == "paper" else 1)
+                               {"paper": 0, "gpu": 1, "gpu_rank": 2}[model])
 
 
 def stream_copy(src: torch.Tensor, dst: torch.Tensor, nbytes: int | None = None):
@@ -109,6 +110,13 @@ class Grid:
         """Open boundary class `cls` (mask value cls + 1): 'wall', 'velocity' (moving wall) or 'pressure'."""
         arr = (ctypes.c_double * 3)(*[float(v) for v in u])
         L.check(self.lib.lbm_set_boundary(self._h, int(cls), L.BC_KINDS[kind], float(rho), arr))
+
+    @property
+    def rank_lookup(self) -> bool:
+        """Whether the bound grid's neighbour-reading kernels look ids up by rank (LBM_OPT_RANK_LOOKUP)."""
+        rc = self.lib.lbm_rank_lookup_active(self._h)
+        L.check(min(rc, 0))
+        return rc == 1
 
     def set_option(self, option, value):
         L.check(self.lib.lbm_set_option(self._h, int(option), int(value)))

@@ -263,8 +263,9 @@ class GpuExecutor:
         req.n_fluid = int(mask.size - int(mask.sum(dtype=np.int64)))
         self.masks[req.rid] = mask
         nf = req.n_fluid + 128
-        # lattice + IDX + partials, and the cellmap held while the index is built
-        return (19 * self.pdf_size + 18 * 4) * nf + 4 * req.n_cells + 4096
+        # lattice + IDX (with the slab order and the rank-lookup arrays: cell_of, 8 bytes per 32 cells) +
+        # partials, and the cellmap held while the index is built
+        return (19 * self.pdf_size + 19 * 4) * nf + 4 * req.n_cells + req.n_cells // 4 + 8192
 
     def admit(self, req):
         from .grid import Grid

@@ -263,3 +263,29 @@ def test_scheduler_on_gpu_fails_only_the_diverged_request():
         assert got[s].permeability == ref[s].permeability
     rep = sch.report(list(got.values()))
     assert rep["diverged"] == 1 and rep["requests"] == 3
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_rank_and_idx_slots_in_one_batch(precision):
+    """A slot takes its grid's neighbour-id lookup (by rank by default, IDX when the option is off at
+    lbm_batch_add); slots of both kinds in one batch reach the bits of the lattice run alone with IDX."""
+    import paper_1111_0922_amd as P
+    K = 15
+    alone = []
+    for gm in GEOMS[:3]:
+        grid, _ = _grid(*gm, precision)
+        grid.set_option(P._lib.OPT_RANK_LOOKUP, 0)
+        grid.step(2 * K)
+        alone.append(from_device(grid.get_pdfs()))
+        del grid
+    batch = P.Batch(8, 4096, precision, use_graph=True)
+    grids = []
+    for i, gm in enumerate(GEOMS[:3]):
+        grid, _ = _grid(*gm, precision)
+        grid.set_option(P._lib.OPT_RANK_LOOKUP, i % 2)
+        assert grid.rank_lookup == bool(i % 2)
+        grids.append((batch.add(grid), grid))
+    for _ in range(2):
+        batch.run(K)
+    for (slot, grid), f_alone in zip(grids, alone):
+        assert np.array_equal(from_device(grid.get_pdfs()).view(np.int64), f_alone.view(np.int64)), slot

@@ -60,6 +60,22 @@ def test_gpu_transfer_model():
     assert P.model_bytes("aa", "indirect", "f32") == 188
     assert P.model_bytes("aa", "indirect", "f16s") == 112
     assert P.model_bytes("cg", "direct", "f64") < 0
+    # neighbour ids by rank: one 4-byte cell_of entry where IDX reads 18, the same on direct grids
+    for prec, s in (("f64", 8), ("f32", 4), ("f32s", 4)):
+        assert P.model_bytes("ts", "indirect", prec, model="gpu_rank") == 4 * q * s + 4
+        assert P.model_bytes("os_pull", "indirect", prec, model="gpu_rank") == 2 * q * s + 4
+        assert P.model_bytes("aa", "indirect", prec, model="gpu_rank") == 2 * q * s + 2
+        assert P.model_bytes("et", "indirect", prec, model="gpu_rank") == 2 * q * s + 28
+        assert P.model_bytes("aa", "direct", prec, model="gpu_rank") == 2 * q * s
+
+
+def test_rank_lookup_query_without_gpu():
+    import paper_1111_0922_amd as P
+    L = P._lib
+    lib = L.load()
+    assert lib.lbm_rank_lookup_active(None) == L.LBM_E_ARG
+    g = P.Grid(16, 8, 8, addressing="indirect")
+    assert lib.lbm_rank_lookup_active(g._h) == L.LBM_E_STATE
 
 
 def test_validation_errors_without_gpu():
@@ -96,12 +112,13 @@ def test_option_ranges_without_gpu():
     g = P.Grid(64, 8, 8, wall_z=True)
     ok = [(L.OPT_WG_LDS, -1), (L.OPT_WG_LDS, 0), (L.OPT_WG_LDS, 122880), (L.OPT_PAIR, -1), (L.OPT_PAIR, 1),
           (L.OPT_BAND, -1), (L.OPT_BAND, 4096), (L.OPT_ROW_STAGE, 0), (L.OPT_ROW_STAGE, 1),
-          (L.OPT_SLAB_ORDER, -1), (L.OPT_SLAB_ORDER, 0), (L.OPT_SLAB_ORDER, 1)]
+          (L.OPT_SLAB_ORDER, -1), (L.OPT_SLAB_ORDER, 0), (L.OPT_SLAB_ORDER, 1),
+          (L.OPT_RANK_LOOKUP, -1), (L.OPT_RANK_LOOKUP, 0), (L.OPT_RANK_LOOKUP, 1)]
     for opt, val in ok:
         g.set_option(opt, val)
     bad = [(L.OPT_WG_LDS, -2), (L.OPT_WG_LDS, 122881), (L.OPT_PAIR, 2), (L.OPT_PAIR, -2), (L.OPT_BAND, -2),
            (L.OPT_BAND, 4097), (L.OPT_PITCH_PAD, -1), (L.OPT_PITCH_PAD, (1 << 20) + 1), (99, 0),
-           (L.OPT_SLAB_ORDER, 2), (L.OPT_SLAB_ORDER, -2)]
+           (L.OPT_SLAB_ORDER, 2), (L.OPT_SLAB_ORDER, -2), (L.OPT_RANK_LOOKUP, 2), (L.OPT_RANK_LOOKUP, -2)]
     for opt, val in bad:
         with pytest.raises(P.LbmError):
             g.set_option(opt, val)
