@@ -377,8 +377,6 @@ def serving_bench(log, n_requests, n_light=100, n_shifted=300, seed_base=100000)
     """
     import paper_1111_0922_amd as P
     from paper_1111_0922_amd.serve import GpuExecutor, Request, Scheduler, poisson_arrivals
-    bl = P.model_bytes("aa", "indirect", "f32")
-
     def run(rate, seed0, n, precision="f32"):
         ex = GpuExecutor(max_slots=64, max_tiles=1 << 20, precision=precision, omega=1.0, g=1e-6)
         sch = Scheduler(ex, hbm_budget=64 << 30, max_slots=64, k_steps=100, tol=1e-6, max_steps=20000,
@@ -386,7 +384,10 @@ def serving_bench(log, n_requests, n_light=100, n_shifted=300, seed_base=100000)
         arr = poisson_arrivals(n, rate, seed=seed0)
         reqs = [Request(rid=i, seed=seed0 + i, arrival=float(a)) for i, a in enumerate(arr)]
         out = sch.serve(reqs)
+        # the bytes the batched kernels move: IDX or the neighbour-id lookup by rank, as the slots ran
+        bl = P.model_bytes("aa", "indirect", precision, model="gpu_rank" if ex.rank_lookup else "gpu")
         rep = sch.report(out, warmup=n // 10, bytes_per_lup=bl, hbm_peak_gbs=HBM_PEAK_GBS)
+        rep["neighbour_ids"] = "rank" if ex.rank_lookup else "idx"
         rep["rate_per_s"] = rate
         rep["arrived"] = n
         rep["warmup_discarded"] = n // 10
@@ -419,7 +420,7 @@ def serving_bench(log, n_requests, n_light=100, n_shifted=300, seed_base=100000)
     out["budget_bytes"] = 64 << 30
     out["max_slots"] = 64
     out["storage"] = "f32"
-    out["bytes_per_lup"] = bl
+    out["bytes_per_lup"] = out["saturated"]["bytes_per_lup"]
     return out
 
 

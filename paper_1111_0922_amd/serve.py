@@ -254,6 +254,7 @@ class GpuExecutor:
         self.events = None
         self.busy_seconds = 0.0
         self.pdf_size = {"f64": 8, "f32": 4, "f16s": 2, "f32s": 4}[precision]
+        self.rank_lookup = False  # whether the admitted lattices look neighbour ids up by rank
 
     def prepare(self, req):
         import lbm_inputs
@@ -281,6 +282,7 @@ class GpuExecutor:
             grid._mask = None
             grid.bind("aa")
             grid.init_equilibrium()
+            self.rank_lookup = grid.rank_lookup
         # the run stream reads this lattice only after the host has seen its set-up finish
         self.setup_stream.synchronize()
         self.joining[req.rid] = grid
