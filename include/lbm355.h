@@ -241,6 +241,15 @@ int lbm_set_boundary(lbm_grid *g, int32_t cls, int32_t kind, double rho, const d
  *     does not apply (bricked numbering, open boundaries, direct grids).
  *     The default is 1 on SoA grids with FP64, FP32 or FP32-shifted storage
  *     and 0 otherwise.
+ *   LBM_OPT_SOA_BLOCK (-1 = default, 0, or a power of two in [64, 65536]
+ *     nodes): storage order of the SoA lattices of an indirect grid.  0 is
+ *     plain SoA: slot (direction j, node n) at j * pitch + n.  B > 0 cuts the
+ *     nodes into blocks of B, each holding its 19 directions one after the
+ *     other: slot (j, n) at ((n / B) * 19 + j) * B + n mod B, so that a
+ *     workgroup's accesses stay in a few memory pages.  Ignored on direct
+ *     and AoS grids.  Changes the lattice layout and sizes: the grid must be
+ *     bound again afterwards.  The default is 1024 for FP64 storage and 0
+ *     for the others.
  * Errors: LBM_E_ARG for an unknown option or a value out of range. */
 enum {
     LBM_OPT_XCD_REMAP = 1,
@@ -250,7 +259,8 @@ enum {
     LBM_OPT_PAIR = 5,
     LBM_OPT_BAND = 6,
     LBM_OPT_SLAB_ORDER = 7,
-    LBM_OPT_RANK_LOOKUP = 8
+    LBM_OPT_RANK_LOOKUP = 8,
+    LBM_OPT_SOA_BLOCK = 9
 };
 int lbm_set_option(lbm_grid *g, int32_t option, int64_t value);
 

@@ -29,6 +29,7 @@ OPT_PAIR = 5
 OPT_BAND = 6
 OPT_SLAB_ORDER = 7
 OPT_RANK_LOOKUP = 8
+OPT_SOA_BLOCK = 9
 NOALLOC_MAX_NODES = 1 << 26   # LBM_NOALLOC_MAX_NODES
 
 SCHEMES = {"ts": TS, "os_push": OS_PUSH, "os_pull": OS_PULL, "aa": AA, "et": ET,

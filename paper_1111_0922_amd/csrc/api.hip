@@ -2,6 +2,7 @@
 // dispatch of the kernel instantiations.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -72,6 +73,22 @@ bool lexicographic(const lbm_grid *g)
 
 int64_t rank_words_count(const lbm_grid *g) { return (g->n_cells + 31) / 32; }
 
+// log2 of the nodes per block of an indirect SoA lattice (slot_index), 0 for plain SoA.
+// Default: blocks of 1024 nodes for FP64.  Measured per launch on the 512^3 pack
+// (plain -> 1024): AA even 2.76-2.79 -> 2.60 ms, odd 3.85-3.88 -> 3.75, two-step
+// 6.18 -> 5.72-5.76 per step, one-step pull 3.12-3.30 -> 3.06-3.10; one-step push
+// and the esoteric twist within their run-to-run spread.  FP32, FP32-shifted and
+// FP16 storage gain nothing overall (AA FP32 even 1.32-1.40 -> 1.24, odd
+// 2.13-2.28 -> 2.24) and stay plain.
+int soa_block_shift(const lbm_grid *g)
+{
+    if (g->d.addressing != LBM_INDIRECT || g->d.layout != LBM_SOA) return 0;
+    const int64_t b = g->soa_block >= 0 ? g->soa_block : (g->d.precision == LBM_F64 ? 1024 : 0);
+    int sh = 0;
+    while (((int64_t)1 << sh) < b) ++sh;
+    return b > 0 ? sh : 0;
+}
+
 int64_t storage_nodes(const lbm_grid *g, int scheme)
 {
     if (g->d.addressing == LBM_DIRECT) return g->n_cells;
@@ -95,6 +112,9 @@ const PrecTable &table(int precision)
 int64_t idx_pitch_of(const lbm_grid *g) { return round_up(g->n_nodes > 0 ? g->n_nodes : 1, 64); }
 
 uint32_t node_blocks(const lbm_grid *g) { return (uint32_t)((g->n_nodes + BLOCK - 1) / BLOCK); }
+
+// storage order the kernels are instantiated for: L_SOA, L_AOS, or L_BLK for a blocked indirect SoA lattice
+int kernel_layout(const lbm_grid *g) { return soa_block_shift(g) ? L_BLK : g->d.layout; }
 
 // byte offset of cell_of in the IDX buffer: after the 18 IDX rows and the slab block order
 int64_t rank_offset(const lbm_grid *g) { return 18 * idx_pitch_of(g) * 4 + round_up((int64_t)node_blocks(g) * 4, 256); }
@@ -209,6 +229,9 @@ KArgs base_args(const lbm_grid *g)
     a.idx = g->idx;
     a.et = g->aux;
     a.pitch = g->pitch;
+    const int bsh = soa_block_shift(g);
+    a.bsh = (uint32_t)bsh;
+    a.bmk = (1u << bsh) - 1u;
     a.idx_pitch = idx_pitch_of(g);
     a.plane = (int64_t)d.nx * d.ny;
     const int z0 = (d.addressing == LBM_DIRECT && d.wall_z) ? 1 : 0;
@@ -422,6 +445,15 @@ int lbm_set_option(lbm_grid *g, int32_t option, int64_t value)
         g->slab = (int)value;
         return LBM_OK;
     }
+    if (option == LBM_OPT_SOA_BLOCK) {
+        const bool pow2 = value >= 64 && value <= 65536 && (value & (value - 1)) == 0;
+        if (!(value == -1 || value == 0 || pow2))
+            return fail(LBM_E_ARG, "SoA block must be -1, 0 or a power of two in [64, 65536] nodes");
+        const int before = soa_block_shift(g);
+        g->soa_block = value;
+        if (soa_block_shift(g) != before) g->scheme = -1; // the lattice layout changes: bind again
+        return LBM_OK;
+    }
     if (option == LBM_OPT_RANK_LOOKUP) {
         if (value < -1 || value > 1) return fail(LBM_E_ARG, "rank lookup must be -1, 0 or 1");
         g->rank = (int)value;
@@ -490,7 +522,9 @@ int lbm_query_sizes(const lbm_grid *g, int32_t scheme, lbm_sizes *out)
     }
     const int64_t ns = storage_nodes(g, scheme);
     const int s = pdf_size(d.precision);
-    out->pitch = round_up(ns, 128) + g->pitch_pad;
+    const int bsh = soa_block_shift(g);
+    // a blocked lattice holds whole blocks: 19 * round_up(ns, block) values
+    out->pitch = round_up(ns, bsh ? std::max<int64_t>(128, (int64_t)1 << bsh) : 128) + g->pitch_pad;
     out->pdf_bytes = d.layout == LBM_SOA ? Q * out->pitch * s : round_up(ns * Q * s, 256);
     out->pdf1_bytes = two_lattices(scheme) ? out->pdf_bytes : 0;
     out->scratch_bytes = round_up((int64_t)node_blocks(g) * 4 * 8, 256);
@@ -629,7 +663,7 @@ int lbm_set_pdfs(lbm_grid *g, const double *d_canon, void *stream)
     KArgs a = base_args(g);
     a.dst = g->pdf[g->cur];
     a.canon_in = d_canon;
-    table(g->d.precision).set[g->d.addressing][g->d.layout][state_rmap(g)](a, node_blocks(g), static_cast<hipStream_t>(stream));
+    table(g->d.precision).set[g->d.addressing][kernel_layout(g)][state_rmap(g)](a, node_blocks(g), static_cast<hipStream_t>(stream));
     return hip_check(hipGetLastError(), "lbm_set_pdfs");
 }
 
@@ -641,7 +675,7 @@ int lbm_get_pdfs(const lbm_grid *g, double *d_canon, void *stream)
     KArgs a = base_args(g);
     a.src = g->pdf[g->cur];
     a.canon = d_canon;
-    table(g->d.precision).get[g->d.addressing][g->d.layout][state_rmap(g)](a, node_blocks(g), static_cast<hipStream_t>(stream));
+    table(g->d.precision).get[g->d.addressing][kernel_layout(g)][state_rmap(g)](a, node_blocks(g), static_cast<hipStream_t>(stream));
     return hip_check(hipGetLastError(), "lbm_get_pdfs");
 }
 
@@ -654,7 +688,7 @@ int lbm_init_equilibrium(lbm_grid *g, const double *d_rho_u, void *stream)
     KArgs a = base_args(g);
     a.dst = g->pdf[0];
     a.rho_u = d_rho_u;
-    table(g->d.precision).init[g->d.addressing][g->d.layout][state_rmap(g)](a, node_blocks(g), static_cast<hipStream_t>(stream));
+    table(g->d.precision).init[g->d.addressing][kernel_layout(g)][state_rmap(g)](a, node_blocks(g), static_cast<hipStream_t>(stream));
     return hip_check(hipGetLastError(), "lbm_init_equilibrium");
 }
 
@@ -668,7 +702,7 @@ int lbm_step(lbm_grid *g, int32_t scheme, int32_t collider, int64_t n_steps, voi
     if (n_steps < 0) return fail(LBM_E_ARG, "negative step count");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const PrecTable &tb = table(g->d.precision);
-    const int A = g->d.addressing, L = g->d.layout, C = collider == LBM_IDENTITY ? 0 : 1;
+    const int A = g->d.addressing, L = kernel_layout(g), C = collider == LBM_IDENTITY ? 0 : 1;
     KArgs a = base_args(g);
     const uint32_t nb = update_blocks(g, a);
     const uint32_t lds_base = a.lds_bytes;
@@ -732,7 +766,7 @@ int lbm_reduce_moments(lbm_grid *g, double *d_out4, void *stream)
     a.src = g->pdf[g->cur];
     a.partials = g->scratch;
     const uint32_t nb = node_blocks(g);
-    table(g->d.precision).reduce[g->d.addressing][g->d.layout][state_rmap(g)](a, nb, s);
+    table(g->d.precision).reduce[g->d.addressing][kernel_layout(g)][state_rmap(g)](a, nb, s);
     launch_reduce_final(g->scratch, nb, d_out4, s);
     return hip_check(hipGetLastError(), "lbm_reduce_moments");
 }

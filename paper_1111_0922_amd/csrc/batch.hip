@@ -53,6 +53,7 @@ struct SlotDesc {
     int32_t nx, ny, nz, rank_on;
     FastDiv dvx, dvy;
     int64_t pitch;
+    uint32_t bsh, bmk;   // blocked SoA lattice (bsh > 0, slot_index) or plain SoA (0)
     int64_t idx_pitch;
     double sigma;        // shifted-storage scale (canonical transfer of the moments)
     CollideParams<double> cpd; // collision factors of the slot's grid (BGK)
@@ -121,6 +122,8 @@ __device__ __forceinline__ KArgs slot_args(const SlotDesc &sd, char *base)
         a.dvy = sd.dvy;
     }
     a.pitch = sd.pitch;
+    a.bsh = sd.bsh;
+    a.bmk = sd.bmk;
     a.idx_pitch = sd.idx_pitch;
     a.n_nodes = sd.n_nodes;
     a.sigma = sd.sigma;
@@ -144,6 +147,23 @@ __device__ __forceinline__ void slot_bc_table(const SlotDesc *sdp)
     if (sdp->bc_on) bc_table_load<typename Store<PREC>::ct>(sdp->bc_can, sdp->bc_f);
 }
 
+// One node's AA step in its slot's storage order (uniform over the tile).
+template <int PREC>
+__device__ __forceinline__ void slot_update(const KArgs &a, uint32_t n, bool odd, bool blocked)
+{
+    if (blocked) {
+        if (odd)
+            update_node<A_INDIRECT, L_BLK, PREC, K_AA_ODD, 1>(a, n);
+        else
+            update_node<A_INDIRECT, L_BLK, PREC, K_AA_EVEN, 1>(a, n);
+    } else {
+        if (odd)
+            update_node<A_INDIRECT, L_SOA, PREC, K_AA_ODD, 1>(a, n);
+        else
+            update_node<A_INDIRECT, L_SOA, PREC, K_AA_EVEN, 1>(a, n);
+    }
+}
+
 // One AA time step (step k of the run) of every active slot: one workgroup
 // per 256-node tile.  (A persistent grid of 8 workgroups per CU striding
 // over the tile list, whose launch shape would not depend on the tile count,
@@ -161,12 +181,7 @@ __global__ void __launch_bounds__(BLOCK) k_aa_batched(const SlotDesc *slots, con
     slot_bc_table<PREC>(slots + tl.slot);
     const bool odd = (sd.t0 + k) & 1;
     const uint32_t n = tile_node0(sd, tl, odd, base) + threadIdx.x;
-    if (n < sd.n_nodes) {
-        if (odd)
-            update_node<A_INDIRECT, L_SOA, PREC, K_AA_ODD, 1>(a, n);
-        else
-            update_node<A_INDIRECT, L_SOA, PREC, K_AA_EVEN, 1>(a, n);
-    }
+    if (n < sd.n_nodes) slot_update<PREC>(a, n, odd, sd.bsh != 0);
 }
 
 // Grid barrier of the cooperative run (every workgroup is resident).  Words
@@ -229,12 +244,7 @@ __global__ void __launch_bounds__(BLOCK) k_aa_batched_coop(const SlotDesc *slots
             }
             const bool odd = (sd.t0 + k) & 1;
             const uint32_t n = tile_node0(sd, tl, odd, base) + threadIdx.x;
-            if (n < sd.n_nodes) {
-                if (odd)
-                    update_node<A_INDIRECT, L_SOA, PREC, K_AA_ODD, 1>(a, n);
-                else
-                    update_node<A_INDIRECT, L_SOA, PREC, K_AA_EVEN, 1>(a, n);
-            }
+            if (n < sd.n_nodes) slot_update<PREC>(a, n, odd, sd.bsh != 0);
         }
         if (k + 1 < k_steps && !grid_barrier(hdr)) return;
     }
@@ -254,10 +264,19 @@ __global__ void __launch_bounds__(BLOCK) k_seg_partials(const SlotDesc *slots, c
     const uint32_t n = tl.node0 + threadIdx.x;
     double m[4] = {0.0, 0.0, 0.0, 0.0};
     if (n < sd.n_nodes) {
-        if ((sd.t0 + steps) & 1)
-            node_moments<A_INDIRECT, L_SOA, PREC, R_AAODD>(a, n, m, slots[tl.slot].bc_can);
-        else
-            node_moments<A_INDIRECT, L_SOA, PREC, R_LOCAL>(a, n, m, slots[tl.slot].bc_can);
+        const bool odd = (sd.t0 + steps) & 1;
+        const double(*can)[Q] = slots[tl.slot].bc_can;
+        if (sd.bsh != 0) {
+            if (odd)
+                node_moments<A_INDIRECT, L_BLK, PREC, R_AAODD>(a, n, m, can);
+            else
+                node_moments<A_INDIRECT, L_BLK, PREC, R_LOCAL>(a, n, m, can);
+        } else {
+            if (odd)
+                node_moments<A_INDIRECT, L_SOA, PREC, R_AAODD>(a, n, m, can);
+            else
+                node_moments<A_INDIRECT, L_SOA, PREC, R_LOCAL>(a, n, m, can);
+        }
     }
     block_sum4(m, partials + 4 * (int64_t)tile);
 }
@@ -510,6 +529,8 @@ int lbm_batch_add(lbm_batch *b, lbm_grid *g, int32_t *slot_out)
     sd.dvx = a.dvx;
     sd.dvy = a.dvy;
     sd.pitch = a.pitch;
+    sd.bsh = a.bsh;
+    sd.bmk = a.bmk;
     sd.idx_pitch = a.idx_pitch;
     sd.sigma = a.sigma;
     sd.cpd = a.cpd;

@@ -39,6 +39,7 @@ struct lbm_grid {
     const uint32_t *cell_of = nullptr;    // those arrays in the bound IDX buffer
     const uint2 *rank_words = nullptr;
     int rank = -1;                        // LBM_OPT_RANK_LOOKUP: 1 on, 0 off, -1 default
+    int64_t soa_block = -1;               // LBM_OPT_SOA_BLOCK: nodes per block of an indirect SoA lattice (0 plain, -1 default)
     // open-boundary classes 1..4 (indirect grids): kind, density, velocity
     int bc_kind[4] = {0, 0, 0, 0};
     double bc_rho[4] = {1.0, 1.0, 1.0, 1.0};
@@ -61,6 +62,7 @@ lbm::KArgs base_args(const lbm_grid *g);
 uint32_t update_blocks(const lbm_grid *g, const lbm::KArgs &a);
 void set_block_order(const lbm_grid *g, lbm::KArgs &a, int kind);
 uint32_t node_blocks(const lbm_grid *g);
+int kernel_layout(const lbm_grid *g);
 int64_t idx_pitch_of(const lbm_grid *g);
 const lbm::PrecTable &table(int precision);
 int state_rmap(const lbm_grid *g);

@@ -153,6 +153,7 @@ PrecTable make_table()
     fill_al<A_DIRECT, L_AOS, P>(t);
     fill_al<A_INDIRECT, L_SOA, P>(t);
     fill_al<A_INDIRECT, L_AOS, P>(t);
+    fill_al<A_INDIRECT, L_BLK, P>(t);
     return t;
 }
 

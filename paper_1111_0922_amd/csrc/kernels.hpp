@@ -118,6 +118,7 @@ struct KArgs {
     const uint32_t *cell_of;   // [idx_pitch]
     const uint2 *rank_words;   // [ceil(n_cells / 32)]
     int64_t pitch;         // SoA elements between direction arrays
+    uint32_t bsh, bmk;     // blocked SoA (L_BLK, slot_index): blocks of 2^bsh nodes, bmk = 2^bsh - 1
     int64_t idx_pitch;
     int64_t plane;         // nx * ny
     int64_t z0_offset;     // z0 * plane: cell address of node 0 (direct)
@@ -420,6 +421,28 @@ struct Node<A_INDIRECT, NEED> {
         }
     }
 };
+
+// ------------------------------------------------------------------ slots
+// Index of PDF slot (direction j, node or cell c) in a lattice buffer.
+//   AoS: c * 19 + j.
+//   SoA: j * pitch + c.
+//   Blocked SoA (indirect grids): ((c >> bsh) * 19 + j) * 2^bsh + (c & bmk).
+//     The 19 directions of a block of 2^bsh nodes lie in one contiguous
+//     region, so the gathers and scatters of a workgroup stay in a few DRAM
+//     pages instead of touching 19 arrays a lattice apart.
+template <int ADDR, int LAY>
+__device__ __forceinline__ int64_t slot_index(const KArgs &a, int j, int64_t c)
+{
+    if constexpr (LAY == L_AOS) {
+        return elem<L_AOS>(j, c, a.pitch);
+    } else if constexpr (LAY == L_BLK) {
+        // the node's part and the direction's part apart: j << bsh is uniform
+        const uint32_t u = (uint32_t)c;
+        return ((int64_t)((u >> a.bsh) * (uint32_t)Q) << a.bsh) + (int64_t)(u & a.bmk) + ((int64_t)j << a.bsh);
+    } else {
+        return elem<L_SOA>(j, c, a.pitch);
+    }
+}
 
 // ------------------------------------------------------------------ maps
 template <int R, class N>
@@ -1048,7 +1071,7 @@ __device__ __forceinline__ void update_node(const KArgs &a, uint32_t n)
     // nontemporal hint where every touched line is read or written whole by
     // this workgroup: direct SoA, and node-local kernels on indirect SoA grids
     constexpr bool local = (R == R_LOCAL && (W == W_LOCAL || W == W_AAEVEN));
-    constexpr bool NT = (LAY == L_SOA) && (ADDR == A_DIRECT || local);
+    constexpr bool NT = (LAY != L_AOS) && (ADDR == A_DIRECT || local);
     Node<ADDR, need_r(R) | need_w(W)> nd;
     nd.init(a, n);
     const st *src = static_cast<const st *>(a.src);
@@ -1060,7 +1083,7 @@ __device__ __forceinline__ void update_node(const KArgs &a, uint32_t n)
         int64_t c;
         gather_pin<ADDR, R>(nd, i);
         read_slot<R>(nd, i, j, c, bc);
-        v[i] = S::load(pdf_load<NT>(src + elem<LAY>(j, c, a.pitch)));
+        v[i] = S::load(pdf_load<NT>(src + slot_index<ADDR, LAY>(a, j, c)));
         gather_order<ADDR, R>();
     }
     bc_arrive_all<ADDR, R>(a, nd, v);
@@ -1079,7 +1102,7 @@ __device__ __forceinline__ void update_node(const KArgs &a, uint32_t n)
         if constexpr (ADDR == A_INDIRECT && (W == W_PUSH || W == W_ET0 || W == W_ET1)) {
             if (bc > 0 && a.bc_on) out = bc_arrive<ct>(a, bc, opp(i), out);
         }
-        pdf_store<NT>(dst + elem<LAY>(j, c, a.pitch), S::save(out));
+        pdf_store<NT>(dst + slot_index<ADDR, LAY>(a, j, c), S::save(out));
     }
 }
 
@@ -1280,7 +1303,7 @@ __global__ void __launch_bounds__(BLOCK) k_get(KArgs a)
         int64_t c;
         int bc;
         read_slot<R>(nd, i, j, c, bc);
-        double f = S::to_canon(src[elem<LAY>(j, c, a.pitch)], i, a.sigma);
+        double f = S::to_canon(src[slot_index<ADDR, LAY>(a, j, c)], i, a.sigma);
         if (bc > 0 && a.bc_on) f = bc_arrive_canon(a, bc, i, f);
         a.canon[(int64_t)i * a.n_nodes + n] = f;
     }
@@ -1304,7 +1327,7 @@ __global__ void __launch_bounds__(BLOCK) k_set(KArgs a)
         read_slot<R>(nd, i, j, c, bc);
         double f = a.canon_in[(int64_t)i * a.n_nodes + n];
         if (bc > 0 && a.bc_on) f = bc_depart_canon(a, bc, i, f);
-        dst[elem<LAY>(j, c, a.pitch)] = S::from_canon(f, i, a.sigma);
+        dst[slot_index<ADDR, LAY>(a, j, c)] = S::from_canon(f, i, a.sigma);
     }
 }
 
@@ -1335,7 +1358,7 @@ __global__ void __launch_bounds__(BLOCK) k_init(KArgs a)
         int64_t c;
         read_slot<R>(nd, i, j, c, bc);
         if (bc > 0 && a.bc_on) feq = bc_depart_canon(a, bc, i, feq);
-        dst[elem<LAY>(j, c, a.pitch)] = S::from_canon(feq, i, a.sigma);
+        dst[slot_index<ADDR, LAY>(a, j, c)] = S::from_canon(feq, i, a.sigma);
     }
 }
 
@@ -1385,7 +1408,7 @@ __device__ __forceinline__ void node_moments(const KArgs &a, uint32_t n, double 
         int64_t c;
         int bc;
         read_slot<R>(nd, i, j, c, bc);
-        double f = S::to_canon(src[elem<LAY>(j, c, a.pitch)], i, a.sigma);
+        double f = S::to_canon(src[slot_index<ADDR, LAY>(a, j, c)], i, a.sigma);
         if (bc > 0 && a.bc_on) f = bc_arrive_canon(can, a.bc_neg, bc, i, f);
         m[0] += f;
         if (cx(i) > 0) m[1] += f;
@@ -1414,15 +1437,15 @@ void launch_reduce_final(const double *partials, uint32_t n_blocks, double *out,
 using Launch = void (*)(const KArgs &, uint32_t, hipStream_t);
 
 struct PrecTable {
-    Launch update[2][2][2][K_NUM]; // [addr][layout][collider][kind]
+    Launch update[2][3][2][K_NUM]; // [addr][layout (L_SOA, L_AOS, L_BLK)][collider][kind]
     Launch pair[2][K_NUM];         // direct SoA, two nodes per lane: [collider][kind]
     Launch wide[2][K_NUM];         // direct SoA, one row segment per workgroup: [collider][kind]
     Launch pair_wide[2][K_NUM];    // direct SoA, two nodes per lane, 512-node row segments
     Launch gen[2][K_NUM];          // direct SoA, any other nx: shifts through LDS across rows
-    Launch get[2][2][R_NUM];
-    Launch set[2][2][R_NUM];
-    Launch init[2][2][R_NUM];
-    Launch reduce[2][2][R_NUM];
+    Launch get[2][3][R_NUM];
+    Launch set[2][3][R_NUM];
+    Launch init[2][3][R_NUM];
+    Launch reduce[2][3][R_NUM];
 };
 
 const PrecTable &table_f64();

@@ -77,7 +77,7 @@ extern "C" int lbm_reduce_moments_noalloc(lbm_grid *g, double *d_out4, void *str
     const uint32_t nb = node_blocks(g);
     // the same kernels and block shape as lbm_reduce_moments: every block
     // overwrites its partial, so nothing needs clearing between calls
-    table(g->d.precision).reduce[g->d.addressing][g->d.layout][state_rmap(g)](a, nb, s);
+    table(g->d.precision).reduce[g->d.addressing][kernel_layout(g)][state_rmap(g)](a, nb, s);
     launch_reduce_final(partials, nb, d_out4, s);
     return hip_check(hipGetLastError(), "lbm_reduce_moments_noalloc");
 }

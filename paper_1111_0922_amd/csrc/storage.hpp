@@ -16,7 +16,10 @@
 namespace lbm {
 
 enum Prec : int { P_F64 = 0, P_F32 = 1, P_F16S = 2, P_F32S = 3 };
-enum Lay : int { L_SOA = 0, L_AOS = 1 };
+// L_BLK: the blocked SoA order of indirect lattices (slot_index in kernels.hpp);
+// the public layouts are SoA and AoS, and an indirect SoA grid is stored as
+// L_SOA or L_BLK
+enum Lay : int { L_SOA = 0, L_AOS = 1, L_BLK = 2 };
 
 template <int P>
 struct Store;

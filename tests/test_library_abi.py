@@ -113,12 +113,16 @@ def test_option_ranges_without_gpu():
     ok = [(L.OPT_WG_LDS, -1), (L.OPT_WG_LDS, 0), (L.OPT_WG_LDS, 122880), (L.OPT_PAIR, -1), (L.OPT_PAIR, 1),
           (L.OPT_BAND, -1), (L.OPT_BAND, 4096), (L.OPT_ROW_STAGE, 0), (L.OPT_ROW_STAGE, 1),
           (L.OPT_SLAB_ORDER, -1), (L.OPT_SLAB_ORDER, 0), (L.OPT_SLAB_ORDER, 1),
-          (L.OPT_RANK_LOOKUP, -1), (L.OPT_RANK_LOOKUP, 0), (L.OPT_RANK_LOOKUP, 1)]
+          (L.OPT_RANK_LOOKUP, -1), (L.OPT_RANK_LOOKUP, 0), (L.OPT_RANK_LOOKUP, 1),
+          (L.OPT_SOA_BLOCK, -1), (L.OPT_SOA_BLOCK, 0), (L.OPT_SOA_BLOCK, 64), (L.OPT_SOA_BLOCK, 1024),
+          (L.OPT_SOA_BLOCK, 65536)]
     for opt, val in ok:
         g.set_option(opt, val)
     bad = [(L.OPT_WG_LDS, -2), (L.OPT_WG_LDS, 122881), (L.OPT_PAIR, 2), (L.OPT_PAIR, -2), (L.OPT_BAND, -2),
            (L.OPT_BAND, 4097), (L.OPT_PITCH_PAD, -1), (L.OPT_PITCH_PAD, (1 << 20) + 1), (99, 0),
-           (L.OPT_SLAB_ORDER, 2), (L.OPT_SLAB_ORDER, -2), (L.OPT_RANK_LOOKUP, 2), (L.OPT_RANK_LOOKUP, -2)]
+           (L.OPT_SLAB_ORDER, 2), (L.OPT_SLAB_ORDER, -2), (L.OPT_RANK_LOOKUP, 2), (L.OPT_RANK_LOOKUP, -2),
+           (L.OPT_SOA_BLOCK, 1), (L.OPT_SOA_BLOCK, 32), (L.OPT_SOA_BLOCK, 100), (L.OPT_SOA_BLOCK, 1 << 17),
+           (L.OPT_SOA_BLOCK, -2)]
     for opt, val in bad:
         with pytest.raises(P.LbmError):
             g.set_option(opt, val)
