@@ -33,11 +33,13 @@ using namespace lbm_host;
 // cap how many are resident per CU.  Measured on the 32 serving lattices
 // (graph runs): FP64 13.95 -> 14.61 GLUP/s with 64 KB (two per CU), FP32
 // 26.2 -> 27.05 with 40-52 KB; FP16 loses with any cap (34.1 -> 25.6 at
-// 40 KB).
-static uint32_t batch_lds(int32_t precision)
+// 40 KB).  When every slot of a launch takes its odd step, FP32 storage
+// reserves 32 KB (four per CU), as the single-lattice odd kernel with the
+// rank lookup prefers (512^3 pack: 2.29 against 2.45 ms at three per CU).
+static uint32_t batch_lds(int32_t precision, int parity)
 {
     if (precision == LBM_F64) return 65536;
-    if (precision == LBM_F32 || precision == LBM_F32S) return 53248;
+    if (precision == LBM_F32 || precision == LBM_F32S) return parity == 1 ? 32768 : 53248;
     return 0;
 }
 
@@ -319,6 +321,7 @@ struct lbm_batch {
     hipGraphExec_t exec = nullptr;
     int32_t graph_k = -1;
     uint32_t graph_blocks = 0;
+    int graph_parity = -2;   // common_parity the graph's launches were captured for
     double *graph_out = nullptr;
 };
 
@@ -389,11 +392,25 @@ int launch_coop(lbm_batch *b, int32_t k_steps, hipStream_t s)
 
 void launch_reduce_body(lbm_batch *b, int32_t k_steps, double *h_out, hipStream_t s);
 
+// Parity (t mod 2) shared by every active slot at the start of the run, or -1.
+int common_parity(const lbm_batch *b)
+{
+    int p = -2;
+    for (int32_t sl = 0; sl < b->max_slots; ++sl) {
+        if (!b->slots[sl].active) continue;
+        const int q = b->slots[sl].t0 & 1;
+        if (p == -2) p = q;
+        if (p != q) return -1;
+    }
+    return p < 0 ? -1 : p;
+}
+
 void launch_batch_body(lbm_batch *b, int32_t k_steps, double *h_out, hipStream_t s)
 {
     const uint32_t nb = batch_blocks(b);
-    const uint32_t lds = batch_lds(b->precision);
+    const int p0 = common_parity(b);
     for (int32_t k = 0; k < k_steps; ++k) {
+        const uint32_t lds = batch_lds(b->precision, p0 < 0 ? -1 : (p0 + k) & 1);
         if (b->precision == LBM_F64)
             hipLaunchKernelGGL(k_aa_batched<P_F64>, dim3(nb), dim3(BLOCK), lds, s, b->d_slots, b->d_tiles,
                                b->d_hdr, k, ws_base(b));
@@ -617,7 +634,8 @@ int lbm_batch_run(lbm_batch *b, int32_t k_steps, double *h_moments, int32_t use_
         if (rc) return rc;
         if (timed_out) return fail(LBM_E_HIP, "cooperative batch run: a grid barrier wait exceeded its bound");
     } else if (use_graph) {
-        if (!b->exec || b->graph_k != k_steps || b->graph_out != h_moments || b->graph_blocks != batch_blocks(b)) {
+        if (!b->exec || b->graph_k != k_steps || b->graph_out != h_moments || b->graph_blocks != batch_blocks(b) ||
+            b->graph_parity != common_parity(b)) {
             drop_graph(b);
             rc = hip_check(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed), "lbm_batch_run (capture)");
             if (rc) return rc;
@@ -632,6 +650,7 @@ int lbm_batch_run(lbm_batch *b, int32_t k_steps, double *h_moments, int32_t use_
             b->graph_k = k_steps;
             b->graph_out = h_moments;
             b->graph_blocks = batch_blocks(b);
+            b->graph_parity = common_parity(b);
         }
         rc = hip_check(hipGraphLaunch(b->exec, s), "lbm_batch_run (graph launch)");
         if (rc) return rc;
