@@ -111,16 +111,20 @@ PDF_SIZE = {"f64": 8, "f32": 4, "f16s": 2, "f32s": 4}
 IDX_BYTES = {"ts_step": 72, "os_push": 72, "os_pull": 72, "aa_even": 0, "aa_odd": 72, "et_even": 28, "et_odd": 28}
 
 
-def kernel_bytes(name, addressing, precision, nodes, rank=False, cells=0):
+def kernel_bytes(name, addressing, precision, nodes, rank=False, cells=0, et_rank=False):
     """Algorithmic HBM bytes of one launch (one step for ts_step): each PDF read and written once,
     no write-allocate, plus the IDX or esoteric-twist table entries an indirect kernel reads.  With
     neighbour ids looked up by rank, a kernel that reads them reads one 4-byte cell_of entry per node
-    instead of 18 IDX entries, and the 8-byte words of ceil(cells / 32) once."""
+    instead of 18 IDX entries, and the 8-byte words of ceil(cells / 32) once; the esoteric twist with
+    its table from the words reads 4 bytes per node and the fluid and ghost words (16 bytes per 32
+    cells) instead of its 28-byte table."""
     pdf = 2 * 19 * PDF_SIZE[precision] * (2 if name == "ts_step" else 1)
     if addressing != "indirect":
         return pdf * nodes
     if rank and IDX_BYTES[name] == 72:
         return (pdf + 4) * nodes + 8 * ((cells + 31) // 32)
+    if et_rank and name.startswith("et"):   # the table from the rank words and the ghost words
+        return (pdf + 4) * nodes + 16 * ((cells + 31) // 32)
     return (pdf + IDX_BYTES[name]) * nodes
 
 
@@ -152,6 +156,7 @@ def measure_row(P, torch, grid, scheme, addressing, precision, workload, steps=1
     GB/s of its algorithmic bytes and fraction of the HBM peak (plus the counters' bytes if current)."""
     nodes = grid.n_nodes
     rank = addressing == "indirect" and grid.rank_lookup
+    et_rank = addressing == "indirect" and grid.et_rank_lookup
     cells = int(np.prod(grid.shape))
     grid.step(warmup, collider=collider)
     torch.cuda.synchronize()
@@ -160,7 +165,8 @@ def measure_row(P, torch, grid, scheme, addressing, precision, workload, steps=1
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     mf = nodes * steps / dt / 1e6
-    bl = P.model_bytes(scheme, addressing, precision, model="gpu_rank" if rank else "gpu")
+    bl = P.model_bytes(scheme, addressing, precision,
+                       model="gpu_rank" if (et_rank if scheme == "et" else rank) else "gpu")
     row = {"MFLUP/s": round(mf, 1), "bytes_per_lup": bl, "neighbour_ids": "rank" if rank else "idx", "GB/s": round(mf * bl / 1e3, 1),
            "frac_hbm_wall": round(mf * bl / 1e3 / HBM_PEAK_GBS, 4), "kernels": {}}
     ms = per_launch_ms(torch, grid, launches, collider)
@@ -170,7 +176,7 @@ def measure_row(P, torch, grid, scheme, addressing, precision, workload, steps=1
         if name in row["kernels"]:
             continue
         t = float(np.mean([ms[p] for p in ms if STEP_KERNELS[scheme][p] == name]))
-        b = kernel_bytes(name, addressing, precision, nodes, rank, cells)
+        b = kernel_bytes(name, addressing, precision, nodes, rank, cells, et_rank)
         k = {"ms": round(t, 4), "algorithmic_bytes": int(b), "GB/s": round(b / (t * 1e-3) / 1e9, 1),
              "frac_hbm": round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         if COPY_GBS[0]:

@@ -201,8 +201,8 @@ int lbm_set_boundary(lbm_grid *g, int32_t cls, int32_t kind, double rho, const d
  *     20480 for the even kernel (two workgroups per CU) and 98304 for the
  *     odd kernel (one per CU).  Indirect SoA kernels that look neighbour ids
  *     up by rank (LBM_OPT_RANK_LOOKUP) use 32768 for the FP64 one-step pull
- *     and the FP32 AA odd kernel, 65536 for the other FP64 kernels; with
- *     IDX the FP64 one-step push uses 98304.
+ *     and the FP32 AA odd kernel, 45056 for the FP64 esoteric twist and 65536
+ *     for the other FP64 kernels; with IDX the FP64 one-step push uses 98304.
  *   LBM_OPT_ROW_STAGE (0/1, default 1): on a direct SoA grid the x-shifted
  *     PDFs move through LDS, so that all global accesses of a wavefront are
  *     aligned: a workgroup holds whole x-rows where nx is a power of two no
@@ -237,10 +237,14 @@ int lbm_set_boundary(lbm_grid *g, int32_t cls, int32_t kind, double rho, const d
  *     reading IDX: the id of a fluid cell is the number of fluid cells before
  *     it, found from the node's cell (4 bytes per node) and, per 32 cells, the
  *     fluid bits and the count before them (8 bytes, shared by the neighbours
- *     of all nodes there).  IDX moves 72 bytes per node.  Ignored where it
- *     does not apply (bricked numbering, open boundaries, direct grids).
+ *     of all nodes there).  IDX moves 72 bytes per node.  The esoteric
+ *     twist takes its six storage addresses and its solid mask from the same
+ *     words (and those of the ghost cells) instead of its 28-byte table.
+ *     Ignored where it does not apply (bricked numbering, open boundaries,
+ *     direct grids).
  *     The default is 1 on SoA grids with FP64, FP32 or FP32-shifted storage
- *     and 0 otherwise.
+ *     and 0 otherwise; by default the esoteric twist uses the words only with
+ *     FP64 storage (with 4-byte storage its table measured faster).
  *   LBM_OPT_SOA_BLOCK (-1 = default, 0, or a power of two in [64, 65536]
  *     nodes): storage order of the SoA lattices of an indirect grid.  0 is
  *     plain SoA: slot (direction j, node n) at j * pitch + n.  B > 0 cuts the
@@ -314,7 +318,9 @@ int lbm_query_sizes(const lbm_grid *g, int32_t scheme, lbm_sizes *out);
  *      cell_of[idx_pitch] (the cell x + nx (y + ny z) of every node), then per
  *      32 cells w = 0 .. ceil(n_cells / 32) - 1 a pair of uint32: bit k set
  *      when cell 32 w + k is fluid, and the fluid id of the word's first fluid
- *      cell (0 when it has none).  Asynchronous.
+ *      cell (0 when it has none); with et_ghosts, after those words (rounded
+ *      up to 256 bytes), the same pairs for the ghost cells (ghost bits, ghost
+ *      number of the group's first ghost).  Asynchronous.
  * d_mask is read by both calls.  d_scratch: build_scratch_bytes of device
  * memory.  Errors: LBM_E_STATE on a direct grid or when call 2 precedes call
  * 1; LBM_E_ARG for a missing d_cellmap, or a missing d_mask (either call) or
@@ -495,13 +501,17 @@ int lbm_stream_copy(const void *d_src, void *d_dst, int64_t bytes, void *stream)
  * (LBM_OPT_RANK_LOOKUP): one 4-byte cell_of entry per node update of a kernel
  * that reads neighbour ids instead of 18 IDX entries (each such launch also
  * reads the 8-byte words of ceil(n_cells / 32), not counted here as they are
- * not per node).  Returns < 0 for combinations the model does not cover. */
+ * not per node); for the esoteric twist, one cell_of entry in place of its
+ * seven table entries.  Returns < 0 for combinations the model does not
+ * cover. */
 double lbm_model_bytes(int32_t scheme, int32_t addressing, int32_t precision, int32_t model);
 
-/* 1 when the bound grid's kernels that read neighbour ids look them up by
- * rank (LBM_OPT_RANK_LOOKUP in effect: option, numbering, boundary classes),
- * 0 when they read IDX or the grid is direct; LBM_E_ARG for a null grid,
- * LBM_E_STATE before lbm_bind.  No paper passage: reports a launch choice. */
+/* Bit 0 set when the bound grid's kernels that read neighbour ids look them
+ * up by rank (LBM_OPT_RANK_LOOKUP in effect: option, numbering, boundary
+ * classes), bit 1 when the esoteric twist takes its storage addresses from
+ * the same words; 0 when they read IDX and the ET table, or the grid is
+ * direct.  LBM_E_ARG for a null grid, LBM_E_STATE before lbm_bind.  No paper
+ * passage: reports a launch choice. */
 int lbm_rank_lookup_active(const lbm_grid *g);
 
 #ifdef __cplusplus

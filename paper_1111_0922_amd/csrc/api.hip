@@ -200,11 +200,15 @@ static void set_residency(const lbm_grid *g, KArgs &a, int kind)
     // pack: FP32 AA odd at four workgroups per CU 2.29 ms against 2.45 at
     // three (the FP32 base); FP64 one-step pull 3.32 at four against 3.47 at
     // two; FP64 one-step push 4.37 at two against 4.90 at one (its IDX
-    // setting below).  The other FP64 kernels stay at two.
+    // setting below); FP64 esoteric twist 4.53 at three against 4.65 at two.
+    // The other FP64 kernels stay at two.
     if (a.rank_words && g->d.layout == LBM_SOA) {
         const bool p32 = g->d.precision == LBM_F32 || g->d.precision == LBM_F32S;
         if (p32 && kind == K_AA_ODD) a.lds_bytes = 32768;
-        if (g->d.precision == LBM_F64) a.lds_bytes = kind == K_OS_PULL ? 32768 : 65536;
+        if (g->d.precision == LBM_F64) {
+            a.lds_bytes = kind == K_OS_PULL ? 32768 : 65536;
+            if (a.ghost_words && (kind == K_ET0 || kind == K_ET1)) a.lds_bytes = 45056;
+        }
         return;
     }
     if (g->d.precision != LBM_F64) return;
@@ -295,6 +299,10 @@ KArgs base_args(const lbm_grid *g)
     if (g->rank_words && (g->rank > 0 || (g->rank < 0 && rank_default)) && !a.bc_on) {
         a.cell_of = g->cell_of;
         a.rank_words = g->rank_words;
+        // the esoteric twist's table from the same words: by default for FP64 only
+        // (512^3 pack, per launch: FP64 4.74 -> 4.53 ms at three workgroups per CU;
+        // FP32 2.45 -> 2.63-2.85, slower)
+        if (g->rank > 0 || d.precision == LBM_F64) a.ghost_words = g->ghost_words;
     }
     a.bc_neg = 0;
     for (int c = 0; c < 4; ++c) {
@@ -517,7 +525,8 @@ int lbm_query_sizes(const lbm_grid *g, int32_t scheme, lbm_sizes *out)
         // the 18 IDX rows, then the XCD slab block order (one entry per node block),
         // then (lexicographic numbering) cell_of and the rank words
         out->idx_bytes = rank_offset(g);
-        if (lexicographic(g)) out->idx_bytes += out->idx_pitch * 4 + round_up(rank_words_count(g) * 8, 256);
+        if (lexicographic(g))
+            out->idx_bytes += out->idx_pitch * 4 + round_up(rank_words_count(g) * 8, 256) * (d.et_ghosts ? 2 : 1);
         if (scheme == LBM_ET) out->aux_bytes = 7 * out->idx_pitch * 4;
     }
     const int64_t ns = storage_nodes(g, scheme);
@@ -609,6 +618,9 @@ int lbm_build_idx(lbm_grid *g, const uint8_t *d_mask, int32_t *d_cellmap, int32_
         b.cell_of = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(d_idx) + rank_offset(g));
         b.rank_words = reinterpret_cast<uint2 *>(b.cell_of + idx_pitch_of(g));
         b.n_words = (uint32_t)rank_words_count(g);
+        if (g->d.et_ghosts)
+            b.ghost_words = reinterpret_cast<uint2 *>(reinterpret_cast<char *>(b.rank_words) +
+                                                      round_up(rank_words_count(g) * 8, 256));
     }
     launch_idx_phase2(b, s);
     int rc = hip_check(hipGetLastError(), "index build (fill pass)");
@@ -644,9 +656,13 @@ int lbm_bind(lbm_grid *g, int32_t scheme, void *d_pdf0, void *d_pdf1, const int3
     g->slab_table = (ind && g->order_built) ? reinterpret_cast<const uint32_t *>(d_idx + 18 * idx_pitch_of(g)) : nullptr;
     g->cell_of = nullptr;
     g->rank_words = nullptr;
+    g->ghost_words = nullptr;
     if (ind && g->rank_built) {
         g->cell_of = reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(d_idx) + rank_offset(g));
         g->rank_words = reinterpret_cast<const uint2 *>(g->cell_of + idx_pitch_of(g));
+        if (g->d.et_ghosts)
+            g->ghost_words = reinterpret_cast<const uint2 *>(reinterpret_cast<const char *>(g->rank_words) +
+                                                             round_up(rank_words_count(g) * 8, 256));
     }
     g->aux = (ind && scheme == LBM_ET) ? d_aux : nullptr;
     g->scratch = static_cast<double *>(d_scratch);
@@ -813,7 +829,7 @@ double lbm_model_bytes(int32_t scheme, int32_t addressing, int32_t precision, in
         case LBM_OS_PUSH:
         case LBM_OS_PULL: pdfs = 2 * q; idxs = nb; break;
         case LBM_AA: pdfs = 2 * q; idxs = nb / 2.0; break;        // on odd steps, none on even
-        case LBM_ET: pdfs = 2 * q; idxs = 7; break;               // six storage addresses + solid mask
+        case LBM_ET: pdfs = 2 * q; idxs = model == 1 ? 7 : 1; break; // six storage addresses + solid mask
         default: return -1.0;
         }
         return pdfs * s + (ind ? idxs * 4.0 : 0.0);
@@ -825,7 +841,8 @@ int lbm_rank_lookup_active(const lbm_grid *g)
 {
     if (!g) return fail(LBM_E_ARG, "null grid");
     if (g->scheme < 0) return fail(LBM_E_STATE, "no buffers bound (call lbm_bind)");
-    return base_args(g).rank_words ? 1 : 0;
+    const KArgs a = base_args(g);
+    return (a.rank_words ? 1 : 0) | (a.ghost_words ? 2 : 0);
 }
 
 } // extern "C"

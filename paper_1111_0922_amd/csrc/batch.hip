@@ -113,6 +113,7 @@ __device__ __forceinline__ KArgs slot_args(const SlotDesc &sd, char *base)
     a.et = nullptr;
     a.cell_of = nullptr;
     a.rank_words = nullptr;
+    a.ghost_words = nullptr;
     if (sd.rank_on) {
         a.cell_of = reinterpret_cast<const uint32_t *>(base + sd.cell_off);
         a.rank_words = reinterpret_cast<const uint2 *>(base + sd.words_off);

@@ -274,7 +274,8 @@ __global__ void __launch_bounds__(BLOCK) k_idx_fill(BuildArgs b)
 // Rank words (one thread per 32 cells): bit k set when cell 32 w + k is
 // fluid, and the fluid id of the word's first fluid cell, which in the
 // lexicographic numbering is the number of fluid cells before the word (0
-// for a word without fluid cells, whose rank is never read).
+// for a word without fluid cells, whose rank is never read); likewise for
+// the ghost cells of the esoteric twist.
 __global__ void __launch_bounds__(BLOCK) k_rank_words(BuildArgs b)
 {
     const uint32_t w = blockIdx.x * BLOCK + threadIdx.x;
@@ -285,6 +286,14 @@ __global__ void __launch_bounds__(BLOCK) k_rank_words(BuildArgs b)
         if (!b.mask[c0 + k]) bits |= 1u << k;
     const uint32_t rank = bits ? (uint32_t)b.cellmap[c0 + (uint32_t)__ffs(bits) - 1u] : 0u;
     b.rank_words[w] = make_uint2(bits, rank);
+    // ghost cells (cellmap -2 - k for ghost k, numbered in the same order)
+    if (b.ghost_words) {
+        uint32_t gbits = 0;
+        for (uint32_t k = 0; k < 32u && c0 + k < b.n_cells; ++k)
+            if (b.cellmap[c0 + k] <= -2) gbits |= 1u << k;
+        const uint32_t grank = gbits ? (uint32_t)(-2 - b.cellmap[c0 + (uint32_t)__ffs(gbits) - 1u]) : 0u;
+        b.ghost_words[w] = make_uint2(gbits, grank);
+    }
 }
 
 // Block order from the slab keys (one workgroup).  Workgroup b runs on XCD

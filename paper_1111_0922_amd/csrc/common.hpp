@@ -38,6 +38,7 @@ struct BuildArgs {
     // cell of every node, and per 32 cells the fluid bits and the fluid count before
     uint32_t *cell_of;    // [idx_pitch]
     uint2 *rank_words;    // [n_words]
+    uint2 *ghost_words;   // [n_words] with et_on: per 32 cells the ghost bits and the ghost count before, or null
     uint32_t n_words;     // ceil(n_cells / 32)
 };
 

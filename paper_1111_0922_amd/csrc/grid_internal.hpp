@@ -38,6 +38,7 @@ struct lbm_grid {
     bool rank_built = false;              // lbm_build_idx wrote cell_of and the rank words after the block order
     const uint32_t *cell_of = nullptr;    // those arrays in the bound IDX buffer
     const uint2 *rank_words = nullptr;
+    const uint2 *ghost_words = nullptr;   // with et_ghosts, after the rank words
     int rank = -1;                        // LBM_OPT_RANK_LOOKUP: 1 on, 0 off, -1 default
     int64_t soa_block = -1;               // LBM_OPT_SOA_BLOCK: nodes per block of an indirect SoA lattice (0 plain, -1 default)
     // open-boundary classes 1..4 (indirect grids): kind, density, velocity

@@ -117,6 +117,7 @@ struct KArgs {
     // number of fluid cells before the word (rank_neighbours).
     const uint32_t *cell_of;   // [idx_pitch]
     const uint2 *rank_words;   // [ceil(n_cells / 32)]
+    const uint2 *ghost_words;  // esoteric twist: per 32 cells the ghost bits and the ghost count before, or null
     int64_t pitch;         // SoA elements between direction arrays
     uint32_t bsh, bmk;     // blocked SoA (L_BLK, slot_index): blocks of 2^bsh nodes, bmk = 2^bsh - 1
     int64_t idx_pitch;
@@ -348,6 +349,53 @@ __device__ __forceinline__ void rank_neighbours(const KArgs &k, uint32_t n, int3
     }
 }
 
+// The esoteric twist's storage addresses and solid mask of node n from the
+// rank words (the ET table's contents): e[k] is the storage entry of cell
+// x + o_k for the six offsets of et_cell (the fluid id, or N_f + the ghost
+// number of a solid storage cell, from the ghost words), and bit i - 1 of
+// mask is set when x + c_i is not fluid.  Reads 4 bytes per node where the
+// table reads 28.
+__device__ __forceinline__ void rank_et(const KArgs &k, uint32_t n, int32_t (&e)[6], uint32_t &mask)
+{
+    const uint32_t c = k.cell_of[n];
+    const uint32_t nx = (uint32_t)k.nx, ny = (uint32_t)k.ny, nz = (uint32_t)k.nz, pl = (uint32_t)k.plane;
+    const uint32_t q = fdiv(c, k.dvx);
+    const uint32_t x = c - q * nx;
+    const uint32_t z = fdiv(q, k.dvy);
+    const uint32_t y = q - z * ny;
+    const uint32_t px[3] = {x == 0 ? nx - 1 : x - 1, x, x + 1 == nx ? 0 : x + 1};
+    const uint32_t py[3] = {(y == 0 ? ny - 1 : y - 1) * nx, y * nx, (y + 1 == ny ? 0 : y + 1) * nx};
+    const uint32_t pz[3] = {(z == 0 ? nz - 1 : z - 1) * pl, z * pl, (z + 1 == nz ? 0 : z + 1) * pl};
+    // directions of the six storage cells x + ex, ey, ez, ex+ey, ex+ez, ey+ez
+    constexpr int dir[6] = {1, 3, 5, 7, 11, 15};
+    uint32_t cc[18];
+    uint2 w[18], gw[6];
+#pragma unroll
+    for (int j = 0; j < 18; ++j) {
+        const int i = j + 1;
+        cc[j] = px[cx(i) + 1] + py[cy(i) + 1] + pz[cz(i) + 1];
+        w[j] = k.rank_words[cc[j] >> 5];
+    }
+#pragma unroll
+    for (int t = 0; t < 6; ++t) gw[t] = k.ghost_words[cc[dir[t] - 1] >> 5];
+    // every word in flight before the first is used (as in rank_neighbours)
+#pragma unroll
+    for (int j = 0; j < 18; ++j) asm volatile("" : "+v"(w[j].x), "+v"(w[j].y));
+#pragma unroll
+    for (int t = 0; t < 6; ++t) asm volatile("" : "+v"(gw[t].x), "+v"(gw[t].y));
+    mask = 0;
+#pragma unroll
+    for (int j = 0; j < 18; ++j) mask |= (((w[j].x >> (cc[j] & 31u)) & 1u) ^ 1u) << j;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+        const int j = dir[t] - 1;
+        const uint32_t b = cc[j] & 31u, below = (1u << b) - 1u;
+        const uint32_t fid = w[j].y + (uint32_t)__popc(w[j].x & below);
+        const uint32_t gid = k.n_nodes + gw[t].y + (uint32_t)__popc(gw[t].x & below);
+        e[t] = (int32_t)(((w[j].x >> b) & 1u) ? fid : gid);
+    }
+}
+
 // Indirect addressing (Sec. 1): node ids of fluid nodes; neighbours from
 // IDX (-1 = wall, -1 - c = open-boundary class c) or by rank; the esoteric
 // twist reads its storage addresses and the solid-neighbour mask from the ET
@@ -371,9 +419,13 @@ struct Node<A_INDIRECT, NEED> {
             }
         }
         if constexpr ((NEED & NEED_ET) != 0) {
+            if (k.rank_words && k.ghost_words) {
+                rank_et(k, n, e, mask);
+            } else {
 #pragma unroll
-            for (int q = 0; q < 6; ++q) e[q] = k.et[(int64_t)q * k.idx_pitch + n];
-            mask = (uint32_t)k.et[6 * k.idx_pitch + n];
+                for (int q = 0; q < 6; ++q) e[q] = k.et[(int64_t)q * k.idx_pitch + n];
+                mask = (uint32_t)k.et[6 * k.idx_pitch + n];
+            }
         }
     }
     __device__ __forceinline__ int64_t nb(int i) const { return m[i - 1]; }

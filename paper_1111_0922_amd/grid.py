@@ -116,7 +116,14 @@ class Grid:
         """Whether the bound grid's neighbour-reading kernels look ids up by rank (LBM_OPT_RANK_LOOKUP)."""
         rc = self.lib.lbm_rank_lookup_active(self._h)
         L.check(min(rc, 0))
-        return rc == 1
+        return bool(rc & 1)
+
+    @property
+    def et_rank_lookup(self) -> bool:
+        """Whether the esoteric twist takes its storage addresses from the rank words."""
+        rc = self.lib.lbm_rank_lookup_active(self._h)
+        L.check(min(rc, 0))
+        return bool(rc & 2)
 
     def set_option(self, option, value):
         L.check(self.lib.lbm_set_option(self._h, int(option), int(value)))

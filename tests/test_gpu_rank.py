@@ -58,11 +58,41 @@ def test_rank_arrays_follow_the_oracle_numbering(shape, r, phi, seed):
     assert np.array_equal(words[:, 1].astype(np.int64), want_rank.astype(np.int64))
 
 
+OFFS = [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (1, 0, 1), (0, 1, 1)]
+
+
+@pytest.mark.parametrize("shape,r,phi,seed", [((40, 37, 33), 4, 0.5, 1), ((7, 1, 45), 1, 0.5, 3)])
+def test_ghost_words_follow_the_ghost_numbering(shape, r, phi, seed):
+    """With et_ghosts, the ghost words after the rank words: bit k of word w set iff cell 32 w + k is a
+    ghost (a solid cell s with s - o fluid for one of the esoteric twist's six offsets o), and the ghost
+    number of the word's first ghost (ghosts numbered in lexicographic order)."""
+    solid = lbm_inputs.sphere_pack(shape, r, phi, seed=seed)[0]
+    grid = make_grid(solid, "et", addressing="indirect")
+    s = grid.sizes("et")
+    nb = (grid.n_nodes + 255) // 256
+    nw = (s.n_cells + 31) // 32
+    off = 18 * s.idx_pitch + (nb * 4 + 255) // 256 * 64 + s.idx_pitch + (nw * 8 + 255) // 256 * 64
+    words = grid.idx.view(-1)[off: off + 2 * nw].cpu().numpy().view(np.uint32).reshape(nw, 2)
+    fluid = solid == 0
+    ghost = np.zeros_like(fluid)
+    for o in OFFS:
+        ghost |= (solid != 0) & np.roll(fluid, (o[2], o[1], o[0]), axis=(0, 1, 2))
+    assert int(ghost.sum()) == s.n_ghost
+    g = np.zeros(32 * nw, np.uint64)
+    g[: solid.size] = ghost.reshape(-1)
+    g = g.reshape(nw, 32)
+    assert np.array_equal(words[:, 0].astype(np.uint64), (g << np.arange(32, dtype=np.uint64)).sum(axis=1))
+    before = np.concatenate([[0], np.cumsum(g.sum(axis=1))[:-1]]).astype(np.int64)
+    want = np.where(g.any(axis=1), before, 0)
+    assert np.array_equal(words[:, 1].astype(np.int64), want)
+
+
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 @pytest.mark.parametrize("layout", ["soa", "aos"])
-@pytest.mark.parametrize("scheme", ["aa", "ts", "os_push", "os_pull"])
+@pytest.mark.parametrize("scheme", ["aa", "ts", "os_push", "os_pull", "et"])
 def test_rank_lookup_gives_the_idx_bits(scheme, layout, precision):
-    """7 steps (AA ends in its odd-t state, read out through the gathering map), moments included."""
+    """7 steps (AA and ET end in their odd-t state, read out through the gathering map), moments
+    included; the esoteric twist takes its storage addresses and solid mask from the same words."""
     import paper_1111_0922_amd as P
     solid = lbm_inputs.sphere_pack((45, 38, 29), 4, 0.55, seed=51)[0]
     ru = lbm_inputs.rho_u_field(solid.shape, lbm_inputs.velocity_noise(solid.shape, 1e-3, seed=52))
@@ -72,6 +102,7 @@ def test_rank_lookup_gives_the_idx_bits(scheme, layout, precision):
     out = []
     for rank in (0, 1):
         grid.set_option(P._lib.OPT_RANK_LOOKUP, rank)
+        assert grid.rank_lookup == bool(rank) and grid.et_rank_lookup == bool(rank and scheme == "et")
         grid.set_pdfs(to_device(f0))
         grid.step(7)
         out.append((from_device(grid.get_pdfs()), from_device(grid.moments())))

@@ -65,7 +65,7 @@ def test_gpu_transfer_model():
         assert P.model_bytes("ts", "indirect", prec, model="gpu_rank") == 4 * q * s + 4
         assert P.model_bytes("os_pull", "indirect", prec, model="gpu_rank") == 2 * q * s + 4
         assert P.model_bytes("aa", "indirect", prec, model="gpu_rank") == 2 * q * s + 2
-        assert P.model_bytes("et", "indirect", prec, model="gpu_rank") == 2 * q * s + 28
+        assert P.model_bytes("et", "indirect", prec, model="gpu_rank") == 2 * q * s + 4
         assert P.model_bytes("aa", "direct", prec, model="gpu_rank") == 2 * q * s
 
 
