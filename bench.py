@@ -62,10 +62,13 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def channel_grid(P, torch, n, scheme, layout, precision="f64"):
+def channel_grid(P, torch, n, scheme, layout, precision="f64", block=None):
+    """The n^3 channel bound to `scheme`, velocity-noise start; `block` sets LBM_OPT_SOA_BLOCK."""
     import lbm_inputs
     grid = P.Grid(n, n, n, layout=layout, precision=precision, wall_z=True, omega=1.6, g=(1e-6, 0.0, 0.0),
                   f16_scale=1024.0)
+    if block is not None:
+        grid.set_option(P._lib.OPT_SOA_BLOCK, block)
     grid.bind(scheme)
     nf = grid.n_nodes
     u = torch.from_numpy(lbm_inputs.velocity_noise((n - 2, n, n), 1e-3, seed=1).reshape(3, -1))
@@ -167,7 +170,9 @@ def measure_row(P, torch, grid, scheme, addressing, precision, workload, steps=1
     mf = nodes * steps / dt / 1e6
     bl = P.model_bytes(scheme, addressing, precision,
                        model="gpu_rank" if (et_rank if scheme == "et" else rank) else "gpu")
-    row = {"MFLUP/s": round(mf, 1), "bytes_per_lup": bl, "neighbour_ids": "rank" if rank else "idx", "GB/s": round(mf * bl / 1e3, 1),
+    blk = grid.lattice_block
+    row = {"MFLUP/s": round(mf, 1), "bytes_per_lup": bl, "neighbour_ids": "rank" if rank else "idx",
+           "storage": (f"{layout} in blocks of {blk}" if blk else layout), "GB/s": round(mf * bl / 1e3, 1),
            "frac_hbm_wall": round(mf * bl / 1e3 / HBM_PEAK_GBS, 4), "kernels": {}}
     ms = per_launch_ms(torch, grid, launches, collider)
     fr = []
@@ -625,6 +630,12 @@ def main():
             del g
             torch.cuda.empty_cache()
             log(f"[bench]   {key}: {table[key]['MFLUP/s']:.0f} MFLUP/s, slowest kernel {table[key]['frac_hbm']:.3f} of HBM")
+        # the AA pattern (plain SoA above, as the headline) with its lattice in 1024-cell blocks
+        g = channel_grid(P, torch, n, "aa", "soa", block=1024)
+        table["aa/soa_blocked"] = measure_row(P, torch, g, "aa", "direct", "f64", "channel256", steps=100)
+        del g
+        torch.cuda.empty_cache()
+        log(f"[bench]   aa/soa_blocked: {table['aa/soa_blocked']['MFLUP/s']:.0f} MFLUP/s")
         # the paper's collision (TRT, Lambda = 3/16) on the same kernels
         g = channel_grid(P, torch, n, "aa", "soa")
         table["aa/soa/trt"] = measure_row(P, torch, g, "aa", "direct", "f64", "channel256", collider="trt", steps=200)

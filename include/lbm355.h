@@ -245,15 +245,19 @@ int lbm_set_boundary(lbm_grid *g, int32_t cls, int32_t kind, double rho, const d
  *     The default is 1 on SoA grids with FP64, FP32 or FP32-shifted storage
  *     and 0 otherwise; by default the esoteric twist uses the words only with
  *     FP64 storage (with 4-byte storage its table measured faster).
- *   LBM_OPT_SOA_BLOCK (-1 = default, 0, or a power of two in [64, 65536]
- *     nodes): storage order of the SoA lattices of an indirect grid.  0 is
- *     plain SoA: slot (direction j, node n) at j * pitch + n.  B > 0 cuts the
- *     nodes into blocks of B, each holding its 19 directions one after the
- *     other: slot (j, n) at ((n / B) * 19 + j) * B + n mod B, so that a
- *     workgroup's accesses stay in a few memory pages.  Ignored on direct
- *     and AoS grids.  Changes the lattice layout and sizes: the grid must be
- *     bound again afterwards.  The default is 1024 for FP64 storage and 0
- *     for the others.
+ *   LBM_OPT_SOA_BLOCK (-1 = default, 0, or a power of two in [64, 65536]):
+ *     storage order of SoA lattices.  0 is plain SoA: slot (direction j,
+ *     node n) at j * pitch + n, n the fluid id (indirect) or the cell index
+ *     (direct).  B > 0 cuts the nodes into blocks of B, each holding its 19
+ *     directions one after the other: slot (j, n) at ((n / B) * 19 + j) * B +
+ *     n mod B, so that a workgroup's accesses stay in a few memory pages.
+ *     Ignored on AoS grids; on a direct grid it disables the two-nodes-per-
+ *     lane kernels (LBM_OPT_PAIR).  Changes the lattice layout and sizes:
+ *     the grid must be bound again afterwards.  The default is 1024 for FP64
+ *     storage on indirect grids, 1024 for the two-step, one-step and
+ *     esoteric-twist schemes with FP64, FP32 or FP32-shifted storage on
+ *     direct grids, and 0 otherwise (the AA pattern on direct grids keeps
+ *     plain SoA).
  * Errors: LBM_E_ARG for an unknown option or a value out of range. */
 enum {
     LBM_OPT_XCD_REMAP = 1,
@@ -513,6 +517,12 @@ double lbm_model_bytes(int32_t scheme, int32_t addressing, int32_t precision, in
  * direct.  LBM_E_ARG for a null grid, LBM_E_STATE before lbm_bind.  No paper
  * passage: reports a launch choice. */
 int lbm_rank_lookup_active(const lbm_grid *g);
+
+/* Nodes per block of the bound grid's SoA lattices (LBM_OPT_SOA_BLOCK in
+ * effect for the bound scheme), 0 for plain SoA or an AoS grid.  LBM_E_ARG
+ * for a null grid, LBM_E_STATE before lbm_bind.  No paper passage: reports
+ * the storage order of this library's lattices. */
+int lbm_lattice_block(const lbm_grid *g);
 
 #ifdef __cplusplus
 }

@@ -61,7 +61,7 @@ EXPORTS = [
     "lbm_set_boundary",
     "lbm_set_option", "lbm_set_block_order", "lbm_query_sizes", "lbm_build_idx", "lbm_bind", "lbm_set_pdfs", "lbm_get_pdfs",
     "lbm_init_equilibrium", "lbm_step", "lbm_time", "lbm_reduce_moments", "lbm_reduce_moments_noalloc", "lbm_stream_copy", "lbm_model_bytes",
-    "lbm_rank_lookup_active",
+    "lbm_rank_lookup_active", "lbm_lattice_block",
     "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_destroy", "lbm_batch_add", "lbm_batch_remove",
     "lbm_batch_run", "lbm_batch_sync", "lbm_batch_moments",
 ]
@@ -110,6 +110,7 @@ def load():
     lib.lbm_model_bytes.argtypes = [i32, i32, i32, i32]
     lib.lbm_model_bytes.restype = dbl
     lib.lbm_rank_lookup_active.argtypes = [gp]
+    lib.lbm_lattice_block.argtypes = [gp]
     lib.lbm_batch_workspace_bytes.argtypes = [i32, i64, ctypes.POINTER(i64)]
     lib.lbm_batch_create.argtypes = [i32, i64, i32, vp, ctypes.POINTER(gp)]
     lib.lbm_batch_destroy.argtypes = [gp]

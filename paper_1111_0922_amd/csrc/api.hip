@@ -73,17 +73,31 @@ bool lexicographic(const lbm_grid *g)
 
 int64_t rank_words_count(const lbm_grid *g) { return (g->n_cells + 31) / 32; }
 
-// log2 of the nodes per block of an indirect SoA lattice (slot_index), 0 for plain SoA.
-// Default: blocks of 1024 nodes for FP64.  Measured per launch on the 512^3 pack
-// (plain -> 1024): AA even 2.76-2.79 -> 2.60 ms, odd 3.85-3.88 -> 3.75, two-step
-// 6.18 -> 5.72-5.76 per step, one-step pull 3.12-3.30 -> 3.06-3.10; one-step push
-// and the esoteric twist within their run-to-run spread.  FP32, FP32-shifted and
-// FP16 storage gain nothing overall (AA FP32 even 1.32-1.40 -> 1.24, odd
-// 2.13-2.28 -> 2.24) and stay plain.
-int soa_block_shift(const lbm_grid *g)
+// log2 of the nodes per block of a SoA lattice of `scheme` (slot_index, L_BLK), 0
+// for plain SoA.  Defaults (blocks of 1024 nodes or cells where measured faster):
+//  - indirect grids, FP64, every scheme.  512^3 pack, per launch (plain ->
+//    1024): AA even 2.76-2.79 -> 2.60 ms, odd 3.85-3.88 -> 3.75, two-step 6.18
+//    -> 5.72-5.76 per step, one-step pull 3.12-3.30 -> 3.06-3.10; one-step push
+//    and the esoteric twist within their run-to-run spread.  FP32, FP32-shifted
+//    and FP16 storage gain nothing overall and stay plain (AA FP32: even
+//    1.32-1.40 -> 1.24 ms, odd 2.13-2.28 -> 2.24);
+//  - direct grids, FP64, FP32 and FP32-shifted storage, the two-step, one-step
+//    and esoteric-twist schemes.  256^3 channel, FP64 (FP32): two-step 1.67 ->
+//    1.58 ms per step (0.84 -> 0.80), one-step push 0.88 -> 0.85 (0.425 ->
+//    0.406), pull 0.84 -> 0.805 (0.43 -> 0.41), esoteric twist 0.86 -> 0.82
+//    (0.43 -> 0.40).  The AA pattern stays plain SoA: its odd kernel reads the
+//    rows y +- 1 of a direction, which plain SoA keeps 2 KB apart in one array
+//    (FP64 even 0.83 -> 0.78 ms, odd 0.85-0.86 -> 0.85-0.89 over runs on
+//    different boxes; FP32 odd 0.42-0.43 -> 0.47).
+// Pairs of nodes per lane (16-bit storage) need plain SoA.
+int soa_block_shift(const lbm_grid *g, int scheme)
 {
-    if (g->d.addressing != LBM_INDIRECT || g->d.layout != LBM_SOA) return 0;
-    const int64_t b = g->soa_block >= 0 ? g->soa_block : (g->d.precision == LBM_F64 ? 1024 : 0);
+    if (g->d.layout != LBM_SOA) return 0;
+    const bool ind = g->d.addressing == LBM_INDIRECT;
+    const int p = g->d.precision;
+    int64_t def = 0;
+    if (ind ? p == LBM_F64 : (scheme != LBM_AA && (p == LBM_F64 || p == LBM_F32 || p == LBM_F32S))) def = 1024;
+    const int64_t b = g->soa_block >= 0 ? g->soa_block : def;
     int sh = 0;
     while (((int64_t)1 << sh) < b) ++sh;
     return b > 0 ? sh : 0;
@@ -114,7 +128,7 @@ int64_t idx_pitch_of(const lbm_grid *g) { return round_up(g->n_nodes > 0 ? g->n_
 uint32_t node_blocks(const lbm_grid *g) { return (uint32_t)((g->n_nodes + BLOCK - 1) / BLOCK); }
 
 // storage order the kernels are instantiated for: L_SOA, L_AOS, or L_BLK for a blocked indirect SoA lattice
-int kernel_layout(const lbm_grid *g) { return soa_block_shift(g) ? L_BLK : g->d.layout; }
+int kernel_layout(const lbm_grid *g) { return soa_block_shift(g, g->scheme) ? L_BLK : g->d.layout; }
 
 // byte offset of cell_of in the IDX buffer: after the 18 IDX rows and the slab block order
 int64_t rank_offset(const lbm_grid *g) { return 18 * idx_pitch_of(g) * 4 + round_up((int64_t)node_blocks(g) * 4, 256); }
@@ -233,7 +247,7 @@ KArgs base_args(const lbm_grid *g)
     a.idx = g->idx;
     a.et = g->aux;
     a.pitch = g->pitch;
-    const int bsh = soa_block_shift(g);
+    const int bsh = soa_block_shift(g, g->scheme);
     a.bsh = (uint32_t)bsh;
     a.bmk = (1u << bsh) - 1u;
     a.idx_pitch = idx_pitch_of(g);
@@ -272,7 +286,7 @@ KArgs base_args(const lbm_grid *g)
     // two nodes per lane: nx a power of two dividing 2 * BLOCK (whole rows) or
     // a multiple of 2 * BLOCK (512-node row segments); by default for 16-bit
     // storage (measured below for the others)
-    const bool pair_on = g->pair > 0 || (g->pair < 0 && d.precision == LBM_F16S);
+    const bool pair_on = (g->pair > 0 || (g->pair < 0 && d.precision == LBM_F16S)) && bsh == 0;
     a.pair = 0;
     if (d.addressing == LBM_DIRECT && d.layout == LBM_SOA && pair_on) {
         if (d.nx >= 2 && d.nx <= 2 * BLOCK && (d.nx & (d.nx - 1)) == 0) a.pair = 1;
@@ -457,9 +471,10 @@ int lbm_set_option(lbm_grid *g, int32_t option, int64_t value)
         const bool pow2 = value >= 64 && value <= 65536 && (value & (value - 1)) == 0;
         if (!(value == -1 || value == 0 || pow2))
             return fail(LBM_E_ARG, "SoA block must be -1, 0 or a power of two in [64, 65536] nodes");
-        const int before = soa_block_shift(g);
+        const int before = soa_block_shift(g, g->scheme);
         g->soa_block = value;
-        if (soa_block_shift(g) != before) g->scheme = -1; // the lattice layout changes: bind again
+        if (g->d.layout == LBM_SOA && soa_block_shift(g, g->scheme) != before)
+            g->scheme = -1; // the lattice layout changes: bind again
         return LBM_OK;
     }
     if (option == LBM_OPT_RANK_LOOKUP) {
@@ -531,7 +546,7 @@ int lbm_query_sizes(const lbm_grid *g, int32_t scheme, lbm_sizes *out)
     }
     const int64_t ns = storage_nodes(g, scheme);
     const int s = pdf_size(d.precision);
-    const int bsh = soa_block_shift(g);
+    const int bsh = soa_block_shift(g, scheme);
     // a blocked lattice holds whole blocks: 19 * round_up(ns, block) values
     out->pitch = round_up(ns, bsh ? std::max<int64_t>(128, (int64_t)1 << bsh) : 128) + g->pitch_pad;
     out->pdf_bytes = d.layout == LBM_SOA ? Q * out->pitch * s : round_up(ns * Q * s, 256);
@@ -727,7 +742,7 @@ int lbm_step(lbm_grid *g, int32_t scheme, int32_t collider, int64_t n_steps, voi
         a.lds_bytes = lds_base; // set_residency adjusts per kernel from the base
         set_residency(g, a, kind);
         (a.pair == 2 ? tb.pair_wide[C][kind] : a.pair ? tb.pair[C][kind]
-         : a.row_staged == 2 ? tb.wide[C][kind] : a.row_staged == 3 ? tb.gen[C][kind]
+         : a.row_staged == 2 ? tb.wide[L == L_BLK][C][kind] : a.row_staged == 3 ? tb.gen[L == L_BLK][C][kind]
          : tb.update[A][L][C][kind])(a, nb, s);
     };
     if (collider == LBM_TRT) {
@@ -835,6 +850,14 @@ double lbm_model_bytes(int32_t scheme, int32_t addressing, int32_t precision, in
         return pdfs * s + (ind ? idxs * 4.0 : 0.0);
     }
     return -1.0;
+}
+
+int lbm_lattice_block(const lbm_grid *g)
+{
+    if (!g) return fail(LBM_E_ARG, "null grid");
+    if (g->scheme < 0) return fail(LBM_E_STATE, "no buffers bound (call lbm_bind)");
+    const int sh = soa_block_shift(g, g->scheme);
+    return sh ? 1 << sh : 0;
 }
 
 int lbm_rank_lookup_active(const lbm_grid *g)

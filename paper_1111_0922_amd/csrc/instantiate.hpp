@@ -15,20 +15,20 @@ void launch_pair(const KArgs &a, uint32_t blocks, hipStream_t s)
 {
     hipLaunchKernelGGL((k_update_pair<P, K, C>), dim3(blocks), dim3(BLOCK), a.lds_bytes, s, a);
 }
-template <int P, int K, int C>
+template <int P, int K, int C, int L>
 void launch_gen(const KArgs &a, uint32_t blocks, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_update_gen<P, K, C>), dim3(blocks), dim3(BLOCK), a.lds_bytes, s, a);
+    hipLaunchKernelGGL((k_update_gen<P, K, C, L>), dim3(blocks), dim3(BLOCK), a.lds_bytes, s, a);
 }
 template <int P, int K, int C>
 void launch_pair_wide(const KArgs &a, uint32_t blocks, hipStream_t s)
 {
     hipLaunchKernelGGL((k_update_pair_wide<P, K, C>), dim3(blocks), dim3(BLOCK), a.lds_bytes, s, a);
 }
-template <int P, int K, int C>
+template <int P, int K, int C, int L>
 void launch_wide(const KArgs &a, uint32_t blocks, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_update_wide<P, K, C>), dim3(blocks), dim3(BLOCK), a.lds_bytes, s, a);
+    hipLaunchKernelGGL((k_update_wide<P, K, C, L>), dim3(blocks), dim3(BLOCK), a.lds_bytes, s, a);
 }
 template <int A, int L, int P, int R>
 void launch_get(const KArgs &a, uint32_t blocks, hipStream_t s)
@@ -77,17 +77,17 @@ void fill_pairs(PrecTable &t)
     t.pair[C][K_ET1] = &launch_pair<P, K_ET1, C>;
 }
 
-template <int P, int C>
+template <int P, int C, int L>
 void fill_gen(PrecTable &t)
 {
-    t.gen[C][K_TS_COLLIDE] = &launch_gen<P, K_TS_COLLIDE, C>;
-    t.gen[C][K_TS_STREAM] = &launch_gen<P, K_TS_STREAM, 0>; // no collision
-    t.gen[C][K_OS_PUSH] = &launch_gen<P, K_OS_PUSH, C>;
-    t.gen[C][K_OS_PULL] = &launch_gen<P, K_OS_PULL, C>;
-    t.gen[C][K_AA_EVEN] = &launch_gen<P, K_AA_EVEN, C>;
-    t.gen[C][K_AA_ODD] = &launch_gen<P, K_AA_ODD, C>;
-    t.gen[C][K_ET0] = &launch_gen<P, K_ET0, C>;
-    t.gen[C][K_ET1] = &launch_gen<P, K_ET1, C>;
+    t.gen[L == L_BLK][C][K_TS_COLLIDE] = &launch_gen<P, K_TS_COLLIDE, C, L>;
+    t.gen[L == L_BLK][C][K_TS_STREAM] = &launch_gen<P, K_TS_STREAM, 0, L>; // no collision
+    t.gen[L == L_BLK][C][K_OS_PUSH] = &launch_gen<P, K_OS_PUSH, C, L>;
+    t.gen[L == L_BLK][C][K_OS_PULL] = &launch_gen<P, K_OS_PULL, C, L>;
+    t.gen[L == L_BLK][C][K_AA_EVEN] = &launch_gen<P, K_AA_EVEN, C, L>;
+    t.gen[L == L_BLK][C][K_AA_ODD] = &launch_gen<P, K_AA_ODD, C, L>;
+    t.gen[L == L_BLK][C][K_ET0] = &launch_gen<P, K_ET0, C, L>;
+    t.gen[L == L_BLK][C][K_ET1] = &launch_gen<P, K_ET1, C, L>;
 }
 
 template <int P, int C>
@@ -103,17 +103,17 @@ void fill_pairs_wide(PrecTable &t)
     t.pair_wide[C][K_ET1] = &launch_pair_wide<P, K_ET1, C>;
 }
 
-template <int P, int C>
+template <int P, int C, int L>
 void fill_wide(PrecTable &t)
 {
-    t.wide[C][K_TS_COLLIDE] = &launch_wide<P, K_TS_COLLIDE, C>;
-    t.wide[C][K_TS_STREAM] = &launch_wide<P, K_TS_STREAM, 0>; // no collision
-    t.wide[C][K_OS_PUSH] = &launch_wide<P, K_OS_PUSH, C>;
-    t.wide[C][K_OS_PULL] = &launch_wide<P, K_OS_PULL, C>;
-    t.wide[C][K_AA_EVEN] = &launch_wide<P, K_AA_EVEN, C>;
-    t.wide[C][K_AA_ODD] = &launch_wide<P, K_AA_ODD, C>;
-    t.wide[C][K_ET0] = &launch_wide<P, K_ET0, C>;
-    t.wide[C][K_ET1] = &launch_wide<P, K_ET1, C>;
+    t.wide[L == L_BLK][C][K_TS_COLLIDE] = &launch_wide<P, K_TS_COLLIDE, C, L>;
+    t.wide[L == L_BLK][C][K_TS_STREAM] = &launch_wide<P, K_TS_STREAM, 0, L>; // no collision
+    t.wide[L == L_BLK][C][K_OS_PUSH] = &launch_wide<P, K_OS_PUSH, C, L>;
+    t.wide[L == L_BLK][C][K_OS_PULL] = &launch_wide<P, K_OS_PULL, C, L>;
+    t.wide[L == L_BLK][C][K_AA_EVEN] = &launch_wide<P, K_AA_EVEN, C, L>;
+    t.wide[L == L_BLK][C][K_AA_ODD] = &launch_wide<P, K_AA_ODD, C, L>;
+    t.wide[L == L_BLK][C][K_ET0] = &launch_wide<P, K_ET0, C, L>;
+    t.wide[L == L_BLK][C][K_ET1] = &launch_wide<P, K_ET1, C, L>;
 }
 
 template <int A, int L, int P, int R>
@@ -144,13 +144,18 @@ PrecTable make_table()
     fill_al<A_DIRECT, L_SOA, P>(t);
     fill_pairs<P, 0>(t);
     fill_pairs<P, 1>(t);
-    fill_wide<P, 0>(t);
-    fill_wide<P, 1>(t);
+    fill_wide<P, 0, L_SOA>(t);
+    fill_wide<P, 1, L_SOA>(t);
+    fill_wide<P, 0, L_BLK>(t);
+    fill_wide<P, 1, L_BLK>(t);
     fill_pairs_wide<P, 0>(t);
     fill_pairs_wide<P, 1>(t);
-    fill_gen<P, 0>(t);
-    fill_gen<P, 1>(t);
+    fill_gen<P, 0, L_SOA>(t);
+    fill_gen<P, 1, L_SOA>(t);
+    fill_gen<P, 0, L_BLK>(t);
+    fill_gen<P, 1, L_BLK>(t);
     fill_al<A_DIRECT, L_AOS, P>(t);
+    fill_al<A_DIRECT, L_BLK, P>(t);
     fill_al<A_INDIRECT, L_SOA, P>(t);
     fill_al<A_INDIRECT, L_AOS, P>(t);
     fill_al<A_INDIRECT, L_BLK, P>(t);

@@ -719,7 +719,7 @@ __device__ __forceinline__ st (&staging_rows())[NXSLOT][BLOCK]
     return xs;
 }
 
-template <int PREC, int KIND, int COLL, bool WIDE>
+template <int PREC, int KIND, int COLL, bool WIDE, int LAY>
 __device__ __forceinline__ void update_direct_staged(const KArgs &a)
 {
     using S = Store<PREC>;
@@ -751,9 +751,9 @@ __device__ __forceinline__ void update_direct_staged(const KArgs &a)
     for (int i = 0; i < Q; ++i) {
         int j, sx, sy, sz;
         read_off<R>(nd, i, j, sx, sy, sz);
-        raw[i] = pdf_load_raw<true, S>(src + elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch));
+        raw[i] = pdf_load_raw<true, S>(src + slot_index<A_DIRECT, LAY>(a, j, nd.shift(0, sy, sz)));
         if (xslot(i) >= 0 && sx != 0 && beyond(sx))
-            halo[WIDE && xslot(i) > 0 ? xslot(i) : 0] = pdf_load_raw<true, S>(src + elem<L_SOA>(j, nd.shift(sx, sy, sz), a.pitch));
+            halo[WIDE && xslot(i) > 0 ? xslot(i) : 0] = pdf_load_raw<true, S>(src + slot_index<A_DIRECT, LAY>(a, j, nd.shift(sx, sy, sz)));
     }
     ct v[Q];
 #pragma unroll
@@ -787,13 +787,13 @@ __device__ __forceinline__ void update_direct_staged(const KArgs &a)
         write_off<W>(nd, i, j, sx, sy, sz);
         if (xslot(i) >= 0 && sx != 0) {
             if (beyond(sx)) {
-                if (valid) pdf_store<true>(dst + elem<L_SOA>(j, nd.shift(sx, sy, sz), a.pitch), S::save(v[i]));
+                if (valid) pdf_store<true>(dst + slot_index<A_DIRECT, LAY>(a, j, nd.shift(sx, sy, sz)), S::save(v[i]));
             } else {
                 xs[xslot(i) < 0 ? 0 : xslot(i)][pos(sx)] = S::save(v[i]);
             }
             continue;
         }
-        if (valid) pdf_store<true>(dst + elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch), S::save(v[i]));
+        if (valid) pdf_store<true>(dst + slot_index<A_DIRECT, LAY>(a, j, nd.shift(0, sy, sz)), S::save(v[i]));
     }
     __syncthreads();
 #pragma unroll
@@ -803,7 +803,7 @@ __device__ __forceinline__ void update_direct_staged(const KArgs &a)
             write_off<W>(nd, i, j, sx, sy, sz);
             // the depositor of this position is segment position xl - sx
             if (sx != 0 && valid && !beyond(-sx))
-                pdf_store<true>(dst + elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch), xs[xslot(i) < 0 ? 0 : xslot(i)][t]);
+                pdf_store<true>(dst + slot_index<A_DIRECT, LAY>(a, j, nd.shift(0, sy, sz)), xs[xslot(i) < 0 ? 0 : xslot(i)][t]);
         }
     }
 }
@@ -817,7 +817,7 @@ __device__ __forceinline__ void update_direct_staged(const KArgs &a)
 // memory by the lane itself, and an owner stores an LDS position only if its
 // depositor lies inside the workgroup.  Every global access of a lane's own
 // node is made at the node's own x.
-template <int PREC, int KIND, int COLL>
+template <int PREC, int KIND, int COLL, int LAY>
 __device__ __forceinline__ void update_direct_general(const KArgs &a)
 {
     using S = Store<PREC>;
@@ -854,9 +854,9 @@ __device__ __forceinline__ void update_direct_general(const KArgs &a)
     for (int i = 0; i < Q; ++i) {
         int j, sx, sy, sz;
         read_off<R>(nd, i, j, sx, sy, sz);
-        raw[i] = pdf_load_raw<true, S>(src + elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch));
+        raw[i] = pdf_load_raw<true, S>(src + slot_index<A_DIRECT, LAY>(a, j, nd.shift(0, sy, sz)));
         if (xslot(i) >= 0 && sx != 0 && valid && !inside(along(sx)))
-            halo[xslot(i) > 0 ? xslot(i) : 0] = pdf_load_raw<true, S>(src + elem<L_SOA>(j, nd.shift(sx, sy, sz), a.pitch));
+            halo[xslot(i) > 0 ? xslot(i) : 0] = pdf_load_raw<true, S>(src + slot_index<A_DIRECT, LAY>(a, j, nd.shift(sx, sy, sz)));
     }
     ct v[Q];
 #pragma unroll
@@ -899,10 +899,10 @@ __device__ __forceinline__ void update_direct_general(const KArgs &a)
             if (inside(q))
                 xs[xslot(i) < 0 ? 0 : xslot(i)][(uint32_t)(q - n0)] = S::save(v[i]);
             else
-                pdf_store<true>(dst + elem<L_SOA>(j, nd.shift(sx, sy, sz), a.pitch), S::save(v[i]));
+                pdf_store<true>(dst + slot_index<A_DIRECT, LAY>(a, j, nd.shift(sx, sy, sz)), S::save(v[i]));
             continue;
         }
-        if (valid) pdf_store<true>(dst + elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch), S::save(v[i]));
+        if (valid) pdf_store<true>(dst + slot_index<A_DIRECT, LAY>(a, j, nd.shift(0, sy, sz)), S::save(v[i]));
     }
     __syncthreads();
 #pragma unroll
@@ -912,7 +912,7 @@ __device__ __forceinline__ void update_direct_general(const KArgs &a)
             write_off<W>(nd, i, j, sx, sy, sz);
             // the depositor of this position is the neighbour at x - sx
             if (sx != 0 && valid && inside(along(-sx)))
-                pdf_store<true>(dst + elem<L_SOA>(j, nd.shift(0, sy, sz), a.pitch), xs[xslot(i) < 0 ? 0 : xslot(i)][t]);
+                pdf_store<true>(dst + slot_index<A_DIRECT, LAY>(a, j, nd.shift(0, sy, sz)), xs[xslot(i) < 0 ? 0 : xslot(i)][t]);
         }
     }
 }
@@ -1284,30 +1284,30 @@ __host__ __device__ constexpr bool shifts_x(int kind)
 
 // Direct SoA grids of any other nx: BLOCK consecutive nodes, shifts through
 // LDS inside the workgroup (a kernel of its own, as above).
-template <int PREC, int KIND, int COLL>
+template <int PREC, int KIND, int COLL, int LAY>
 __global__ void __launch_bounds__(BLOCK) k_update_gen(KArgs a)
 {
     if constexpr (shifts_x(KIND)) {
-        update_direct_general<PREC, KIND, COLL>(a);
+        update_direct_general<PREC, KIND, COLL, LAY>(a);
     } else {
         const uint32_t n = logical_block(a) * BLOCK + threadIdx.x;
         if (n >= a.n_nodes) return;
-        update_node<A_DIRECT, L_SOA, PREC, KIND, COLL>(a, n);
+        update_node<A_DIRECT, LAY, PREC, KIND, COLL>(a, n);
     }
 }
 
 // Direct SoA grids whose nx is a multiple of BLOCK: one row segment per
 // workgroup (a kernel of its own, so that the segment-end work does not count
 // against the registers of the other kernels).
-template <int PREC, int KIND, int COLL>
+template <int PREC, int KIND, int COLL, int LAY>
 __global__ void __launch_bounds__(BLOCK) k_update_wide(KArgs a)
 {
     if constexpr (shifts_x(KIND)) {
-        update_direct_staged<PREC, KIND, COLL, true>(a);
+        update_direct_staged<PREC, KIND, COLL, true, LAY>(a);
     } else {
         const uint32_t n = logical_block(a) * BLOCK + threadIdx.x;
         if (n >= a.n_nodes) return;
-        update_node<A_DIRECT, L_SOA, PREC, KIND, COLL>(a, n);
+        update_node<A_DIRECT, LAY, PREC, KIND, COLL>(a, n);
     }
 }
 
@@ -1319,9 +1319,9 @@ __global__ void __launch_bounds__(BLOCK) k_update(KArgs a)
     // open boundaries exist on indirect grids, for the maps that cross links
     constexpr bool links = R == R_PULL || R == R_AAODD || W == W_PUSH || W == W_ET0 || W == W_ET1;
     if constexpr (ADDR == A_INDIRECT && links) bc_table_fill<typename Store<PREC>::ct>(a);
-    if constexpr (ADDR == A_DIRECT && LAY == L_SOA && shifts_x(KIND)) {
+    if constexpr (ADDR == A_DIRECT && LAY != L_AOS && shifts_x(KIND)) {
         if (a.row_staged == 1) {
-            update_direct_staged<PREC, KIND, COLL, false>(a);
+            update_direct_staged<PREC, KIND, COLL, false, LAY>(a);
             return;
         }
     }
@@ -1491,9 +1491,9 @@ using Launch = void (*)(const KArgs &, uint32_t, hipStream_t);
 struct PrecTable {
     Launch update[2][3][2][K_NUM]; // [addr][layout (L_SOA, L_AOS, L_BLK)][collider][kind]
     Launch pair[2][K_NUM];         // direct SoA, two nodes per lane: [collider][kind]
-    Launch wide[2][K_NUM];         // direct SoA, one row segment per workgroup: [collider][kind]
+    Launch wide[2][2][K_NUM];      // direct SoA, one row segment per workgroup: [blocked][collider][kind]
     Launch pair_wide[2][K_NUM];    // direct SoA, two nodes per lane, 512-node row segments
-    Launch gen[2][K_NUM];          // direct SoA, any other nx: shifts through LDS across rows
+    Launch gen[2][2][K_NUM];       // direct SoA, any nx, shifts through LDS: [blocked][collider][kind]
     Launch get[2][3][R_NUM];
     Launch set[2][3][R_NUM];
     Launch init[2][3][R_NUM];

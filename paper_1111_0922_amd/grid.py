@@ -119,6 +119,13 @@ class Grid:
         return bool(rc & 1)
 
     @property
+    def lattice_block(self) -> int:
+        """Nodes per block of the bound SoA lattices (LBM_OPT_SOA_BLOCK), 0 for plain SoA or AoS."""
+        rc = self.lib.lbm_lattice_block(self._h)
+        L.check(min(rc, 0))
+        return rc
+
+    @property
     def et_rank_lookup(self) -> bool:
         """Whether the esoteric twist takes its storage addresses from the rank words."""
         rc = self.lib.lbm_rank_lookup_active(self._h)

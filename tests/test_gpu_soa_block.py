@@ -1,5 +1,6 @@
-"""Blocked SoA lattices of indirect grids (LBM_OPT_SOA_BLOCK): the stated storage order, and the same bits
-as plain SoA in every kernel, read-out and reduction, alone and batched."""
+"""Blocked SoA lattices (LBM_OPT_SOA_BLOCK): the stated storage order, and the same bits as plain SoA in
+every kernel, read-out and reduction, on indirect grids (alone and batched) and on direct grids (the
+row-staged, row-segment and across-row kernels)."""
 import numpy as np
 import pytest
 import torch
@@ -19,9 +20,9 @@ def _setup():
     return solid, ru
 
 
-def _blocked_grid(solid, scheme, block, **kw):
+def _blocked_grid(solid, scheme, block, addressing="indirect", **kw):
     import paper_1111_0922_amd as P
-    grid = make_grid(solid, scheme, addressing="indirect", **kw)
+    grid = make_grid(solid, scheme, addressing=addressing, **kw)
     grid.set_option(P._lib.OPT_SOA_BLOCK, block)
     grid.bind(scheme)      # the layout changed: new buffers
     return grid
@@ -117,3 +118,33 @@ def test_blocked_and_plain_slots_in_one_batch(precision):
         batch.run(K)
     for (slot, grid), f_alone in zip(grids, alone):
         assert np.array_equal(from_device(grid.get_pdfs()).view(np.int64), f_alone.view(np.int64)), slot
+
+
+@pytest.mark.parametrize("shape", [(64, 12, 9), (512, 3, 6), (45, 7, 8)])
+@pytest.mark.parametrize("scheme", ["aa", "ts", "os_push", "os_pull", "et"])
+def test_blocked_direct_lattice_gives_the_plain_bits(scheme, shape):
+    """Direct channels whose nx selects the whole-row, the 256-node row-segment and the across-row
+    kernels, FP64 and FP32: plain SoA against blocks of 64 and 1024 cells (the default for FP64 on
+    every scheme but AA); FP64 against the oracle too.  The box sizes are no multiple of the blocks."""
+    import paper_1111_0922_amd as P
+    nx, ny, nz = shape
+    solid = lbm_inputs.channel_mask(nx, ny, nz)
+    ru = lbm_inputs.rho_u_field(solid.shape, lbm_inputs.velocity_noise(solid.shape, 1e-3, seed=63))
+    f0 = oracle.fluid_view(oracle.init_equilibrium(ru, solid), solid)
+    for precision in ("f64", "f32"):
+        out = []
+        for block in (0, 64, 1024, -1):
+            grid = _blocked_grid(solid, scheme, block, addressing="direct", precision=precision, omega=1.3,
+                                 g=(1e-5, 2e-6, 0))
+            assert grid.lattice_block == (block if block >= 0 else (0 if scheme == "aa" else 1024))
+            grid.set_pdfs(to_device(f0))
+            grid.step(7)
+            out.append((from_device(grid.get_pdfs()), from_device(grid.moments())))
+            del grid
+        for f, m in out[1:]:
+            assert np.array_equal(out[0][0].view(np.int64), f.view(np.int64)), precision
+            assert np.array_equal(out[0][1], m), precision
+        if precision == "f64":
+            want = oracle.fluid_view(oracle.run_ts(oracle.init_equilibrium(ru, solid), solid, 7, 1.3,
+                                                   (1e-5, 2e-6, 0)), solid)
+            assert float(np.max(np.abs(out[-1][0] - want) / np.abs(want))) <= 1e-12

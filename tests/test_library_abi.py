@@ -74,8 +74,10 @@ def test_rank_lookup_query_without_gpu():
     L = P._lib
     lib = L.load()
     assert lib.lbm_rank_lookup_active(None) == L.LBM_E_ARG
+    assert lib.lbm_lattice_block(None) == L.LBM_E_ARG
     g = P.Grid(16, 8, 8, addressing="indirect")
     assert lib.lbm_rank_lookup_active(g._h) == L.LBM_E_STATE
+    assert lib.lbm_lattice_block(g._h) == L.LBM_E_STATE
 
 
 def test_validation_errors_without_gpu():
