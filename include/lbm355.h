@@ -86,7 +86,8 @@ typedef struct lbm_grid lbm_grid;
 typedef struct {
     int32_t nx, ny, nz;  /* box in cells; x is the fastest index                */
     int32_t addressing;  /* enum lbm_addressing                                  */
-    int32_t layout;      /* enum lbm_layout                                      */
+    int32_t layout;      /* enum lbm_layout: SoA slot (j, n) at j * pitch + n, or
+                            in blocks (LBM_OPT_SOA_BLOCK); AoS at n * 19 + j     */
     int32_t precision;   /* enum lbm_precision                                   */
     int32_t wall_z;      /* DIRECT only: 1 = cell planes z = 0 and z = nz-1 are
                             solid walls (half-way bounce-back); 0 = periodic z.
@@ -116,7 +117,8 @@ typedef struct {
     int64_t n_nodes;       /* nodes updated per step (fluid nodes); 0 before
                               lbm_build_idx on an indirect grid                     */
     int64_t n_ghost;       /* extra storage entries of the esoteric twist           */
-    int64_t pitch;         /* SoA: elements between direction arrays                */
+    int64_t pitch;         /* SoA: elements between direction arrays (blocked SoA:
+                              whole blocks per direction, 19 * pitch values)        */
     int64_t idx_pitch;     /* entries between IDX rows                              */
     int64_t pdf_bytes;     /* one lattice for the queried scheme                    */
     int64_t pdf1_bytes;    /* second lattice (TS, OS push, OS pull) or 0           */
