@@ -309,15 +309,8 @@ struct Node<A_DIRECT, NEED> {
     __device__ __forceinline__ void pin_et(int) {}
 };
 
-// The 18 neighbour ids of node n from the rank words, where the fluid id of a
-// cell is the number of fluid cells before it in x-fastest order: for cell
-// c = 32 w + b, fluid when bit b of word w is set, with id rank(w) +
-// popcount(bits(w) below b).  The result equals IDX with every non-fluid
-// neighbour as -1.  Per node this reads 4 bytes of cell_of; the words (8
-// bytes per 32 cells, about 33 MB for a 512^3 box) are shared by the 18
-// neighbours of ~13 nodes each and mostly come from the cache, where IDX
-// streams 72 bytes per node from memory.
-__device__ __forceinline__ void rank_neighbours(const KArgs &k, uint32_t n, int32_t (&m)[18])
+// Cells x + c_i (i = 1..18, periodic wrap) of node n, from the node's cell.
+__device__ __forceinline__ void neighbour_cells(const KArgs &k, uint32_t n, uint32_t (&cc)[18])
 {
     const uint32_t c = k.cell_of[n];
     const uint32_t nx = (uint32_t)k.nx, ny = (uint32_t)k.ny, nz = (uint32_t)k.nz, pl = (uint32_t)k.plane;
@@ -328,14 +321,25 @@ __device__ __forceinline__ void rank_neighbours(const KArgs &k, uint32_t n, int3
     const uint32_t px[3] = {x == 0 ? nx - 1 : x - 1, x, x + 1 == nx ? 0 : x + 1};
     const uint32_t py[3] = {(y == 0 ? ny - 1 : y - 1) * nx, y * nx, (y + 1 == ny ? 0 : y + 1) * nx};
     const uint32_t pz[3] = {(z == 0 ? nz - 1 : z - 1) * pl, z * pl, (z + 1 == nz ? 0 : z + 1) * pl};
+#pragma unroll
+    for (int j = 0; j < 18; ++j) cc[j] = px[cx(j + 1) + 1] + py[cy(j + 1) + 1] + pz[cz(j + 1) + 1];
+}
+
+// The 18 neighbour ids of node n from the rank words, where the fluid id of a
+// cell is the number of fluid cells before it in x-fastest order: for cell
+// c = 32 w + b, fluid when bit b of word w is set, with id rank(w) +
+// popcount(bits(w) below b).  The result equals IDX with every non-fluid
+// neighbour as -1.  Per node this reads 4 bytes of cell_of; the words (8
+// bytes per 32 cells, about 33 MB for a 512^3 box) are shared by the 18
+// neighbours of ~13 nodes each and mostly come from the cache, where IDX
+// streams 72 bytes per node from memory.
+__device__ __forceinline__ void rank_neighbours(const KArgs &k, uint32_t n, int32_t (&m)[18])
+{
     uint32_t cc[18];
+    neighbour_cells(k, n, cc);
     uint2 w[18];
 #pragma unroll
-    for (int j = 0; j < 18; ++j) {
-        const int i = j + 1;
-        cc[j] = px[cx(i) + 1] + py[cy(i) + 1] + pz[cz(i) + 1];
-        w[j] = k.rank_words[cc[j] >> 5];
-    }
+    for (int j = 0; j < 18; ++j) w[j] = k.rank_words[cc[j] >> 5];
     // All 18 words in flight before the first is used: without this opaque use
     // the compiler loads a word's rank only under the lane's fluid bit and waits
     // for each load in turn (36 round trips instead of one).
@@ -357,25 +361,13 @@ __device__ __forceinline__ void rank_neighbours(const KArgs &k, uint32_t n, int3
 // table reads 28.
 __device__ __forceinline__ void rank_et(const KArgs &k, uint32_t n, int32_t (&e)[6], uint32_t &mask)
 {
-    const uint32_t c = k.cell_of[n];
-    const uint32_t nx = (uint32_t)k.nx, ny = (uint32_t)k.ny, nz = (uint32_t)k.nz, pl = (uint32_t)k.plane;
-    const uint32_t q = fdiv(c, k.dvx);
-    const uint32_t x = c - q * nx;
-    const uint32_t z = fdiv(q, k.dvy);
-    const uint32_t y = q - z * ny;
-    const uint32_t px[3] = {x == 0 ? nx - 1 : x - 1, x, x + 1 == nx ? 0 : x + 1};
-    const uint32_t py[3] = {(y == 0 ? ny - 1 : y - 1) * nx, y * nx, (y + 1 == ny ? 0 : y + 1) * nx};
-    const uint32_t pz[3] = {(z == 0 ? nz - 1 : z - 1) * pl, z * pl, (z + 1 == nz ? 0 : z + 1) * pl};
     // directions of the six storage cells x + ex, ey, ez, ex+ey, ex+ez, ey+ez
     constexpr int dir[6] = {1, 3, 5, 7, 11, 15};
     uint32_t cc[18];
+    neighbour_cells(k, n, cc);
     uint2 w[18], gw[6];
 #pragma unroll
-    for (int j = 0; j < 18; ++j) {
-        const int i = j + 1;
-        cc[j] = px[cx(i) + 1] + py[cy(i) + 1] + pz[cz(i) + 1];
-        w[j] = k.rank_words[cc[j] >> 5];
-    }
+    for (int j = 0; j < 18; ++j) w[j] = k.rank_words[cc[j] >> 5];
 #pragma unroll
     for (int t = 0; t < 6; ++t) gw[t] = k.ghost_words[cc[dir[t] - 1] >> 5];
     // every word in flight before the first is used (as in rank_neighbours)
@@ -478,7 +470,7 @@ struct Node<A_INDIRECT, NEED> {
 // Index of PDF slot (direction j, node or cell c) in a lattice buffer.
 //   AoS: c * 19 + j.
 //   SoA: j * pitch + c.
-//   Blocked SoA (indirect grids): ((c >> bsh) * 19 + j) * 2^bsh + (c & bmk).
+//   Blocked SoA: ((c >> bsh) * 19 + j) * 2^bsh + (c & bmk).
 //     The 19 directions of a block of 2^bsh nodes lie in one contiguous
 //     region, so the gathers and scatters of a workgroup stay in a few DRAM
 //     pages instead of touching 19 arrays a lattice apart.
