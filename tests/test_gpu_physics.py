@@ -5,7 +5,8 @@ force: at the relaxation omega = 1/(1/2 + sqrt(3)/4) (BGK with Lambda = 3/16)
 the discrete steady solution is the exact parabola u(z) = g/(2 nu) (z - 1/2)
 (H + 1/2 - z) for fluid planes z = 1..H, and the slit's Darcy permeability is
 H^3/(12 nz) (1 + 1/(2 H^2)).  Checked on the direct channel and on the
-indirect grid with the walls given as a mask, for several schemes.
+indirect grid with the walls given as a mask, for several schemes.  A shear
+wave in a periodic box decays at the lattice viscosity nu = (1/omega - 1/2)/3.
 """
 import math
 
@@ -75,3 +76,40 @@ def test_poiseuille_reduced_precision(precision, nz, bound):
         assert err < bound
     else:
         assert 1e-2 < err < 0.2  # stagnation below the binary16 resolution, as derived above
+
+
+@pytest.mark.parametrize("omega,tol", [(1.0, 1e-5), (1.6, 3e-3)])
+@pytest.mark.parametrize("axis", ["x", "z"])
+@pytest.mark.parametrize("scheme,addressing", [("aa", "direct"), ("et", "direct"), ("ts", "direct"),
+                                               ("os_pull", "direct"), ("aa", "indirect"), ("et", "indirect")])
+def test_shear_wave_decays_at_the_lattice_viscosity(scheme, addressing, axis, omega, tol):
+    """A transverse wave u = U sin(k s) e_t (s along x or z, L = 64) in a fully periodic box decays as
+    exp(-nu k^2 t) with nu = (1/omega - 1/2)/3, to O(k^2) relative terms (the tolerances of the oracle's
+    own test).  Along x the shifts go through the kernels' LDS staging; the direct grids use the default
+    storage orders (1024-cell blocks for the two-step, one-step and esoteric-twist schemes), the indirect
+    ones the rank lookup and blocks."""
+    L = 64
+    shape = (L, 2, 2) if axis == "x" else (2, 2, L)       # (nx, ny, nz)
+    nx, ny, nz = shape
+    solid = np.zeros((nz, ny, nx), np.uint8)
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    s = (xx if axis == "x" else zz).reshape(-1).astype(np.float64)
+    k = 2 * np.pi / L
+    t = 1 if axis == "x" else 0                           # u_y(x) or u_x(z)
+    rho_u = np.zeros((4, solid.size))
+    rho_u[0] = 1.0
+    rho_u[1 + t] = 1e-4 * np.sin(k * s)
+    grid = make_grid(solid, scheme, addressing=addressing, omega=omega, g=(0, 0, 0))
+    grid.init_equilibrium(torch.from_numpy(rho_u).cuda())
+
+    def amplitude():
+        f = from_device(grid.get_pdfs())
+        u = np.tensordot(C[t], f, axes=(0, 0)) / f.sum(axis=0)
+        return float((u * np.sin(k * s)).sum() * 2 / solid.size)
+
+    grid.step(200)
+    a1 = amplitude()
+    grid.step(2000)
+    a2 = amplitude()
+    nu = (1.0 / omega - 0.5) / 3.0
+    assert abs(-math.log(a2 / a1) / (k * k * 2000) / nu - 1) < tol
