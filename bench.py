@@ -405,6 +405,7 @@ def serving_bench(log, n_requests, n_light=100, n_shifted=300, seed_base=100000)
         rep["steps_mean"] = float(np.mean([r.steps for r in out]))
         rep["makespan_s"] = sch.makespan
         rep["storage"] = precision
+        rep["lattice_block"] = ex.lattice_block
         rep["permeability"] = {r.seed: r.permeability for r in out}
         log(f"[bench]   {rep['requests']} measured requests, {rep['solves_per_s']:.2f} solves/s, "
             f"p50 {rep['p50_latency_s']:.2f} s, p99 {rep['p99_latency_s']:.2f} s, "
@@ -483,6 +484,7 @@ def precision_study(log, n=384, radius=8, porosity=0.6, seed=4, tol=1e-7, max_st
         res[key] = {"steps": steps, "status": mon.status if mon.status != "running" else "cap",
                     "U": U, "permeability": nu * phi * U / g, "MFLUP/s": round(mf, 1),
                     "frac_hbm": round(mf * bl / 1e3 / HBM_PEAK_GBS, 4), "bytes_per_lup": bl,
+                    "neighbour_ids": "rank" if grid.rank_lookup else "idx", "lattice_block": grid.lattice_block,
                     "mass_drift": float(abs(m[0] - m0[0]) / m0[0]),
                     "last_window_change": mon.last_change, "trend_per_window": mon.trend,
                     "noise_per_window": mon.noise}

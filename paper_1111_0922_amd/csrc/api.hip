@@ -78,9 +78,15 @@ int64_t rank_words_count(const lbm_grid *g) { return (g->n_cells + 31) / 32; }
 //  - indirect grids, FP64, every scheme.  512^3 pack, per launch (plain ->
 //    1024): AA even 2.76-2.79 -> 2.60 ms, odd 3.85-3.88 -> 3.75, two-step 6.18
 //    -> 5.72-5.76 per step, one-step pull 3.12-3.30 -> 3.06-3.10; one-step push
-//    and the esoteric twist within their run-to-run spread.  FP32, FP32-shifted
-//    and FP16 storage gain nothing overall and stay plain (AA FP32: even
-//    1.32-1.40 -> 1.24 ms, odd 2.13-2.28 -> 2.24);
+//    and the esoteric twist within their run-to-run spread;
+//  - indirect grids, FP32 and FP32-shifted storage, every scheme.  512^3 pack
+//    with neighbour ids by rank, FP32 (per launch): AA even 1.37-1.38 -> 1.24
+//    ms, odd 2.27 -> 2.18; two-step 3.40-3.44 -> 3.13-3.15; one-step push 2.23
+//    -> 2.12, pull 2.02-2.04 -> 1.81-1.91; esoteric twist 2.43 -> 2.33.  With
+//    IDX the AA pattern is level (even 1.39 -> 1.25, odd 2.35 -> 2.42).  The
+//    serving mix of lattices (edges 32-192, batched) runs 30.5 -> 32.6 GLUP/s.
+//    FP16 storage keeps plain SoA and its pairs of nodes per lane (AA even 0.73
+//    -> 0.66 ms, odd 2.07 -> 2.02-2.11 without pairs: within the spread);
 //  - direct grids, FP64, FP32 and FP32-shifted storage, the two-step, one-step
 //    and esoteric-twist schemes.  256^3 channel, FP64 (FP32): two-step 1.67 ->
 //    1.58 ms per step (0.84 -> 0.80), one-step push 0.88 -> 0.85 (0.425 ->
@@ -96,7 +102,7 @@ int soa_block_shift(const lbm_grid *g, int scheme)
     const bool ind = g->d.addressing == LBM_INDIRECT;
     const int p = g->d.precision;
     int64_t def = 0;
-    if (ind ? p == LBM_F64 : (scheme != LBM_AA && (p == LBM_F64 || p == LBM_F32 || p == LBM_F32S))) def = 1024;
+    if ((p == LBM_F64 || p == LBM_F32 || p == LBM_F32S) && (ind || scheme != LBM_AA)) def = 1024;
     const int64_t b = g->soa_block >= 0 ? g->soa_block : def;
     int sh = 0;
     while (((int64_t)1 << sh) < b) ++sh;

@@ -255,6 +255,7 @@ class GpuExecutor:
         self.busy_seconds = 0.0
         self.pdf_size = {"f64": 8, "f32": 4, "f16s": 2, "f32s": 4}[precision]
         self.rank_lookup = False  # whether the admitted lattices look neighbour ids up by rank
+        self.lattice_block = 0     # nodes per block of the admitted lattices (0: plain SoA)
 
     def prepare(self, req):
         import lbm_inputs
@@ -263,7 +264,7 @@ class GpuExecutor:
         req.n_cells = int(mask.size)
         req.n_fluid = int(mask.size - int(mask.sum(dtype=np.int64)))
         self.masks[req.rid] = mask
-        nf = req.n_fluid + 128
+        nf = req.n_fluid + 1024   # the lattice covers whole blocks of 1024 nodes
         # lattice + IDX (with the slab order and the rank-lookup arrays: cell_of, 8 bytes per 32 cells) +
         # partials, and the cellmap held while the index is built
         return (19 * self.pdf_size + 19 * 4) * nf + 4 * req.n_cells + req.n_cells // 4 + 8192
@@ -283,6 +284,7 @@ class GpuExecutor:
             grid.bind("aa")
             grid.init_equilibrium()
             self.rank_lookup = grid.rank_lookup
+            self.lattice_block = grid.lattice_block
         # the run stream reads this lattice only after the host has seen its set-up finish
         self.setup_stream.synchronize()
         self.joining[req.rid] = grid
