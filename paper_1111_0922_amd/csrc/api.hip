@@ -84,9 +84,12 @@ int64_t rank_words_count(const lbm_grid *g) { return (g->n_cells + 31) / 32; }
 //    ms, odd 2.27 -> 2.18; two-step 3.40-3.44 -> 3.13-3.15; one-step push 2.23
 //    -> 2.12, pull 2.02-2.04 -> 1.81-1.91; esoteric twist 2.43 -> 2.33.  With
 //    IDX the AA pattern is level (even 1.39 -> 1.25, odd 2.35 -> 2.42).  The
-//    serving mix of lattices (edges 32-192, batched) runs 30.5 -> 32.6 GLUP/s.
-//    FP16 storage keeps plain SoA and its pairs of nodes per lane (AA even 0.73
-//    -> 0.66 ms, odd 2.07 -> 2.02-2.11 without pairs: within the spread);
+//    serving mix of lattices (edges 32-192, batched) runs 30.5 -> 32.6 GLUP/s;
+//  - indirect grids, FP16 storage (with IDX, its default), every scheme.  512^3
+//    pack: AA 36.7 -> 38.8 GLUP/s (even 0.73-0.74 -> 0.67 ms, odd 2.19-2.20 ->
+//    2.11), two-step 2.40-2.42 -> 2.25-2.26 ms per step, one-step pull 1.72 ->
+//    1.62-1.63 ms, push 1.85 -> 1.80-1.82, esoteric twist 2.30 -> 2.29; 384^3
+//    pack AA 38.1 -> 39.3;
 //  - direct grids, FP64, FP32 and FP32-shifted storage, the two-step, one-step
 //    and esoteric-twist schemes.  256^3 channel, FP64 (FP32): two-step 1.67 ->
 //    1.58 ms per step (0.84 -> 0.80), one-step push 0.88 -> 0.85 (0.425 ->
@@ -95,14 +98,15 @@ int64_t rank_words_count(const lbm_grid *g) { return (g->n_cells + 31) / 32; }
 //    rows y +- 1 of a direction, which plain SoA keeps 2 KB apart in one array
 //    (FP64 even 0.83 -> 0.78 ms, odd 0.85-0.86 -> 0.85-0.89 over runs on
 //    different boxes; FP32 odd 0.42-0.43 -> 0.47).
-// Pairs of nodes per lane (16-bit storage) need plain SoA.
+// Pairs of nodes per lane (16-bit storage, direct grids) need plain SoA, and
+// keep it by default.
 int soa_block_shift(const lbm_grid *g, int scheme)
 {
     if (g->d.layout != LBM_SOA) return 0;
     const bool ind = g->d.addressing == LBM_INDIRECT;
     const int p = g->d.precision;
     int64_t def = 0;
-    if ((p == LBM_F64 || p == LBM_F32 || p == LBM_F32S) && (ind || scheme != LBM_AA)) def = 1024;
+    if (ind || (scheme != LBM_AA && p != LBM_F16S)) def = 1024;
     const int64_t b = g->soa_block >= 0 ? g->soa_block : def;
     int sh = 0;
     while (((int64_t)1 << sh) < b) ++sh;

@@ -176,3 +176,52 @@ def test_512_porous_sampled(scheme, pack512):
         del ft, ft1
     m1 = from_device(grid.moments())
     assert abs(m1[0] - m0[0]) / m0[0] <= 1e-13
+
+
+@pytest.fixture(scope="module")
+def pack384():
+    return lbm_inputs.sphere_pack(384, 8, 0.6, seed=4)[0]
+
+
+@pytest.mark.parametrize("prec,sigma", [("f32", 1.0), ("f32s", 1.0), ("f16s", 1024.0)])
+def test_384_precision_pack_sampled(prec, sigma, pack384):
+    """The precision study's reduced storage forms on its 384^3 pack, indirect AA in the launch
+    configuration the library picks by default (lattices in 1024-node blocks; neighbour ids by rank
+    with FP32 and FP32-shifted storage, IDX with FP16-shifted).  Both AA kernels are sampled against the
+    oracle's update under the same storage rounding, at the bars of the small-lattice precision tests,
+    which hold while |f - w_i| < 2^-12 (checked on the state): FP32 relative 1e-6; FP32-shifted 2e-9
+    in f; FP16-shifted 4 binary16 ulp of h, 4 * 2^-23 in f."""
+    solid = pack384
+    omega, g = 1.0, (1e-6, 0.0, 0.0)
+    grid = make_grid(solid, "aa", addressing="indirect", precision=prec, omega=omega, g=g, f16_scale=sigma)
+    assert grid.lattice_block == 1024
+    assert grid.rank_lookup == (prec != "f16s")
+    grid.cellmap = None
+    grid._mask = None
+    fl = solid.reshape(-1) == 0
+    ru = lbm_inputs.rho_u_field(solid.shape, lbm_inputs.velocity_noise(solid.shape, 1e-4, seed=5))
+    grid.init_equilibrium(to_device(np.ascontiguousarray(ru.reshape(4, -1)[:, fl])))
+    del ru
+    m0 = from_device(grid.moments())
+    grid.step(3)
+    _, w, _ = oracle.tables()
+    rng = np.random.default_rng(3)
+    ids_all = _fluid_ids(solid)
+    kw = {"precision": prec, "sigma": sigma}
+    for extra in (1, 2):
+        ft = from_device(grid.get_pdfs())
+        assert float(np.max(np.abs(ft - w[:, None]))) < 2.0 ** -12
+        grid.step(1)
+        ft1 = from_device(grid.get_pdfs())
+        cells = rng.choice(np.flatnonzero(fl), 200, replace=False)
+        ids = ids_all[cells]
+        want = _sample_update(ft, solid, cells, omega, g, **kw)
+        if prec == "f32":
+            assert rel_err(ft1[:, ids], want) <= 1e-6, extra
+        elif prec == "f32s":
+            assert float(np.max(np.abs(ft1[:, ids] - want))) <= 2e-9, extra
+        else:
+            assert float(np.max(np.abs(ft1[:, ids] - want))) <= 4 * 2.0 ** -23, extra
+        del ft, ft1
+    m1 = from_device(grid.moments())
+    assert abs(m1[0] - m0[0]) / m0[0] <= (1e-9 if prec == "f32s" else 1e-6)   # the small tests' mass bars
