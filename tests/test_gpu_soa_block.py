@@ -148,3 +148,21 @@ def test_blocked_direct_lattice_gives_the_plain_bits(scheme, shape):
             want = oracle.fluid_view(oracle.run_ts(oracle.init_equilibrium(ru, solid), solid, 7, 1.3,
                                                    (1e-5, 2e-6, 0)), solid)
             assert float(np.max(np.abs(out[-1][0] - want) / np.abs(want))) <= 1e-12
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "f32s", "f16s"])
+def test_indirect_lattices_are_blocked_by_default(precision):
+    """Every storage form and scheme of an indirect SoA grid stores its lattice in 1024-node blocks
+    unless LBM_OPT_SOA_BLOCK says otherwise; AoS lattices report no blocks."""
+    import paper_1111_0922_amd as P
+    solid = lbm_inputs.sphere_pack((30, 20, 18), 3, 0.5, seed=64)[0]
+    for scheme in ("aa", "ts", "os_push", "os_pull", "et"):
+        grid = make_grid(solid, scheme, addressing="indirect", precision=precision, f16_scale=1024.0)
+        assert grid.lattice_block == 1024, scheme
+        assert grid.sizes(scheme).pitch % 1024 == 0
+        grid.set_option(P._lib.OPT_SOA_BLOCK, 0)
+        grid.bind(scheme)
+        assert grid.lattice_block == 0, scheme
+        del grid
+    grid = make_grid(solid, "aa", addressing="indirect", layout="aos", precision=precision, f16_scale=1024.0)
+    assert grid.lattice_block == 0

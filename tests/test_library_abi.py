@@ -135,6 +135,28 @@ def test_option_ranges_without_gpu():
     assert g.sizes("aa").pitch == p0
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32", "f32s", "f16s"])
+@pytest.mark.parametrize("scheme", ["aa", "ts", "os_push", "os_pull", "et"])
+def test_default_storage_order_of_direct_grids_without_gpu(scheme, precision):
+    """On a direct SoA grid the lattice is stored in 1024-cell blocks by default for the two-step,
+    one-step and esoteric-twist schemes with 8- and 4-byte storage, and in plain SoA for the AA pattern
+    and for FP16-shifted storage: a blocked lattice's pitch covers whole blocks, a plain one's is the
+    cell count rounded to 128.  AoS lattices have no blocks."""
+    import paper_1111_0922_amd as P
+    nx, ny, nz = 100, 30, 20
+    n = nx * ny * nz
+    g = P.Grid(nx, ny, nz, wall_z=True, precision=precision, f16_scale=1.0)
+    blocked = scheme != "aa" and precision != "f16s"
+    assert g.sizes(scheme).pitch == -(-n // (1024 if blocked else 128)) * (1024 if blocked else 128)
+    g.set_option(P._lib.OPT_SOA_BLOCK, 0)
+    assert g.sizes(scheme).pitch == -(-n // 128) * 128
+    g.set_option(P._lib.OPT_SOA_BLOCK, 4096)
+    assert g.sizes(scheme).pitch == -(-n // 4096) * 4096
+    aos = P.Grid(nx, ny, nz, wall_z=True, layout="aos", precision=precision, f16_scale=1.0)
+    aos.set_option(P._lib.OPT_SOA_BLOCK, 4096)
+    assert aos.sizes(scheme).pdf_bytes == -(-n * 19 * {"f64": 8, "f16s": 2}.get(precision, 4) // 256) * 256
+
+
 def test_every_declaration_cites_a_passage_or_says_it_has_none():
     """Each entry point's comment in lbm355.h names the paper passage that defines it (a section,
     table or figure) or says that it has none (an addition of this library)."""
