@@ -256,10 +256,11 @@ int lbm_set_boundary(lbm_grid *g, int32_t cls, int32_t kind, double rho, const d
  *     Ignored on AoS grids; on a direct grid it disables the two-nodes-per-
  *     lane kernels (LBM_OPT_PAIR).  Changes the lattice layout and sizes:
  *     the grid must be bound again afterwards.  The default is 1024 on
- *     indirect grids; on direct grids 1024 for the two-step, one-step and
- *     esoteric-twist schemes with FP64, FP32 or FP32-shifted storage, and 0
- *     for the AA pattern and for FP16-shifted storage (which keeps its
- *     two-nodes-per-lane kernels).
+ *     indirect grids.  On direct grids it is 1024 for the two-step, one-step
+ *     and esoteric-twist schemes with FP64, FP32 or FP32-shifted storage;
+ *     4096 for the AA pattern with FP64 storage when nx divides 4096 or 4096
+ *     divides nx (the blocks then hold whole rows); 0 otherwise (FP16-shifted
+ *     storage keeps its two-nodes-per-lane kernels).
  * Errors: LBM_E_ARG for an unknown option or a value out of range. */
 enum {
     LBM_OPT_XCD_REMAP = 1,

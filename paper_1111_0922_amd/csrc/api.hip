@@ -94,10 +94,16 @@ int64_t rank_words_count(const lbm_grid *g) { return (g->n_cells + 31) / 32; }
 //    and esoteric-twist schemes.  256^3 channel, FP64 (FP32): two-step 1.67 ->
 //    1.58 ms per step (0.84 -> 0.80), one-step push 0.88 -> 0.85 (0.425 ->
 //    0.406), pull 0.84 -> 0.805 (0.43 -> 0.41), esoteric twist 0.86 -> 0.82
-//    (0.43 -> 0.40).  The AA pattern stays plain SoA: its odd kernel reads the
-//    rows y +- 1 of a direction, which plain SoA keeps 2 KB apart in one array
-//    (FP64 even 0.83 -> 0.78 ms, odd 0.85-0.86 -> 0.85-0.89 over runs on
-//    different boxes; FP32 odd 0.42-0.43 -> 0.47).
+//    (0.43 -> 0.40);
+//  - direct grids, the AA pattern with FP64 storage, blocks of 4096 cells where
+//    they hold whole rows (nx divides 4096 or 4096 divides nx).  Per pair of
+//    steps (even + odd, plain -> 1024 -> 4096): 128^3 0.246 -> 0.203 -> 0.202
+//    ms, 256^3 1.66-1.68 -> 1.63 -> 1.61, 256x256x512 3.39-3.41 -> 3.32 -> 3.30,
+//    512x256x256 3.63-3.64 -> 3.57-3.59 -> 3.55.  Blocks of 1024 speed up the
+//    even kernel but slow the odd one (256^3: 0.85 -> 0.85-0.86 ms); at 4096
+//    the odd kernel gains too (0.834).  Where rows straddle blocks the odd
+//    kernel loses (384^3: 6.12-6.13 plain, 6.21 at 4096), and FP32 and FP16
+//    storage keep plain SoA (FP32 odd 0.43 -> 0.49 ms at 4096).
 // Pairs of nodes per lane (16-bit storage, direct grids) need plain SoA, and
 // keep it by default.
 int soa_block_shift(const lbm_grid *g, int scheme)
@@ -106,7 +112,12 @@ int soa_block_shift(const lbm_grid *g, int scheme)
     const bool ind = g->d.addressing == LBM_INDIRECT;
     const int p = g->d.precision;
     int64_t def = 0;
-    if (ind || (scheme != LBM_AA && p != LBM_F16S)) def = 1024;
+    if (ind || (scheme != LBM_AA && p != LBM_F16S)) {
+        def = 1024;
+    } else if (scheme == LBM_AA && p == LBM_F64) {
+        const int64_t nx = g->d.nx;
+        if (4096 % nx == 0 || nx % 4096 == 0) def = 4096;
+    }
     const int64_t b = g->soa_block >= 0 ? g->soa_block : def;
     int sh = 0;
     while (((int64_t)1 << sh) < b) ++sh;

@@ -49,12 +49,27 @@ def _fluid_ids(solid):
 @pytest.mark.parametrize("scheme", ["ts", "os_push", "os_pull", "aa", "et"])
 def test_256_channel_sampled(scheme, layout):
     """Every scheme x layout of the benchmark's table, at its size and in its launch configuration
-    (row staging, residency, the AoS band order)."""
+    (row staging, residency, the AoS band order; the library's default storage order, which for the
+    AA pattern in FP64 is 4096-cell blocks)."""
+    _channel_sampled(scheme, layout)
+
+
+def test_256_channel_sampled_aa_plain_soa():
+    """The headline's configuration: the AA pattern on the 256^3 channel in plain SoA."""
+    _channel_sampled("aa", "soa", block=0)
+
+
+def _channel_sampled(scheme, layout, block=None):
+    import paper_1111_0922_amd as P
     n = 256
     solid = lbm_inputs.channel_mask(n, n, n)
     omega, g = 1.6, (1e-6, 0.0, 0.0)
     rng = np.random.default_rng(1)
     grid = make_grid(solid, scheme, layout=layout, omega=omega, g=g)
+    if block is not None:
+        grid.set_option(P._lib.OPT_SOA_BLOCK, block)
+        grid.bind(scheme)
+        assert grid.lattice_block == block
     nf = grid.n_nodes
     u = torch.from_numpy(lbm_inputs.velocity_noise((n - 2, n, n), 1e-3, seed=1).reshape(3, -1))
     rho_u = torch.cat([torch.ones(1, nf, dtype=torch.float64), u], 0)
@@ -85,6 +100,10 @@ def test_256_channel_sampled_precision_and_trt(case):
     sigma = 1024.0 if prec == "f16s" else 1.0
     rng = np.random.default_rng(2)
     grid = make_grid(solid, "aa", precision=prec, omega=omega, g=g, f16_scale=sigma)
+    if case == "trt":            # the benchmark runs TRT on the headline's plain SoA
+        import paper_1111_0922_amd as P
+        grid.set_option(P._lib.OPT_SOA_BLOCK, 0)
+        grid.bind("aa")
     nf = grid.n_nodes
     u = torch.from_numpy(lbm_inputs.velocity_noise((n - 2, n, n), 1e-3, seed=1).reshape(3, -1))
     grid.init_equilibrium(torch.cat([torch.ones(1, nf, dtype=torch.float64), u], 0).cuda())

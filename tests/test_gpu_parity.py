@@ -51,6 +51,24 @@ def test_fp64_config1_matches_oracle(scheme, addressing, layout, oracle_config1,
     gpu_results[(scheme, addressing, layout)] = got
 
 
+@pytest.mark.parametrize("block", [0, 4096])
+def test_fp64_config1_direct_aa_plain_and_blocked(block, oracle_config1, gpu_results):
+    """The direct AA pattern in plain SoA (the paper's layout, which the benchmark's headline runs) and
+    in 4096-cell blocks (the default for FP64 lattices whose rows fit whole blocks) against the oracle."""
+    import paper_1111_0922_amd as P
+    solid, f0, f100, omega, g = oracle_config1
+    grid = make_grid(solid, "aa", omega=omega, g=g)
+    assert grid.lattice_block == 4096
+    grid.set_option(P._lib.OPT_SOA_BLOCK, block)
+    grid.bind("aa")
+    assert grid.lattice_block == block
+    grid.set_pdfs(to_device(oracle.fluid_view(f0, solid)))
+    grid.step(STEPS)
+    got = from_device(grid.get_pdfs())
+    assert rel_err(got, oracle.fluid_view(f100, solid)) <= 1e-12
+    gpu_results[("aa", "direct", f"soa_block{block}")] = got
+
+
 def test_all_variants_bit_identical(gpu_results):
     """Propagation only moves bits and all kernels share one collision: identical states."""
     keys = sorted(gpu_results)

@@ -135,19 +135,24 @@ def test_option_ranges_without_gpu():
     assert g.sizes("aa").pitch == p0
 
 
+@pytest.mark.parametrize("nx", [100, 128, 8192])
 @pytest.mark.parametrize("precision", ["f64", "f32", "f32s", "f16s"])
 @pytest.mark.parametrize("scheme", ["aa", "ts", "os_push", "os_pull", "et"])
-def test_default_storage_order_of_direct_grids_without_gpu(scheme, precision):
+def test_default_storage_order_of_direct_grids_without_gpu(scheme, precision, nx):
     """On a direct SoA grid the lattice is stored in 1024-cell blocks by default for the two-step,
-    one-step and esoteric-twist schemes with 8- and 4-byte storage, and in plain SoA for the AA pattern
-    and for FP16-shifted storage: a blocked lattice's pitch covers whole blocks, a plain one's is the
-    cell count rounded to 128.  AoS lattices have no blocks."""
+    one-step and esoteric-twist schemes with 8- and 4-byte storage; the AA pattern with FP64 storage
+    in 4096-cell blocks when they hold whole rows (nx divides 4096 or 4096 divides nx); everything
+    else in plain SoA.  A blocked lattice's pitch covers whole blocks, a plain one's is the cell count
+    rounded to 128.  AoS lattices have no blocks."""
     import paper_1111_0922_amd as P
-    nx, ny, nz = 100, 30, 20
+    ny, nz = 30, 20
     n = nx * ny * nz
     g = P.Grid(nx, ny, nz, wall_z=True, precision=precision, f16_scale=1.0)
-    blocked = scheme != "aa" and precision != "f16s"
-    assert g.sizes(scheme).pitch == -(-n // (1024 if blocked else 128)) * (1024 if blocked else 128)
+    if scheme != "aa":
+        b = 1024 if precision != "f16s" else 128
+    else:
+        b = 4096 if precision == "f64" and (4096 % nx == 0 or nx % 4096 == 0) else 128
+    assert g.sizes(scheme).pitch == -(-n // b) * b
     g.set_option(P._lib.OPT_SOA_BLOCK, 0)
     assert g.sizes(scheme).pitch == -(-n // 128) * 128
     g.set_option(P._lib.OPT_SOA_BLOCK, 4096)
