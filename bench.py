@@ -11,8 +11,9 @@ Besides the headline the JSON line carries:
   roofline      achieved HBM bandwidth of the dominant kernel from its
                 algorithmic bytes per launch and its event-timed average
                 launch duration, against the 8 TB/s HBM3E peak;
-  schemes       every scheme x layout on the same lattice, AA also in FP32, FP32-shifted
-                and FP16-shifted storage, with the TRT collision, and on an indirect 256^3
+  schemes       every scheme x layout on the same lattice, AA also in the library's default
+                blocked order, in FP32, FP32-shifted and FP16-shifted storage, with the
+                TRT collision, and on an indirect 256^3
                 duct with a velocity inlet and a pressure outlet: whole-run MFLUP/s, and
                 each kernel's event-timed duration, GB/s and fraction of the HBM peak
                 (with its counted bytes while profiles/ is current for these kernels);
@@ -172,7 +173,7 @@ def measure_row(P, torch, grid, scheme, addressing, precision, workload, steps=1
                        model="gpu_rank" if (et_rank if scheme == "et" else rank) else "gpu")
     blk = grid.lattice_block
     row = {"MFLUP/s": round(mf, 1), "bytes_per_lup": bl, "neighbour_ids": "rank" if rank else "idx",
-           "storage": (f"{layout} in blocks of {blk}" if blk else layout), "GB/s": round(mf * bl / 1e3, 1),
+           "storage": (f"soa in blocks of {blk}" if blk else layout), "GB/s": round(mf * bl / 1e3, 1),
            "frac_hbm_wall": round(mf * bl / 1e3 / HBM_PEAK_GBS, 4), "kernels": {}}
     ms = per_launch_ms(torch, grid, launches, collider)
     fr = []
@@ -209,22 +210,25 @@ def pack_grid(P, torch, mask_t, scheme, n=512, precision="f64", omega=1.6):
 
 
 CHANNEL_SET = [(sc, lay, "f64") for lay in ("soa", "aos") for sc in ("ts", "os_push", "os_pull", "aa", "et")] + \
-              [("aa", "soa", p) for p in ("f32", "f32s", "f16s")]
+              [("aa", "soa_blocked", "f64")] + [("aa", "soa", p) for p in ("f32", "f32s", "f16s")]
 PACK_SET = [(sc, "soa", "f64") for sc in ("ts", "os_push", "os_pull", "aa", "et")]
 
 
-def plain_block(scheme, layout, prec):
-    """LBM_OPT_SOA_BLOCK of a channel table row: the FP64 AA pattern in plain SoA, as the headline runs
-    it (the library's default for this lattice is 4096-cell blocks, measured in its own row); every
-    other row in the library's default order."""
-    return 0 if (scheme, layout, prec) == ("aa", "soa", "f64") else None
+def table_grid(P, torch, n, scheme, layout, prec):
+    """The n^3 channel of one table row.  Row "soa" of the FP64 AA pattern runs plain SoA, as the
+    headline does; row "soa_blocked" runs it in the library's default order for this lattice (4096-cell
+    blocks); every other row runs the library's default order."""
+    if layout == "soa_blocked":
+        return channel_grid(P, torch, n, scheme, "soa", prec)
+    plain = (scheme, layout, prec) == ("aa", "soa", "f64")
+    return channel_grid(P, torch, n, scheme, layout, prec, block=0 if plain else None)
 
 
 def profile_set(P, torch, which, steps, warmup, log):
     """Every kernel of one workload for a profiler: `warmup` + `steps` steps per configuration."""
     if which == "channel":
         for scheme, layout, prec in CHANNEL_SET:
-            g = channel_grid(P, torch, 256, scheme, layout, prec, block=plain_block(scheme, layout, prec))
+            g = table_grid(P, torch, 256, scheme, layout, prec)
             dt = time_steps(torch, g, steps, warmup)
             print(json.dumps({"profile": f"channel256/{scheme}/{layout}/{prec}", "steps": steps,
                               "MFLUP/s": round(g.n_nodes * steps / dt / 1e6, 1)}), flush=True)
@@ -632,20 +636,13 @@ def main():
         table = {}
         cc = counter_table("channel256")
         for scheme, layout, prec in CHANNEL_SET:
-            g = channel_grid(P, torch, n, scheme, layout, prec, block=plain_block(scheme, layout, prec))
+            g = table_grid(P, torch, n, scheme, layout, prec)
             key = f"{scheme}/{layout}" + ("" if prec == "f64" else f"/{prec}")
             table[key] = measure_row(P, torch, g, scheme, "direct", prec, "channel256", counters=cc, layout=layout,
                                      steps=100 if prec == "f64" else 200)
             del g
             torch.cuda.empty_cache()
             log(f"[bench]   {key}: {table[key]['MFLUP/s']:.0f} MFLUP/s, slowest kernel {table[key]['frac_hbm']:.3f} of HBM")
-        # the AA pattern (plain SoA above, as the headline) in the library's default storage order for
-        # this lattice: 4096-cell blocks
-        g = channel_grid(P, torch, n, "aa", "soa")
-        table["aa/soa_blocked"] = measure_row(P, torch, g, "aa", "direct", "f64", "channel256", steps=100)
-        del g
-        torch.cuda.empty_cache()
-        log(f"[bench]   aa/soa_blocked: {table['aa/soa_blocked']['MFLUP/s']:.0f} MFLUP/s")
         # the paper's collision (TRT, Lambda = 3/16) on the headline's kernels
         g = channel_grid(P, torch, n, "aa", "soa", block=0)
         table["aa/soa/trt"] = measure_row(P, torch, g, "aa", "direct", "f64", "channel256", collider="trt", steps=200)
