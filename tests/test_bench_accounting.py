@@ -83,3 +83,18 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120, cwd=ROOT)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr) or "1 GPU" in (r.stdout + r.stderr)
+
+
+def test_channel_table_rows_pick_their_storage_order(monkeypatch):
+    """The FP64 AA row that carries the headline's counters runs plain SoA (block 0) whatever the
+    library's default is; the blocked row and every other row run the library's default (no option)."""
+    calls = []
+    monkeypatch.setattr(bench, "channel_grid", lambda P, torch, n, scheme, layout, prec="f64", block=None:
+                        calls.append((scheme, layout, prec, block)))
+    for scheme, layout, prec in bench.CHANNEL_SET:
+        bench.table_grid(None, None, 256, scheme, layout, prec)
+    assert len(calls) == len(bench.CHANNEL_SET)
+    assert ("aa", "soa", "f64", 0) in calls
+    assert ("aa", "soa", "f64", None) in calls          # the row "aa/soa_blocked"
+    assert sum(1 for c in calls if c[3] == 0) == 1
+    assert ("aa", "soa_blocked", "f64") in bench.CHANNEL_SET
