@@ -590,7 +590,7 @@ def main():
 
     n = 256
     log(f"[bench] AA SoA FP64 256^3 channel: warmup {args.warmup}, steps {args.steps}")
-    grid = channel_grid(P, torch, n, "aa", "soa", block=0)   # plain SoA, the layout the paper measures
+    grid = table_grid(P, torch, n, "aa", "soa", "f64")   # plain SoA, the layout the paper measures
     nf = grid.n_nodes
     m0 = grid.moments().cpu().numpy()
     dt = time_steps(torch, grid, args.steps, args.warmup)

@@ -98,3 +98,6 @@ def test_channel_table_rows_pick_their_storage_order(monkeypatch):
     assert ("aa", "soa", "f64", None) in calls          # the row "aa/soa_blocked"
     assert sum(1 for c in calls if c[3] == 0) == 1
     assert ("aa", "soa_blocked", "f64") in bench.CHANNEL_SET
+    # the headline is measured on the grid of that same row
+    import inspect
+    assert 'table_grid(P, torch, n, "aa", "soa", "f64")' in inspect.getsource(bench.main)
